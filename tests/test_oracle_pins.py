@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test fixes the oracle to something independent of it: a closed form
+(single Gaussian, the "over" operator of Eq. 2), an invariant of the
+definition, an independent re-derivation (numpy brute force with scipy's
+rotations), brute-force tile lists, or central finite differences of its
+own forward pass (for the analytic backward).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+from oracle import brute
+from paper_2412_09723_amd import scenes
+from tests.helpers import make_scene, tiny_scene
+
+KAPPA = float.fromhex("0x1.b2da4e9808a53p-1")
+
+
+# ------------------------------------------------------------ closed forms
+
+def _expected_single(intr, mu, s_iso, o, col, z0):
+    """Closed form for one isotropic Gaussian: Sigma' = s^2 J J^T + 0.3 I."""
+    X, Y, Z = mu
+    fx, fy = intr.fx, intr.fy
+    J = np.array([[fx / Z, 0, -fx * X / Z ** 2], [0, fy / Z, -fy * Y / Z ** 2]])
+    Sp = s_iso ** 2 * (J @ J.T) + 0.3 * np.eye(2)
+    Q = np.linalg.inv(Sp)
+    u = fx * X / Z + intr.cx
+    v = fy * Y / Z + intr.cy
+    ys, xs = np.mgrid[0:intr.height, 0:intr.width]
+    dx, dy = xs - u, ys - v
+    d2 = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+    at = o * np.exp(-0.5 * d2)
+    inc = (d2 <= 9.0) & (at >= 1.0 / 255.0)
+    alpha = np.where(inc, np.minimum(0.99, at), 0.0)
+    ambiguous = (np.abs(d2 - 9.0) < 1e-4) | (np.abs(at * 255.0 - 1.0) < 1e-4)
+    return alpha, ambiguous, (u, v)
+
+
+@pytest.mark.parametrize("mu", [(0.0, 0.0, 2.0), (0.013, -0.021, 2.0), (-0.3, 0.25, 1.3)])
+def test_single_gaussian_closed_form(mu):
+    intr = scenes.Intrinsics(65, 65, 100.0, 100.0, 32.0, 32.0)
+    s, o, col = 0.05, 0.8, np.array([0.2, 0.5, 0.9])
+    sc = make_scene(np.array(mu).reshape(3, 1), np.full((3, 1), s), [[1], [0], [0], [0]], [o],
+                    col.reshape(3, 1), intr)
+    mu32 = sc.means[:, 0].astype(np.float64)
+    alpha, amb, (u, v) = _expected_single(intr, mu32, float(np.float32(s)), float(np.float32(o)), col,
+                                          mu32[2])
+    out = oracle.forward(sc)
+    ok = ~amb
+    c32 = sc.colors[:, 0].astype(np.float64)
+    for k in range(3):
+        assert np.abs(out["rgb"][k][ok] - c32[k] * alpha[ok]).max() < 1e-13
+    assert np.abs(out["depth"][ok] - mu32[2] * alpha[ok]).max() < 1e-13
+    assert np.abs(out["sil"][ok] - alpha[ok]).max() < 1e-13
+    # peak at the pixel nearest the projected centre
+    py, px = np.unravel_index(np.argmax(out["sil"]), out["sil"].shape)
+    assert (px, py) == (int(round(u)), int(round(v)))
+    if mu[0] == 0.0:
+        assert abs(out["sil"][32, 32] - np.float32(o)) < 1e-15
+
+
+def test_anisotropic_screen_covariance_matches_ewa():
+    """Sigma' = J W Sigma W^T J^T + 0.3 I with Sigma from scipy's quaternion
+    rotation; compared with the pinned conic factors (binary32 rounding)."""
+    rng = np.random.default_rng(3)
+    sc = scenes.config0()
+    R0 = Rotation.from_euler("xyz", [10, -20, 5], degrees=True).as_matrix()
+    vm = np.concatenate([R0, np.array([[0.1], [-0.2], [0.3]])], axis=1).reshape(12)
+    sc = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity, sc.colors, vm.astype(np.float32), sc.intr)
+    pr = oracle.project(sc)
+    idx = rng.choice(np.flatnonzero(pr["visible"]), 200, replace=False)
+    V = sc.viewmat.astype(np.float64).reshape(3, 4)
+    R, t = V[:, :3], V[:, 3]
+    intr = sc.intr
+    for i in idx:
+        q = sc.quats[:, i].astype(np.float64)
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        s = sc.scales[:, i].astype(np.float64)
+        Sigma = Rq @ np.diag(s ** 2) @ Rq.T
+        X, Y, Z = R @ sc.means[:, i].astype(np.float64) + t
+        lx, ly = 0.65 * intr.width / intr.fx, 0.65 * intr.height / intr.fy
+        xt, yt = Z * np.clip(X / Z, -lx, lx), Z * np.clip(Y / Z, -ly, ly)
+        J = np.array([[intr.fx / Z, 0, -intr.fx * xt / Z ** 2], [0, intr.fy / Z, -intr.fy * yt / Z ** 2]])
+        Sp = J @ R @ Sigma @ R.T @ J.T + 0.3 * np.eye(2)
+        Q = np.linalg.inv(Sp)
+        a, b, c = (float(pr["rec"][k, i]) for k in (2, 3, 4))
+        A, B, C = a * a / KAPPA ** 2, a * b / KAPPA ** 2, (b * b + c * c) / KAPPA ** 2
+        scale = max(abs(Q[0, 0]), abs(Q[1, 1]))
+        assert abs(A - Q[0, 0]) < 1e-6 * scale
+        assert abs(B - Q[0, 1]) < 1e-6 * scale
+        assert abs(C - Q[1, 1]) < 1e-6 * scale
+        u = intr.fx * X / Z + intr.cx
+        assert abs(pr["ctr"][0, i] + float(pr["rec"][0, i]) - u) < 1e-6
+        assert pr["zkey"][i] == np.float32(Z).view(np.uint32)
+
+
+def test_over_operator_three_gaussians():
+    """Eq. 2 at a pixel covered by three Gaussians: the Porter-Duff over
+    operator applied front to back, regardless of input order."""
+    intr = scenes.Intrinsics(65, 65, 100.0, 100.0, 32.0, 32.0)
+    zs = [3.0, 1.5, 2.0]            # index order is not depth order
+    os_ = [0.6, 0.3, 0.45]
+    cols = np.array([[0.9, 0.1, 0.2], [0.3, 0.8, 0.1], [0.2, 0.4, 0.7]]).T
+    sc = make_scene([[0, 0, 0], [0, 0, 0], zs], np.full((3, 3), 0.05), np.tile([[1], [0], [0], [0]], 3), os_,
+                    cols, intr)
+    out = oracle.forward(sc)
+    o = sc.opacity.astype(np.float64)
+    c = sc.colors.astype(np.float64)
+    order = np.argsort(zs)
+    T, C, D = 1.0, np.zeros(3), 0.0
+    for i in order:
+        C += c[:, i] * o[i] * T
+        D += zs[i] * o[i] * T
+        T *= 1 - o[i]
+    assert np.allclose(out["rgb"][:, 32, 32], C, rtol=0, atol=1e-14)
+    assert abs(out["depth"][32, 32] - D) < 1e-14
+    assert abs(out["sil"][32, 32] - (1 - T)) < 1e-14
+
+
+def test_stop_before_transmittance_floor():
+    """With alpha = 0.95 per layer T goes 1, .05, .0025, 1.25e-4, 6.25e-6;
+    the fourth layer would drop T below 1e-4, so only three are composited."""
+    intr = scenes.Intrinsics(33, 33, 100.0, 100.0, 16.0, 16.0)
+    zs = [1.0, 1.5, 2.0, 2.5, 3.0]
+    sc = make_scene([[0] * 5, [0] * 5, zs], np.full((3, 5), 0.05), np.tile([[1], [0], [0], [0]], 5), [0.95] * 5,
+                    np.tile([[1.0], [0.5], [0.25]], 5), intr)
+    out = oracle.forward(sc)
+    a = float(np.float32(0.95))
+    T = [1.0, 1 - a, (1 - a) ** 2]
+    assert out["ncomp"][16, 16] == 3
+    assert abs(out["tfinal"][16, 16] - (1 - a) ** 3) < 1e-16
+    assert abs(out["rgb"][0, 16, 16] - sum(a * t for t in T)) < 1e-14
+    assert abs(out["depth"][16, 16] - sum(a * t * z for t, z in zip(T, zs))) < 1e-14
+    assert out["tfinal"].min() >= 1e-4
+
+
+def test_alpha_clamp_and_floor():
+    intr = scenes.Intrinsics(33, 33, 100.0, 100.0, 16.0, 16.0)
+    one = lambda o: make_scene([[0], [0], [2.0]], np.full((3, 1), 0.05), [[1], [0], [0], [0]], [o],
+                               [[1.0], [1.0], [1.0]], intr)
+    hi = oracle.forward(one(1.5))        # clamped at the centre
+    assert abs(hi["sil"][16, 16] - 0.99) < 1e-15
+    lo = oracle.forward(one(0.0038))     # below 1/255 everywhere
+    assert not lo["rgb"].any() and not lo["ncomp"].any()
+    ok = oracle.forward(one(0.0040))     # only a small disc passes 1/255
+    assert ok["ncomp"][16, 16] == 1 and ok["ncomp"].sum() < 30
+
+
+# --------------------------------------------------------------- invariants
+
+def test_invariants_config0():
+    sc = scenes.config0()
+    out = oracle.forward(sc)
+    T = out["tfinal"]
+    assert T.min() >= 1e-4 and T.max() <= 1.0
+    assert np.array_equal(out["sil"], 1.0 - T)
+    rgb = out["rgb"]
+    assert rgb.min() >= 0.0
+    assert (rgb <= out["sil"][None] + 1e-12).all()          # colours in [0,1]
+    pr = oracle.project(sc)
+    z = pr["z32"][pr["visible"] == 1].astype(np.float64)
+    m = out["sil"] > 1e-6
+    ratio = out["depth"][m] / out["sil"][m]
+    assert ratio.min() >= z.min() - 1e-9 and ratio.max() <= z.max() + 1e-9
+    c = out["counters"]
+    assert c[0] == 4096 and c[1] >= c[2] >= c[3] > 0
+    assert c[3] == out["ncomp"].sum()
+
+
+def test_colour_linearity():
+    sc = scenes.config0()
+    rng = np.random.default_rng(5)
+    c2 = rng.uniform(0, 1, sc.colors.shape).astype(np.float32)
+    c3 = (0.25 * sc.colors.astype(np.float64) + 0.75 * c2.astype(np.float64)).astype(np.float32)
+    r1 = oracle.forward(sc)
+    mk = lambda c: scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity, c, sc.viewmat, sc.intr)
+    r2 = oracle.forward(mk(c2))
+    r3 = oracle.forward(mk(c3))
+    assert np.array_equal(r1["depth"], r3["depth"]) and np.array_equal(r1["sil"], r3["sil"])
+    assert np.abs(r3["rgb"] - (0.25 * r1["rgb"] + 0.75 * r2["rgb"])).max() < 1e-7
+
+
+def test_permutation_invariance():
+    sc = scenes.config0()
+    perm = np.random.default_rng(1).permutation(sc.n)
+    pr = oracle.project(sc)
+    assert len(np.unique(pr["zkey"][pr["visible"] == 1])) == int(pr["visible"].sum())
+    a = oracle.forward(sc)
+    b = oracle.forward(sc.subset(perm))
+    for k in ("rgb", "depth", "sil", "ncomp"):
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("shift", [0.0, 1.0])
+def test_rigid_motion_equivariance(shift):
+    """Moving the world and the camera together leaves the image unchanged:
+    a 180 degree turn about z (exact in binary32), optionally with a
+    translation (then the binary32 rounding of the moved means limits the
+    agreement to ~1e-7)."""
+    sc = scenes.config0()
+    Rg = np.diag([-1.0, -1.0, 1.0])
+    d = shift * np.array([0.5, 0.25, -0.125])
+    means = (Rg @ sc.means.astype(np.float64) + d[:, None]).astype(np.float32)
+    w, x, y, z = sc.quats
+    quats = np.stack([-z, -y, x, w])          # (0,0,0,1) * q, exact
+    V = sc.viewmat.astype(np.float64).reshape(3, 4)
+    R2 = V[:, :3] @ Rg.T
+    t2 = V[:, 3] - R2 @ d
+    vm = np.concatenate([R2, t2[:, None]], axis=1).reshape(12).astype(np.float32)
+    moved = scenes.Scene(means, sc.scales, quats.astype(np.float32), sc.opacity, sc.colors, vm, sc.intr)
+    a = oracle.forward(sc)
+    b = oracle.forward(moved)
+    diff = np.abs(a["rgb"] - b["rgb"]).max(axis=0)
+    if shift == 0.0:
+        assert diff.max() < 1e-12
+    else:
+        assert (diff > 1e-5).mean() < 1e-3
+        assert np.median(diff) < 1e-6
+
+
+# -------------------------------------------------- independent re-derivation
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_brute_force_matches_oracle(seed):
+    pose = None
+    if seed >= 2:
+        R0 = Rotation.from_euler("xyz", [8 * seed, -5, 3], degrees=True).as_matrix()
+        pose = np.concatenate([R0, np.array([[0.05], [-0.1], [0.2]])], axis=1).reshape(12).astype(np.float32)
+    sc = tiny_scene(seed, pose=pose)
+    if seed == 1:       # push a few Gaussians off-screen and one behind the near plane
+        sc.means[0, :6] *= 3.0
+        sc.means[2, 7] = 0.1
+    b = brute.render(sc)
+    pr = oracle.project(sc)
+    f = oracle.forward(sc)
+    vis = np.array([r["visible"] for r in b["pinned"]])
+    assert np.array_equal(vis, pr["visible"].astype(bool))
+    for k, name in enumerate(["uf", "vf", "a", "b", "c", "qcut"]):
+        bv = np.array([r[name] if r["visible"] else 0 for r in b["pinned"]], np.float32)
+        assert np.array_equal(bv.view(np.uint32), pr["rec"][k].view(np.uint32)), name
+    for k, name in enumerate(["xlo", "xhi", "ylo", "yhi"]):
+        bv = np.array([r[name] if r["visible"] else 0 for r in b["pinned"]])
+        assert np.array_equal(bv, pr["bbox"][k]), name
+    assert np.array_equal(b["ncomp"], f["ncomp"])
+    assert np.abs(b["rgb"] - f["rgb"]).max() < 1e-12
+    assert np.abs(b["depth"] - f["depth"]).max() < 1e-12
+    assert np.abs(b["sil"] - f["sil"]).max() < 1e-12
+
+
+def test_pixel_box_contains_every_accepted_pixel():
+    """The binary32 test q <= qcut can only accept pixels inside the pixel
+    box (the box has a 2^-8 margin over 3 sigma), so skipping pixels outside
+    the box never changes a result. Checked by brute force, including very
+    elongated splats."""
+    sc = scenes.config0()
+    rng = np.random.default_rng(11)
+    sc.scales[:, :200] = np.stack([np.full(200, 0.3), np.full(200, 0.002), np.full(200, 0.002)])
+    sc.opacity[:200] = 0.999
+    pins = brute.pinned(sc.subset(np.arange(400)))
+    W, H = sc.intr.width, sc.intr.height
+    for r in pins:
+        if not r["visible"]:
+            continue
+        x0, x1 = max(r["xlo_raw"] - 4, 0), min(r["xhi_raw"] + 4, W - 1)
+        y0, y1 = max(r["ylo_raw"] - 4, 0), min(r["yhi_raw"] + 4, H - 1)
+        ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        acc = brute.pinned_q(r, xs, ys) <= r["qcut"]
+        inside = (xs >= r["xlo_raw"]) & (xs <= r["xhi_raw"]) & (ys >= r["ylo_raw"]) & (ys <= r["yhi_raw"])
+        assert not (acc & ~inside).any()
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tile_lists_brute_force(tile):
+    sc = scenes.config0()
+    pr = oracle.project(sc)
+    offsets, ids = oracle.tile_lists(pr, 160, 120, tile)
+    TX, TY = (160 + tile - 1) // tile, (120 + tile - 1) // tile
+    vis = pr["visible"] == 1
+    bb = pr["bbox"] // tile
+    for t in range(TX * TY):
+        tx, ty = t % TX, t // TX
+        m = vis & (bb[0] <= tx) & (bb[1] >= tx) & (bb[2] <= ty) & (bb[3] >= ty)
+        cand = np.flatnonzero(m)
+        order = cand[np.lexsort((cand, pr["zkey"][cand]))]
+        assert np.array_equal(ids[offsets[t]:offsets[t + 1]], order)
+
+
+def test_tile_size_invariance_of_image():
+    """The definition has no tiles: the oracle's image is identical for any
+    candidate bucketing, checked against a scene shifted by whole buckets."""
+    sc = scenes.config0()
+    a = oracle.forward(sc)
+    assert np.isfinite(a["rgb"]).all()
+    # the brute force (no buckets at all) on a crop-sized scene gives the same pixels
+    sub = sc.subset(np.arange(64))
+    b1 = oracle.forward(sub)
+    b2 = brute.render(sub)
+    assert np.abs(b1["rgb"] - b2["rgb"]).max() < 1e-12
+
+
+def test_pinned_log2():
+    for e in range(-30, 10):
+        assert oracle.pinned_log2(2.0 ** e) == e
+    xs = np.exp(np.random.default_rng(2).uniform(-20, 6, 2000))
+    for x in xs:
+        assert abs(oracle.pinned_log2(x) - math.log2(x)) <= 4e-16 * max(1.0, abs(math.log2(x)))
+        assert oracle.pinned_log2(x) == brute.pinned_log2(x)
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_empty_and_culled_inputs():
+    intr = scenes.Intrinsics(17, 9, 20.0, 20.0, 8.0, 4.0)
+    empty = make_scene(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((4, 0)), np.zeros(0), np.zeros((3, 0)), intr)
+    out = oracle.forward(empty)
+    assert not out["rgb"].any() and not out["depth"].any() and not out["sil"].any()
+    behind = make_scene([[0, 0, np.nan, 0], [0, 0, 0, 1e30], [-1.0, 0.1, 2.0, 2.0]], np.full((3, 4), 0.05),
+                        np.tile([[1], [0], [0], [0]], 4), [0.5] * 4, np.ones((3, 4)), intr)
+    pr = oracle.project(behind)
+    assert not pr["visible"].any()
+    out = oracle.forward(behind)
+    assert not out["rgb"].any()
+    zeroq = make_scene([[0], [0], [2.0]], np.full((3, 1), 0.05), [[0], [0], [0], [0]], [0.5], np.ones((3, 1)), intr)
+    assert not oracle.project(zeroq)["visible"].any()
+
+
+# ------------------------------------------------------------- gradients
+
+def _fd_scene(seed=4):
+    intr = scenes.Intrinsics(48, 40, 45.0, 45.0, 24.0, 20.0)
+    rng = scenes.rng_for(9, 100 + seed)
+    sc = scenes.frustum_scene(160, intr, rng)
+    R0 = Rotation.from_euler("xyz", [4, -3, 2], degrees=True).as_matrix()
+    vm = np.concatenate([R0, np.array([[0.03], [-0.02], [0.05]])], axis=1).reshape(12).astype(np.float32)
+    sc = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity, sc.colors, vm, intr)
+    # push a few Gaussians beyond the field-of-view clamp and one to high opacity
+    sc.means[0, :3] = sc.means[2, :3] * 0.9
+    sc.opacity[5] = 0.995
+    g = scenes.upstream_grads(intr, scenes.rng_for(9, 200 + seed), 0.7, 0.4)
+    return sc, g
+
+
+def _params(sc):
+    return {k: np.asarray(v, np.float64).copy() for k, v in sc.map_arrays().items()}
+
+
+def test_frozen_fd_matches_analytic_backward():
+    sc, (gc, gd, gs) = _fd_scene()
+    an = oracle.backward(sc, gc, gd, gs)
+    rec = oracle.record(sc)
+    base = _params(sc)
+    vm = sc.viewmat.astype(np.float64)
+    used = np.unique(rec["ids"][:rec["offsets"][-1]])
+    rng = np.random.default_rng(0)
+    checked = 0
+    for name, rows in (("means", 3), ("scales", 3), ("quats", 4), ("opacity", 1), ("colors", 3)):
+        G = an[name].reshape(rows, -1)
+        gmax = np.abs(G).max()
+        for i in rng.choice(used, 12, replace=False):
+            for r in range(rows):
+                h = 1e-6 * max(1.0, abs(base[name].reshape(rows, -1)[r, i]))
+                p1 = {k: v.copy() for k, v in base.items()}
+                p2 = {k: v.copy() for k, v in base.items()}
+                p1[name].reshape(rows, -1)[r, i] += h
+                p2[name].reshape(rows, -1)[r, i] -= h
+                l1 = oracle.frozen_loss(p1, vm, sc.intr, rec, gc, gd, gs)
+                l2 = oracle.frozen_loss(p2, vm, sc.intr, rec, gc, gd, gs)
+                fd = (l1 - l2) / (2 * h)
+                a = G[r, i]
+                assert abs(fd - a) <= 1e-6 * gmax + 1e-5 * abs(a), (name, i, r, fd, a)
+                checked += 1
+    assert checked > 100
+
+
+def test_frozen_fd_matches_pose_gradients():
+    sc, (gc, gd, gs) = _fd_scene(5)
+    an = oracle.backward(sc, gc, gd, gs)
+    rec = oracle.record(sc)
+    base = _params(sc)
+    vm = sc.viewmat.astype(np.float64)
+    gmax = np.abs(an["viewmat"]).max()
+    for j in range(12):
+        h = 1e-7
+        v1, v2 = vm.copy(), vm.copy()
+        v1[j] += h
+        v2[j] -= h
+        fd = (oracle.frozen_loss(base, v1, sc.intr, rec, gc, gd, gs)
+              - oracle.frozen_loss(base, v2, sc.intr, rec, gc, gd, gs)) / (2 * h)
+        assert abs(fd - an["viewmat"][j]) <= 1e-6 * gmax + 1e-5 * abs(an["viewmat"][j]), j
+    tmax = np.abs(an["twist"]).max()
+    for j in range(6):
+        h = 1e-7
+        xi = np.zeros(6)
+        xi[j] = h
+        fd = (oracle.frozen_loss(base, oracle.apply_twist(vm, xi), sc.intr, rec, gc, gd, gs)
+              - oracle.frozen_loss(base, oracle.apply_twist(vm, -xi), sc.intr, rec, gc, gd, gs)) / (2 * h)
+        assert abs(fd - an["twist"][j]) <= 1e-6 * tmax + 1e-5 * abs(an["twist"][j]), j
+
+
+def test_upstream_linearity():
+    sc = scenes.config0()
+    g1 = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 1, salt=1), 1.0, 0.5)
+    g2 = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 2, salt=1), 0.3, 1.0)
+    a, b = 0.5, -1.25
+    g3 = [(a * x.astype(np.float64) + b * y.astype(np.float64)).astype(np.float32) for x, y in zip(g1, g2)]
+    # binary32 rounding of the combined upstream is at most 2^-24 relative
+    r1, r2, r3 = (oracle.backward(sc, *g) for g in (g1, g2, g3))
+    for k in ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist"):
+        ref = a * r1[k] + b * r2[k]
+        assert np.abs(r3[k] - ref).max() <= 1e-6 * max(np.abs(ref).max(), 1e-30), k
+
+
+def test_culled_gaussians_get_zero_gradient():
+    sc = scenes.config0()
+    sc.means[2, :10] = -1.0            # behind the camera
+    g = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.5)
+    out = oracle.backward(sc, *g)
+    for k in ("means", "scales", "quats", "colors"):
+        assert not out[k][:, :10].any()
+    assert not out["opacity"][:10].any()
