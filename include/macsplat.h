@@ -1,0 +1,232 @@
+/*
+ * macsplat.h -- C ABI of the MI355X differentiable RGB-D Gaussian rasterizer.
+ *
+ * What it computes (MAC-Ego3D, arXiv 2412.09723):
+ *   * Sec. 3.3, Eq. 2: a map of 3D Gaussians (mean, covariance, opacity,
+ *     colour) rendered into an image by front-to-back alpha compositing,
+ *     I(p) = sum_i c_i f_i(p) prod_{j<i} (1 - f_j(p)).
+ *   * Sec. 3.5, Eq. 7: depth maps rendered the same way from the Gaussians;
+ *     the silhouette (accumulated opacity) 1 - prod_j (1 - f_j(p)).
+ *   * Sec. 3.4 "Optimization" and Sec. 3.5 "Optimization": gradients of a
+ *     loss on those images with respect to the map and the camera pose.
+ *   * Sec. 3.1: the pose is an element of SE(3); here the world-to-camera
+ *     transform [R|t].
+ *   * App. C.1: Gaussians carry per-axis scales; the covariance is
+ *     Sigma = Rq diag(s)^2 Rq^T with Rq the rotation of a quaternion.
+ *
+ * The paper does not define the projection f_i. This library uses EWA
+ * local-affine splatting: Sigma' = J R Sigma R^T J^T + 0.3 I (pixels^2), J the
+ * perspective Jacobian with the normalised image coordinate clamped to 1.3x
+ * the half field of view; f_i(p) = min(0.99, o_i exp(-d^2/2)), d^2 the
+ * Mahalanobis distance of p under Sigma'; a Gaussian counts at p only if
+ * d^2 <= 9 and o_i exp(-d^2/2) >= 1/255; compositing stops before the
+ * Gaussian that would take the transmittance below 1e-4; depth is
+ * sum z alpha T with z the camera-frame depth of the mean; background 0;
+ * pixel (x, y) is sampled at integer coordinates (x, y).
+ *
+ * Discrete structure (pinned recipe). Visibility, pixel boxes, depth keys,
+ * per-tile lists and per-pixel acceptance are integer outcomes of
+ * floating-point tests. They are defined by this evaluation order, which any
+ * conforming implementation reproduces bit for bit:
+ *   Projection, IEEE binary64, round to nearest, no fused multiply-add,
+ *   sums left to right as written; float inputs widened exactly.
+ *     p_i = ((R_i0 m_0 + R_i1 m_1) + R_i2 m_2) + t_i
+ *     culled unless p_2 > near, p finite, o and s finite;
+ *     n2 = ((w w + x x) + y y) + z z, culled unless 0 < n2 < inf;
+ *     r = 1/sqrt(n2); (w,x,y,z) *= r; Rq from the products xx, yy, zz, xy,
+ *       xz, yz, wx, wy, wz as Rq00 = 1 - 2(yy+zz), Rq01 = 2(xy-wz),
+ *       Rq02 = 2(xz+wy), Rq10 = 2(xy+wz), Rq11 = 1 - 2(xx+zz),
+ *       Rq12 = 2(yz-wx), Rq20 = 2(xz-wy), Rq21 = 2(yz+wx), Rq22 = 1 - 2(xx+yy);
+ *     M_ij = Rq_ij s_j;  W_ij = (R_i0 M_0j + R_i1 M_1j) + R_i2 M_2j;
+ *     rz = 1/p_2; xn = p_0 rz; yn = p_1 rz; limx = (0.65 W)/fx;
+ *       limy = (0.65 H)/fy; xc = min(max(xn, -limx), limx), yc likewise;
+ *     j00 = fx rz; j02 = -((fx xc) rz); j11 = fy rz; j12 = -((fy yc) rz);
+ *     V0k = j00 W_0k + j02 W_2k;  V1k = j11 W_1k + j12 W_2k;
+ *     S00 = ((V00 V00 + V01 V01) + V02 V02) + 0.3;
+ *     S01 = (V00 V10 + V01 V11) + V02 V12;
+ *     S11 = ((V10 V10 + V11 V11) + V12 V12) + 0.3;
+ *     culled unless S00 <= 2^22, S11 <= 2^22, S01 finite;
+ *     u = fx xn + cx; v = fy yn + cy; culled unless |u|, |v| <= 2^22;
+ *     rx = ceil(3.01171875 sqrt(S00)); ry = ceil(3.01171875 sqrt(S11));
+ *     box: xlo = ceil(u - rx), xhi = floor(u + rx), ylo, yhi likewise;
+ *       culled unless xlo <= W-1, xhi >= 0, ylo <= H-1, yhi >= 0;
+ *       then clamped to the image;
+ *     det = S00 S11 - S01 S01, culled unless det > 0;
+ *     z32 = (float)p_2, culled unless finite; depth key = bits(z32);
+ *     sd = sqrt(det); s1 = sqrt(S11); l11 = s1/sd; l12 = -S01/(sd s1);
+ *       l22 = 1/s1; a = (float)(K l11), b = (float)(K l12),
+ *       c = (float)(K l22) with K = sqrt(log2(e)/2) = 0x1.b2da4e9808a53p-1;
+ *     ui = floor(u), uf = (float)(u - ui), vi, vf likewise;
+ *     qcut = (float)min(Q9, L2(255 o)) (-inf when 255 o <= 0), where
+ *       Q9 = 4.5 log2(e) = 0x1.9f7f051d0f35ep+2 and L2 is the pinned log2:
+ *       m, e = frexp(x); m = 2m, e = e-1; if m > 1.4142135623730951 then
+ *       m = m/2, e = e+1; y = (m-1)/(m+1); P = 1/23; for k = 10..0:
+ *       P = P y^2 + 1/(2k+1); L2 = e + (2 y P) log2(e).
+ *   Per-pixel acceptance, IEEE binary32, fma fused:
+ *     dx = (float)(x - ui) - uf; dy = (float)(y - vi) - vf;
+ *     t1 = fma(a, dx, b dy); t2 = c dy; q = fma(t1, t1, t2 t2);
+ *     accepted iff q <= qcut.  (q approximates d^2 log2(e)/2; the 2^-8 box
+ *     margin guarantees that no pixel outside the box is ever accepted.)
+ *   Order: a pixel visits accepted Gaussians by ascending (depth key, index).
+ *   Tile lists for tile size B: Gaussian i is in tile (tx, ty) iff
+ *     xlo/B <= tx <= xhi/B and ylo/B <= ty <= yhi/B (integer division),
+ *     each list ordered by (depth key, index).
+ * Continuous values (alpha, transmittance, colours, depth, gradients) are
+ * binary32 on the device.
+ *
+ * Conventions. Camera x right, y down, z forward. viewmat is the row-major
+ * 3x4 world-to-camera matrix [R|t]. Arrays are structure-of-arrays float32:
+ * means [3][n], scales [3][n] (standard deviations in metres), quats [4][n]
+ * (w, x, y, z; any non-zero norm, normalised inside), opacity [n] (already in
+ * (0,1)), colors [3][n] (RGB). Images are planar: rgb [3][H][W], depth and
+ * silhouette [H][W].
+ *
+ * Memory and streams. Every array pointer is a DEVICE pointer unless stated
+ * otherwise, allocated and owned by the caller. The library allocates no
+ * device memory: scratch state lives in a caller-provided workspace of
+ * ms_workspace_bytes() bytes (256-byte aligned). All work is enqueued on the
+ * given HIP stream (hipStream_t passed as void*; NULL = default stream);
+ * calls are stream-ordered and return before the device finishes, except
+ * those documented as synchronising.
+ *
+ * Errors. Functions return an ms_status and never throw. Host-side argument
+ * checks are synchronous. A (Gaussian, tile) pair count above the capacity is
+ * detected on the device: the job's images are then filled with NaN, nothing
+ * is truncated silently, and the condition is reported by ms_read_stats() and
+ * by the next ms_backward() on that workspace (MS_ERR_CAPACITY).
+ */
+#ifndef MACSPLAT_H
+#define MACSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MS_ABI_VERSION 1
+
+typedef enum {
+  MS_OK = 0,
+  MS_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad option */
+  MS_ERR_CAPACITY = 2,      /* more (Gaussian, tile) pairs than the workspace holds */
+  MS_ERR_WORKSPACE = 3,     /* workspace too small or misaligned */
+  MS_ERR_HIP = 4,           /* a HIP runtime call failed; see ms_last_error() */
+  MS_ERR_UNSUPPORTED = 5    /* option value outside the supported set */
+} ms_status;
+
+/* Pinhole intrinsics, pixels. width, height in [1, 16384]. */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+} ms_intrinsics;
+
+/* Flags of ms_options.flags. */
+#define MS_FLAG_POSE_GRAD_ONLY 1u   /* backward: only the pose gradient (map gradients untouched) */
+#define MS_FLAG_NO_POSE_GRAD 2u     /* backward: skip the pose gradient (viewmat/twist untouched) */
+
+/* Launch options. tile: screen tile edge in pixels, 8 | 16 | 32.
+ * wave_batch: Gaussians staged per wavefront per step, 32 | 64 | 128.
+ * near_z: near plane in metres, > 0 (0.2 is the documented default). */
+typedef struct {
+  int32_t tile;
+  int32_t wave_batch;
+  float near_z;
+  uint32_t flags;
+} ms_options;
+
+/* A Gaussian map (device pointers, float32 SoA, see Conventions). n >= 0. */
+typedef struct {
+  int64_t n;
+  const float *means, *scales, *quats, *opacity, *colors;
+} ms_map;
+
+/* Rendered images or their upstream gradients (device pointers). */
+typedef struct {
+  float *rgb;          /* [3][H][W] */
+  float *depth;        /* [H][W] */
+  float *silhouette;   /* [H][W] */
+} ms_images;
+
+/* Gradients (device pointers), same shapes as ms_map; written, not
+ * accumulated: entries of culled Gaussians are set to zero. viewmat: [12]
+ * dL/d[R|t] row-major. twist: [6] dL/dxi for the left perturbation
+ * exp(xi^) [R|t], xi = (rho, phi), rho the translation part. Pointers the
+ * flags exclude may be NULL. */
+typedef struct {
+  float *means, *scales, *quats, *opacity, *colors;
+  float *viewmat, *twist;
+} ms_grads;
+
+/* ABI version (MS_ABI_VERSION). */
+int32_t ms_abi_version(void);
+
+/* Static description of a status code. Never NULL. */
+const char* ms_status_string(int32_t status);
+
+/* Detail of the last non-OK status returned on the calling thread. */
+const char* ms_last_error(void);
+
+/* Workspace size in bytes for a job of n Gaussians at the given intrinsics
+ * and options holding up to pair_capacity (Gaussian, tile) pairs. Returns 0
+ * for invalid arguments. The same (n, intrinsics, tile, pair_capacity) must
+ * be passed to ms_forward and the matching ms_backward. */
+size_t ms_workspace_bytes(int64_t n, const ms_intrinsics* intr, const ms_options* opts, int64_t pair_capacity);
+
+/* Forward render (Eq. 2 and its depth/silhouette analogues).
+ * map: Gaussian map; viewmat: device float[12]; intr, opts: host structs;
+ * workspace: device buffer of ws_bytes >= ms_workspace_bytes(...), 256-byte
+ * aligned, reused by the matching ms_backward (its forward state lives
+ * there); out: device images written in full.
+ * Enqueued on `stream`; returns before completion. */
+int32_t ms_forward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                   void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* out, void* stream);
+
+/* Backward pass of the last ms_forward on this workspace (same map, viewmat,
+ * intrinsics, options and capacity). grad_out: upstream gradients dL/d(rgb,
+ * depth, silhouette) (device); grads: written (see ms_grads). Transmittance is
+ * recomputed per pixel from the forward's per-pixel final transmittance and
+ * last-composited index; no per-Gaussian per-pixel state is stored.
+ * Returns MS_ERR_CAPACITY when the forward overflowed (checked on the host
+ * only if a previous ms_read_stats() saw it; otherwise the device skips the
+ * work and the gradients are NaN). Enqueued on `stream`. */
+int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                    void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* grad_out,
+                    const ms_grads* grads, void* stream);
+
+/* Counters of the last forward on a workspace, copied to host memory
+ * out[6]: visible Gaussians, (Gaussian, tile) pairs, pair-capacity overflow
+ * flag (0/1), tiles, and two reserved entries (-1). Arguments as for
+ * ms_forward. SYNCHRONISES the stream. */
+int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
+                      const ms_options* opts, int64_t pair_capacity, int64_t out[6], void* stream);
+
+/* Device views of the forward state inside a workspace, for inspection and
+ * testing (pointers into `workspace`, valid while it is not reused). */
+typedef struct {
+  uint32_t* depth_key;      /* [n] binary32 depth bits, 0xFFFFFFFF when culled */
+  uint32_t* sorted_index;   /* [n] Gaussian index of depth rank r (first n_visible valid) */
+  int32_t* rank_of;         /* [n] depth rank of Gaussian i, -1 when culled */
+  uint32_t* pair_tile;      /* [pair_capacity] tile id of each sorted pair */
+  uint32_t* pair_rank;      /* [pair_capacity] depth rank of each sorted pair */
+  uint32_t* tile_range;     /* [tiles][2] start, end into the sorted pairs */
+  float* records;           /* [n][16] per-rank projected record, see ms_record_layout */
+  float* tfinal;            /* [H][W] final transmittance */
+  uint32_t* last;           /* [H][W] last composited position (+1) in the pixel's tile list */
+  uint64_t* counters;       /* [8] visible, pairs, overflow, ... */
+  float* grad2d;            /* [n][10] per-rank screen-space gradient accumulators */
+} ms_state_view;
+
+/* Record layout (16 x 32-bit words per visible Gaussian, in depth-rank order):
+ * 0 ui (int32), 1 vi (int32), 2 uf, 3 vf, 4 a, 5 b, 6 c, 7 qcut,
+ * 8 log2(opacity), 9 z32, 10-12 colour, 13 xlo | xhi << 16, 14 ylo | yhi << 16,
+ * 15 Gaussian index (uint32). */
+int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
+                          const ms_options* opts, int64_t pair_capacity, ms_state_view* view);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MACSPLAT_H */

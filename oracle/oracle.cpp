@@ -67,7 +67,7 @@ const double CENTRE_LIMIT = 4194304.0;   // 2^22 px
 const double SIGMA2_LIMIT = 4194304.0;   // 2^22 px^2
 
 // Margins of the ambiguity flags (relative).
-const double MARGIN_STOP = 1e-3;
+const double MARGIN_STOP = 1e-4;
 const double MARGIN_CLAMP = 1e-4;
 
 struct Cam {

@@ -1,0 +1,105 @@
+"""ctypes binding of libmacsplat.so (the C ABI declared in include/macsplat.h).
+
+Argument marshalling only: every step of the render runs in the HIP kernels of
+the library. Importing this module does not touch the GPU; load() fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmacsplat.so")
+
+MS_OK = 0
+MS_ERR_INVALID_ARG = 1
+MS_ERR_CAPACITY = 2
+MS_ERR_WORKSPACE = 3
+MS_ERR_HIP = 4
+MS_ERR_UNSUPPORTED = 5
+MS_FLAG_POSE_GRAD_ONLY = 1
+MS_FLAG_NO_POSE_GRAD = 2
+
+EXPORTED = [
+    "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes",
+    "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
+]
+
+
+class MsIntrinsics(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class MsOptions(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("wave_batch", ctypes.c_int32), ("near_z", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
+
+
+class MsMap(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("colors", ctypes.c_void_p)]
+
+
+class MsImages(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("silhouette", ctypes.c_void_p)]
+
+
+class MsGrads(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("colors", ctypes.c_void_p), ("viewmat", ctypes.c_void_p),
+                ("twist", ctypes.c_void_p)]
+
+
+class MsStateView(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in (
+        "depth_key", "sorted_index", "rank_of", "pair_tile", "pair_rank", "tile_range", "records",
+        "tfinal", "last", "counters", "grad2d")]
+
+
+_lib = None
+
+
+class MacsplatError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"macsplat status {status}: {detail}")
+        self.status = status
+
+
+def load():
+    """Load the in-tree library; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python -m paper_2412_09723_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.ms_abi_version.restype = ctypes.c_int32
+    lib.ms_status_string.argtypes = [ctypes.c_int32]
+    lib.ms_status_string.restype = ctypes.c_char_p
+    lib.ms_last_error.restype = ctypes.c_char_p
+    lib.ms_workspace_bytes.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64]
+    lib.ms_workspace_bytes.restype = ctypes.c_size_t
+    lib.ms_forward.argtypes = [P, P, P, P, P, ctypes.c_size_t, ctypes.c_int64, P, P]
+    lib.ms_forward.restype = ctypes.c_int32
+    lib.ms_backward.argtypes = [P, P, P, P, P, ctypes.c_size_t, ctypes.c_int64, P, P, P]
+    lib.ms_backward.restype = ctypes.c_int32
+    lib.ms_read_stats.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int64, P, P]
+    lib.ms_read_stats.restype = ctypes.c_int32
+    lib.ms_state_view_get.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int64, P]
+    lib.ms_state_view_get.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != MS_OK:
+        lib = load()
+        raise MacsplatError(status, (lib.ms_last_error() or b"").decode())
+
+
+def ref(s):
+    return ctypes.byref(s)

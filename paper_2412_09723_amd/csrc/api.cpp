@@ -1,0 +1,274 @@
+// Host side of the C ABI: argument validation, workspace planning and the
+// launch sequence of the forward and backward passes. Allocates nothing;
+// every launch goes to the caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(ms_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t fail(ms_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return (int32_t)s;
+}
+
+int32_t hip_fail(hipError_t e, const char* where) {
+  return fail(MS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool valid_options(const ms_options* o) {
+  return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) &&
+         (o->wave_batch == 32 || o->wave_batch == 64 || o->wave_batch == 128) && std::isfinite(o->near_z) &&
+         o->near_z > 0.f;
+}
+
+int32_t check_common(const ms_intrinsics* intr, const ms_options* opts, int64_t n, int64_t cap) {
+  if (!intr || !opts) return fail(MS_ERR_INVALID_ARG, "null intrinsics or options");
+  if (intr->width < 1 || intr->width > 16384 || intr->height < 1 || intr->height > 16384)
+    return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", intr->width, intr->height);
+  if (!(std::isfinite(intr->fx) && std::isfinite(intr->fy) && std::isfinite(intr->cx) && std::isfinite(intr->cy)) ||
+      !(intr->fx > 0.f) || !(intr->fy > 0.f))
+    return fail(MS_ERR_INVALID_ARG, "intrinsics must be finite with fx, fy > 0");
+  if (opts->tile != 8 && opts->tile != 16 && opts->tile != 32)
+    return fail(MS_ERR_UNSUPPORTED, "tile %d not in {8, 16, 32}", opts->tile);
+  if (opts->wave_batch != 32 && opts->wave_batch != 64 && opts->wave_batch != 128)
+    return fail(MS_ERR_UNSUPPORTED, "wave_batch %d not in {32, 64, 128}", opts->wave_batch);
+  if (!valid_options(opts)) return fail(MS_ERR_INVALID_ARG, "near_z must be finite and > 0");
+  if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(MS_ERR_INVALID_ARG, "n = %lld outside [0, 2^31)", (long long)n);
+  if (cap < 0 || cap > (int64_t)0xFFFFFFFF)
+    return fail(MS_ERR_INVALID_ARG, "pair capacity %lld outside [0, 2^32)", (long long)cap);
+  return MS_OK;
+}
+
+int32_t check_map(const ms_map* map) {
+  if (!map) return fail(MS_ERR_INVALID_ARG, "null map");
+  if (map->n > 0 && (!map->means || !map->scales || !map->quats || !map->opacity || !map->colors))
+    return fail(MS_ERR_INVALID_ARG, "null map array");
+  return MS_OK;
+}
+
+int32_t check_ws(const void* ws, size_t ws_bytes, const Plan& p) {
+  if (!ws) return fail(MS_ERR_WORKSPACE, "null workspace");
+  if (((uintptr_t)ws & 255u) != 0) return fail(MS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < p.total)
+    return fail(MS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.total);
+  return MS_OK;
+}
+
+Camera make_cam(const ms_intrinsics* intr, const ms_options* opts) {
+  Camera c;
+  c.W = intr->width;
+  c.H = intr->height;
+  c.fx = intr->fx;
+  c.fy = intr->fy;
+  c.cx = intr->cx;
+  c.cy = intr->cy;
+  c.near_z = opts->near_z;
+  return c;
+}
+
+}  // namespace
+
+bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p) {
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  p.cap = cap;
+  p.tile = tile;
+  p.tx = (W + tile - 1) / tile;
+  p.ty = (H + tile - 1) / tile;
+  p.tiles = p.tx * p.ty;
+  p.pixels = (int64_t)W * H;
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t cc = cap > 0 ? cap : 1;
+  p.scan_blocks_n = (int)((nn + 2047) / 2048);
+  auto clampi = [](int64_t v, int64_t lo, int64_t hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); };
+  p.sort_blocks_v = clampi((nn + 4095) / 4096, 1, 512);
+  p.sort_blocks_p = clampi((cc + 8191) / 8192, 1, 512);
+  p.pose_blocks = (int)((nn + 255) / 256);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  p.counters = take(sizeof(uint64_t) * C_COUNT);
+  p.key = take(4 * nn);
+  p.vis_pos = take(4 * nn);
+  p.ntiles = take(4 * nn);
+  p.rec_i = take(64 * nn);
+  p.rank_of = take(4 * nn);
+  p.ckey = take(4 * nn);
+  p.cval = take(4 * nn);
+  p.ckey2 = take(4 * nn);
+  p.cval2 = take(4 * nn);
+  p.rec = take(64 * nn);
+  p.cnt = take(4 * nn);
+  p.cnt_off = take(8 * nn);
+  p.scan_part = take(8 * (size_t)(p.scan_blocks_n + 1));
+  p.pkey = take(4 * cc);
+  p.pval = take(4 * cc);
+  p.pkey2 = take(4 * cc);
+  p.pval2 = take(4 * cc);
+  p.trange = take(8 * (size_t)p.tiles);
+  p.tfinal = take(4 * (size_t)p.pixels);
+  p.last = take(4 * (size_t)p.pixels);
+  p.g2d = take(4 * (size_t)kGradFields * nn);
+  const int sb = p.sort_blocks_v > p.sort_blocks_p ? p.sort_blocks_v : p.sort_blocks_p;
+  p.hist = take(4 * 256 * (size_t)sb);
+  p.pose_part = take(8 * 12 * (size_t)p.pose_blocks);
+  p.total = o;
+  return true;
+}
+
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+int32_t ms_abi_version(void) { return MS_ABI_VERSION; }
+
+const char* ms_status_string(int32_t s) {
+  switch (s) {
+    case MS_OK: return "ok";
+    case MS_ERR_INVALID_ARG: return "invalid argument";
+    case MS_ERR_CAPACITY: return "pair capacity exceeded";
+    case MS_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case MS_ERR_HIP: return "HIP runtime error";
+    case MS_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* ms_last_error(void) { return g_last_error.c_str(); }
+
+size_t ms_workspace_bytes(int64_t n, const ms_intrinsics* intr, const ms_options* opts, int64_t pair_capacity) {
+  if (check_common(intr, opts, n, pair_capacity) != MS_OK) return 0;
+  Plan p;
+  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  return p.total;
+}
+
+int32_t ms_forward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                   void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* out, void* stream) {
+  int32_t s = check_map(map);
+  if (s != MS_OK) return s;
+  s = check_common(intr, opts, map->n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
+  if (!out || !out->rgb || !out->depth || !out->silhouette) return fail(MS_ERR_INVALID_ARG, "null output image");
+  Plan p;
+  make_plan(map->n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Camera cam = make_cam(intr, opts);
+  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, 2 * C_COUNT, st);
+  if (e != hipSuccess) return hip_fail(e, "counters");
+  e = launch_project_fwd(*map, viewmat, cam, p, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "project");
+  e = launch_bin(p, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "bin");
+  e = launch_composite_fwd(cam, p, opts->wave_batch, ws, *out, st);
+  if (e != hipSuccess) return hip_fail(e, "composite");
+  return MS_OK;
+}
+
+int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                    void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* grad_out,
+                    const ms_grads* grads, void* stream) {
+  int32_t s = check_map(map);
+  if (s != MS_OK) return s;
+  s = check_common(intr, opts, map->n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
+  if (!grad_out || !grad_out->rgb || !grad_out->depth || !grad_out->silhouette)
+    return fail(MS_ERR_INVALID_ARG, "null upstream gradient image");
+  if (!grads) return fail(MS_ERR_INVALID_ARG, "null gradients");
+  const bool map_g = !(opts->flags & MS_FLAG_POSE_GRAD_ONLY);
+  const bool pose_g = !(opts->flags & MS_FLAG_NO_POSE_GRAD);
+  if (map_g && map->n > 0 &&
+      (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->colors))
+    return fail(MS_ERR_INVALID_ARG, "null map gradient array");
+  if (pose_g && (!grads->viewmat || !grads->twist)) return fail(MS_ERR_INVALID_ARG, "null pose gradient");
+  Plan p;
+  make_plan(map->n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Camera cam = make_cam(intr, opts);
+  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * map->n, st);
+  if (e != hipSuccess) return hip_fail(e, "zero");
+  e = launch_composite_bwd(cam, p, opts->wave_batch, ws, *grad_out, st);
+  if (e != hipSuccess) return hip_fail(e, "composite backward");
+  e = launch_project_bwd(*map, viewmat, cam, p, ws, *grads, opts->flags, st);
+  if (e != hipSuccess) return hip_fail(e, "project backward");
+  return MS_OK;
+}
+
+int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
+                      const ms_options* opts, int64_t pair_capacity, int64_t out[6], void* stream) {
+  int32_t s = check_common(intr, opts, n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!out) return fail(MS_ERR_INVALID_ARG, "null output");
+  Plan p;
+  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  uint64_t c[C_COUNT];
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(c, (const char*)workspace + p.counters, sizeof(c), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "read stats");
+  out[0] = (int64_t)c[C_VISIBLE];
+  out[1] = (int64_t)c[C_PAIRS];
+  out[2] = (int64_t)c[C_OVERFLOW];
+  out[3] = p.tiles;
+  out[4] = -1;
+  out[5] = -1;
+  return MS_OK;
+}
+
+int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
+                          const ms_options* opts, int64_t pair_capacity, ms_state_view* v) {
+  int32_t s = check_common(intr, opts, n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!v) return fail(MS_ERR_INVALID_ARG, "null view");
+  Plan p;
+  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  char* ws = (char*)workspace;
+  v->depth_key = at<uint32_t>(ws, p.key);
+  v->sorted_index = at<uint32_t>(ws, p.cval);
+  v->rank_of = at<int32_t>(ws, p.rank_of);
+  v->pair_tile = at<uint32_t>(ws, p.pkey);
+  v->pair_rank = at<uint32_t>(ws, p.pval);
+  v->tile_range = at<uint32_t>(ws, p.trange);
+  v->records = at<float>(ws, p.rec);
+  v->tfinal = at<float>(ws, p.tfinal);
+  v->last = at<uint32_t>(ws, p.last);
+  v->counters = at<uint64_t>(ws, p.counters);
+  v->grad2d = at<float>(ws, p.g2d);
+  return MS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal definitions shared by the HIP translation units of libmacsplat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "macsplat.h"
+
+namespace ms {
+
+// ---------------------------------------------------------------- constants
+// sqrt(log2(e)/2): Mahalanobis factors are scaled so that q = d^2 log2(e)/2
+// and the splat weight is o * 2^-q.
+constexpr double kKappa = 0x1.b2da4e9808a53p-1;
+// 4.5 log2(e): q at the 3-sigma footprint d^2 = 9.
+constexpr double kQ9 = 0x1.9f7f051d0f35ep+2;
+constexpr double kLog2e = 0x1.71547652b82fep+0;
+constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+constexpr double kBoxSigmas = 3.01171875;     // 3 (1 + 2^-8)
+constexpr double kDilation = 0.3;             // px^2 low-pass added to Sigma'
+constexpr double kGuard = 0.65;               // 1.3 x half field of view
+constexpr double kCentreLimit = 4194304.0;    // 2^22 px
+constexpr double kSigma2Limit = 4194304.0;    // 2^22 px^2
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+
+// Record of one visible Gaussian, 16 x 32-bit words (64 bytes), stored in
+// depth-rank order. Layout documented in macsplat.h (ms_record_layout).
+enum RecWord {
+  R_UI = 0, R_VI = 1, R_UF = 2, R_VF = 3, R_A = 4, R_B = 5, R_C = 6, R_QCUT = 7,
+  R_LO2 = 8, R_Z = 9, R_CR = 10, R_CG = 11, R_CB = 12, R_BX = 13, R_BY = 14, R_IDX = 15
+};
+
+constexpr int kGradFields = 10;   // per-rank screen-space adjoint accumulators
+// 0 E = sum dL/dalpha * alpha~ (unclamped), 1 P1 = sum t1 e, 2 P2 = sum t2 e,
+// 3 P1x = sum t1 e dx, 4 P1y = sum t1 e dy, 5 P2y = sum t2 e dy,
+// 6-8 sum G_rgb alpha T, 9 sum G_depth alpha T.
+
+// Device counters (uint64): visible, pairs, overflow, tiles, visited.
+enum Counter { C_VISIBLE = 0, C_PAIRS = 1, C_OVERFLOW = 2, C_TILES = 3, C_VISITED = 4, C_COUNT = 8 };
+
+struct Camera {
+  int W, H;
+  float fx, fy, cx, cy;
+  float near_z;
+};
+
+// ------------------------------------------------------------ workspace plan
+struct Plan {
+  int64_t n, cap;
+  int tile, tx, ty, tiles;
+  int64_t pixels;
+  int scan_blocks_n;     // blocks of the length-n scans
+  int sort_blocks_v;     // blocks of the depth sort
+  int sort_blocks_p;     // blocks of the pair sort
+  int pose_blocks;
+  // byte offsets
+  size_t counters, key, vis_pos, ntiles, rec_i, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part,
+      pkey, pval, pkey2, pval2, trange, tfinal, last, g2d, hist, pose_part;
+  size_t total;
+};
+
+bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p);
+
+// Number of LSD passes (<= 8 bits each) for keys of `bits` significant bits.
+inline int sort_passes(int bits) { return (bits + 7) / 8; }
+// Significant bits of a tile id.
+inline int tile_bits(int tiles) {
+  int b = 0;
+  while ((1 << b) < tiles) b++;
+  return b;
+}
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns the launch status.
+hipError_t launch_project_fwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p,
+                              char* ws, hipStream_t st);
+hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st);
+hipError_t launch_composite_fwd(const Camera& cam, const Plan& p, int wave_batch, char* ws, const ms_images& out,
+                                hipStream_t st);
+hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch, char* ws, const ms_images& gout,
+                                hipStream_t st);
+hipError_t launch_project_bwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p, char* ws,
+                              const ms_grads& g, uint32_t flags, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStream_t st);
+
+template <typename T>
+__host__ __device__ inline T* at(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+}  // namespace ms

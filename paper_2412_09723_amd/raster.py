@@ -1,0 +1,237 @@
+"""PyTorch-facing entry points of the rasterizer (thin layer over the C ABI).
+
+PyTorch supplies device memory (inputs, outputs, the workspace) and the
+current HIP stream; all arithmetic runs in libmacsplat's HIP kernels.
+
+Map tensors use the ABI's structure-of-arrays layout: means/scales [3, N],
+quats [4, N] (w, x, y, z), opacity [N], colors [3, N], float32, on the GPU.
+`to_soa` converts [N, 3]-style tensors once.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+from ._lib import MsGrads, MsImages, MsIntrinsics, MsMap, MsOptions, MsStateView, check, ref
+
+NEAR_Z = 0.2
+
+
+@dataclasses.dataclass(frozen=True)
+class RenderOptions:
+    tile: int = 16
+    wave_batch: int = 64
+    near_z: float = NEAR_Z
+    pair_capacity: int | None = None     # None: sized from the map (see default_capacity)
+    check: bool = False                  # read the device counters after the forward (synchronises)
+
+
+def default_capacity(n: int, width: int, height: int, tile: int) -> int:
+    """Pair capacity heuristic: 16 tiles per Gaussian plus 64 per tile."""
+    tiles = ((width + tile - 1) // tile) * ((height + tile - 1) // tile)
+    return int(min(16 * n + 64 * tiles + 4096, 0xFFFFFFFF))
+
+
+def to_soa(t: torch.Tensor) -> torch.Tensor:
+    """[N, k] -> contiguous [k, N]."""
+    return t.t().contiguous() if t.dim() == 2 else t.contiguous()
+
+
+def intr_struct(intr) -> MsIntrinsics:
+    return MsIntrinsics(int(intr.width), int(intr.height), float(intr.fx), float(intr.fy), float(intr.cx),
+                        float(intr.cy))
+
+
+def opts_struct(opts: RenderOptions, flags: int = 0) -> MsOptions:
+    return MsOptions(int(opts.tile), int(opts.wave_batch), float(opts.near_z), int(flags))
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_map(m: dict):
+    n = m["means"].shape[1]
+    shapes = {"means": (3, n), "scales": (3, n), "quats": (4, n), "opacity": (n,), "colors": (3, n)}
+    dev = m["means"].device
+    for k, shp in shapes.items():
+        t = m[k]
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{k} has shape {tuple(t.shape)}, expected {shp}")
+        if t.dtype != torch.float32 or t.device != dev:
+            raise ValueError(f"{k} must be float32 on {dev}")
+        if not t.is_contiguous():
+            raise ValueError(f"{k} must be contiguous")
+    if dev.type != "cuda":
+        raise ValueError("map tensors must live on the GPU")
+    return n
+
+
+class Job:
+    """One render job: its map, pose, intrinsics, options and workspace.
+
+    The workspace is a caller-owned uint8 tensor; the forward state stays in
+    it until the next forward on the same Job."""
+
+    def __init__(self, m: dict, viewmat: torch.Tensor, intr, opts: RenderOptions = RenderOptions(),
+                 workspace: torch.Tensor | None = None):
+        self.m = m
+        self.n = _check_map(m)
+        self.viewmat = viewmat
+        if viewmat.shape != (12,) or viewmat.dtype != torch.float32 or viewmat.device != m["means"].device:
+            raise ValueError("viewmat must be a float32 [12] tensor on the map's device")
+        self.intr = intr
+        self.opts = opts
+        self.cap = opts.pair_capacity if opts.pair_capacity is not None else default_capacity(
+            self.n, intr.width, intr.height, opts.tile)
+        self.c_intr = intr_struct(intr)
+        self.c_map = MsMap(self.n, m["means"].data_ptr(), m["scales"].data_ptr(), m["quats"].data_ptr(),
+                           m["opacity"].data_ptr(), m["colors"].data_ptr())
+        lib = _lib.load()
+        self.ws_bytes = lib.ms_workspace_bytes(self.n, ref(self.c_intr), ref(opts_struct(opts)), self.cap)
+        if self.ws_bytes == 0:
+            check(_lib.MS_ERR_INVALID_ARG)
+        if workspace is None or workspace.numel() < self.ws_bytes:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=m["means"].device)
+        self.ws = workspace
+
+    # -- forward -----------------------------------------------------------
+    def forward(self, out: tuple | None = None):
+        H, W = self.intr.height, self.intr.width
+        dev = self.m["means"].device
+        if out is None:
+            rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+            depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+            sil = torch.empty((H, W), dtype=torch.float32, device=dev)
+        else:
+            rgb, depth, sil = out
+        imgs = MsImages(rgb.data_ptr(), depth.data_ptr(), sil.data_ptr())
+        lib = _lib.load()
+        check(lib.ms_forward(ref(self.c_map), _ptr(self.viewmat), ref(self.c_intr), ref(opts_struct(self.opts)),
+                             _ptr(self.ws), self.ws_bytes, self.cap, ref(imgs), _stream_ptr(dev)))
+        if self.opts.check:
+            st = self.stats()
+            if st["overflow"]:
+                raise _lib.MacsplatError(_lib.MS_ERR_CAPACITY,
+                                         f"{st['pairs']} pairs exceed the capacity {self.cap}")
+        return rgb, depth, sil
+
+    # -- backward ----------------------------------------------------------
+    def backward(self, g_rgb, g_depth, g_sil, map_grads: bool = True, pose_grads: bool = True,
+                 out: dict | None = None) -> dict:
+        dev = self.m["means"].device
+        flags = 0
+        if not map_grads:
+            flags |= _lib.MS_FLAG_POSE_GRAD_ONLY
+        if not pose_grads:
+            flags |= _lib.MS_FLAG_NO_POSE_GRAD
+        g = out if out is not None else {}
+        if map_grads and out is None:
+            for k in ("means", "scales", "quats", "opacity", "colors"):
+                g[k] = torch.empty_like(self.m[k])
+        if pose_grads and out is None:
+            g["viewmat"] = torch.empty(12, dtype=torch.float32, device=dev)
+            g["twist"] = torch.empty(6, dtype=torch.float32, device=dev)
+        gi = MsImages(g_rgb.data_ptr(), g_depth.data_ptr(), g_sil.data_ptr())
+        gg = MsGrads(*[g[k].data_ptr() if k in g else 0
+                       for k in ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist")])
+        lib = _lib.load()
+        check(lib.ms_backward(ref(self.c_map), _ptr(self.viewmat), ref(self.c_intr),
+                              ref(opts_struct(self.opts, flags)), _ptr(self.ws), self.ws_bytes, self.cap, ref(gi),
+                              ref(gg), _stream_ptr(dev)))
+        return g
+
+    # -- inspection ---------------------------------------------------------
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * 6)()
+        lib = _lib.load()
+        check(lib.ms_read_stats(_ptr(self.ws), self.ws_bytes, self.n, ref(self.c_intr), ref(opts_struct(self.opts)),
+                                self.cap, out, _stream_ptr(self.m["means"].device)))
+        return dict(visible=out[0], pairs=out[1], overflow=bool(out[2]), tiles=out[3])
+
+    def state(self) -> dict:
+        """Device views of the forward state (see ms_state_view in the header)."""
+        v = MsStateView()
+        lib = _lib.load()
+        check(lib.ms_state_view_get(_ptr(self.ws), self.ws_bytes, self.n, ref(self.c_intr),
+                                    ref(opts_struct(self.opts)), self.cap, ref(v)))
+        base = self.ws.data_ptr()
+        n = max(self.n, 1)
+        H, W = self.intr.height, self.intr.width
+        t = self.opts.tile
+        tiles = ((W + t - 1) // t) * ((H + t - 1) // t)
+
+        def view(ptr, count, dtype):
+            off = ptr - base
+            nbytes = count * torch.empty((), dtype=dtype).element_size()
+            return self.ws[off:off + nbytes].view(dtype)
+
+        return dict(
+            depth_key=view(v.depth_key, n, torch.int32),
+            sorted_index=view(v.sorted_index, n, torch.int32),
+            rank_of=view(v.rank_of, n, torch.int32),
+            pair_tile=view(v.pair_tile, max(self.cap, 1), torch.int32),
+            pair_rank=view(v.pair_rank, max(self.cap, 1), torch.int32),
+            tile_range=view(v.tile_range, 2 * tiles, torch.int32).view(tiles, 2),
+            records=view(v.records, 16 * n, torch.float32).view(n, 16),
+            tfinal=view(v.tfinal, H * W, torch.float32).view(H, W),
+            last=view(v.last, H * W, torch.int32).view(H, W),
+            counters=view(v.counters, 8, torch.int64),
+            grad2d=view(v.grad2d, 10 * n, torch.float32).view(n, 10),
+        )
+
+
+class RasterizeRGBD(torch.autograd.Function):
+    """Differentiable RGB-D render: (map, viewmat) -> (rgb, depth, silhouette).
+
+    The backward recomputes per-pixel transmittance from the forward's final
+    transmittance and last index (no per-Gaussian per-pixel state). The
+    left-twist pose gradient of the last backward is kept on the Job as
+    `job.twist_grad`."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, colors, viewmat, intr, opts, holder):
+        m = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
+                 opacity=opacity.contiguous(), colors=colors.contiguous())
+        job = Job(m, viewmat.contiguous(), intr, opts, holder.get("workspace"))
+        holder["workspace"] = job.ws
+        holder["job"] = job
+        rgb, depth, sil = job.forward()
+        ctx.job = job
+        ctx.needs = ctx.needs_input_grad
+        return rgb, depth, sil
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g_rgb, g_depth, g_sil):
+        job = ctx.job
+        H, W = job.intr.height, job.intr.width
+        dev = job.m["means"].device
+        z = lambda shp: torch.zeros(shp, dtype=torch.float32, device=dev)
+        g_rgb = z((3, H, W)) if g_rgb is None else g_rgb.contiguous()
+        g_depth = z((H, W)) if g_depth is None else g_depth.contiguous()
+        g_sil = z((H, W)) if g_sil is None else g_sil.contiguous()
+        need_map = any(ctx.needs[:5])
+        need_pose = bool(ctx.needs[5])
+        g = job.backward(g_rgb, g_depth, g_sil, map_grads=need_map or not need_pose, pose_grads=need_pose)
+        job.twist_grad = g.get("twist")
+        gm = lambda k, i: g.get(k) if ctx.needs[i] else None
+        return (gm("means", 0), gm("scales", 1), gm("quats", 2), gm("opacity", 3), gm("colors", 4),
+                g.get("viewmat") if need_pose else None, None, None, None)
+
+
+def render(m: dict, viewmat: torch.Tensor, intr, opts: RenderOptions = RenderOptions(), holder: dict | None = None):
+    """Differentiable render of a map (dict of SoA tensors) from `viewmat`.
+
+    `holder` (optional dict) keeps the workspace across calls and receives the
+    Job under "job"."""
+    holder = {} if holder is None else holder
+    return RasterizeRGBD.apply(m["means"], m["scales"], m["quats"], m["opacity"], m["colors"], viewmat, intr, opts,
+                               holder)
