@@ -1,0 +1,217 @@
+"""Benchmark: RGB-D forward+backward throughput of the rasterizer on one MI355X.
+
+Workload: the single-agent tracking step on a synthetic indoor room (1M
+Gaussians, 1200x680, fx = fy = 600): 10 iterations of forward render, L1 RGB
++ 0.5 L1 depth loss gradient against a frame rendered from a pose 2 cm /
+1 degree away, full backward (all Gaussian parameters and the pose), and an
+Adam step on the pose's twist. One benchmark step = one tracking step; the
+metric is rendered-and-differentiated pixels per second (Mpix/s).
+
+Prints one JSON line (see the keys below). Also reports, for the dominant
+kernel, its live HIP-event duration against its roofline, and the CPU
+oracle's throughput on a bounded sample of the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic floating-point work per composited (pixel, Gaussian) pair,
+# counting an FMA as two flops and a transcendental as one.
+FLOPS_PER_PAIR = {"composite": 27, "composite_bwd": 52}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=10, help="forward+backward iterations per tracking step")
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--bin-tile", type=int, default=128, help="binning tile edge (0: same as --tile)")
+    ap.add_argument("--wave-batch", type=int, default=64)
+    ap.add_argument("--pose-only", action="store_true", help="pose gradients only (tracking variant)")
+    ap.add_argument("--fwd-records", choices=("lds", "scalar"), default="lds",
+                    help="forward compositing record path: LDS staging or scalar (SGPR) loads")
+    ap.add_argument("--bwd-records", choices=("lds", "scalar", "mfma"), default="mfma",
+                    help="backward compositing record path")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    return ap.parse_args()
+
+
+def kernel_source_hash(files=("composite.hip",)) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2412_09723_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_stage: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_stage}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, target_s: float):
+    """The oracle (unchanged) on the same frame: forward + backward passes
+    repeated until about `target_s` seconds of work."""
+    import numpy as np
+    import oracle
+    from paper_2412_09723_amd import scenes
+    cores = len(os.sched_getaffinity(0))
+    up = scenes.upstream_grads(scene.intr, scenes.rng_for(1, 0, salt=2), 0.5, 0.0)
+    oracle.load()
+    reps, t0 = 0, time.perf_counter()
+    fwd = None
+    while True:
+        fwd = oracle.forward(scene, nthreads=cores)
+        oracle.backward(scene, *up, nthreads=cores)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or el / reps * (reps + 1) > 2.5 * target_s:
+            break
+    px = scene.intr.pixels * reps
+    return {"value": px / el / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} forward+backward passes of the 1200x680 frame of the 1M-Gaussian room "
+                      f"({el:.1f} s, OpenMP over {cores} threads)",
+            "counters": {"visible": int(fwd["counters"][0]), "evaluated": int(fwd["counters"][1]),
+                         "accepted": int(fwd["counters"][2]), "composited": int(fwd["counters"][3])}}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the per-agent shard design is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_09723_amd import _lib, raster, scenes
+    from paper_2412_09723_amd.track import Tracker
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = scenes.config1(n=args.n)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    m = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), colors=t(sc.colors))
+    opts = raster.RenderOptions(tile=args.tile, wave_batch=args.wave_batch, fwd_records=args.fwd_records,
+                                bwd_records=args.bwd_records, bin_tile=args.bin_tile)
+    # observed frame: render from the pose perturbed by 2 cm / 1 degree
+    vm_obs = t(scenes.perturb_pose(sc.viewmat, scenes.rng_for(1, 0, salt=3)))
+    obs_job = raster.Job(m, vm_obs, sc.intr, raster.RenderOptions(tile=args.tile, wave_batch=args.wave_batch,
+                                                                  check=True))
+    target = obs_job.forward()
+    del obs_job
+    vm = t(sc.viewmat)
+    tracker = Tracker(m, vm, target, sc.intr, opts, lr=1e-3, w_depth=0.5, map_grads=not args.pose_only)
+    job = tracker.job
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        tracker.step(args.iters)
+    torch.cuda.synchronize()
+    st = job.stats()
+    if st["overflow"]:
+        raise RuntimeError(f"pair capacity overflow: {st}")
+
+    # per-stage breakdown (one profiled step, outside the timed region)
+    prof_all = _lib.Profiler()
+    with prof_all:
+        tracker.step(args.iters)
+    stages = prof_all.read()
+    prof_all.close()
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    dominant = max(("composite", "composite_bwd"), key=lambda k: stage_ms[k])
+
+    # timed region; the dominant kernel's launches carry HIP events on the
+    # stream they run on (the current torch stream)
+    prof = _lib.Profiler(stages=(dominant,))
+    torch.cuda.synchronize()
+    with prof:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            tracker.step(args.iters)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    dom = prof.read()[dominant]
+    prof.close()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    px = sc.intr.pixels * args.iters
+    value = px / (ms_per_step / 1e3) / 1e6
+
+    st = job.stats()
+    if st["overflow"]:
+        raise RuntimeError(f"pair capacity overflow: {st}")
+    kern_ms = dom[0] / max(dom[1], 1)
+    flops = FLOPS_PER_PAIR[dominant] * st["composited"]
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": f"k_{dominant}", "achieved": round(achieved, 3),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": read_traffic(dominant), "avg_launch_ms": round(kern_ms, 4), "launches": dom[1],
+                "units": {"composited_pairs": st["composited"], "flops_per_pair": FLOPS_PER_PAIR[dominant]},
+                "work": {"fwd_wave_entries": st["staged"], "bwd_wave_steps": st["reduced"]}}
+
+    # whole-path algorithmic HBM bytes per forward+backward
+    state = job.state()
+    last = state["last"].cpu().numpy().astype(np.int64)
+    T = args.bin_tile or args.tile
+    H, W = sc.intr.height, sc.intr.width
+    pad = np.zeros(((H + T - 1) // T * T, (W + T - 1) // T * T), np.int64)
+    pad[:H, :W] = last
+    k_r = int(pad.reshape(pad.shape[0] // T, T, pad.shape[1] // T, T).max(axis=(1, 3)).sum())
+    N, Nv, K, P = sc.n, st["visible"], st["pairs"], sc.intr.pixels
+    alg_bytes = 68 * N + 280 * Nv + 4 * K + 96 * k_r + 68 * P
+    fb_ms = ms_per_step / args.iters
+    path_hbm = {"bytes_per_fwd_bwd": alg_bytes, "achieved_GBs": round(alg_bytes / (fb_ms * 1e-3) / 1e9, 1),
+                "frac_of_8TBs": round(alg_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "N": N, "N_visible": Nv, "K_pairs": K, "K_r_staged": k_r, "pixels": P}
+
+    out = {
+        "metric": "Mpix/s RGB-D fwd+bwd @1M Gaussians 1200x680; served frames/s + p99 vs plain",
+        "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tracking step: 10 x (RGB-D forward + L1 loss grad + full backward + pose Adam), "
+                               f"1M-Gaussian 6x4x3 m room, 1200x680, tile {args.tile}, wave batch {args.wave_batch}, "
+                               f"bin tile {args.bin_tile or args.tile}, {args.fwd_records}/{args.bwd_records} records"
+                               + (", pose-only gradients" if args.pose_only else ""),
+                   "gaussians": sc.n, "width": W, "height": H, "iterations_per_step": args.iters},
+        "roofline": roofline,
+        "path_hbm": path_hbm,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "fwd_bwd_ms": round(fb_ms, 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,7 +68,7 @@
  *     accepted iff q <= qcut.  (q approximates d^2 log2(e)/2; the 2^-8 box
  *     margin guarantees that no pixel outside the box is ever accepted.)
  *   Order: a pixel visits accepted Gaussians by ascending (depth key, index).
- *   Tile lists for tile size B: Gaussian i is in tile (tx, ty) iff
+ *   Tile lists for bin tile size B: Gaussian i is in tile (tx, ty) iff
  *     xlo/B <= tx <= xhi/B and ylo/B <= ty <= yhi/B (integer division),
  *     each list ordered by (depth key, index).
  * Continuous values (alpha, transmittance, colours, depth, gradients) are
@@ -125,15 +125,25 @@ typedef struct {
 /* Flags of ms_options.flags. */
 #define MS_FLAG_POSE_GRAD_ONLY 1u   /* backward: only the pose gradient (map gradients untouched) */
 #define MS_FLAG_NO_POSE_GRAD 2u     /* backward: skip the pose gradient (viewmat/twist untouched) */
+#define MS_FLAG_SCALAR_FWD 4u       /* forward compositing reads each Gaussian's record with wave-uniform
+                                       scalar loads instead of staging wave_batch records through LDS */
+#define MS_FLAG_SCALAR_BWD 8u       /* the same for backward compositing */
+#define MS_FLAG_MFMA_BWD 16u        /* backward compositing with scalar records and the per-Gaussian pixel
+                                       reduction done as a matrix-core product (tile 8 or 16) */
 
-/* Launch options. tile: screen tile edge in pixels, 8 | 16 | 32.
- * wave_batch: Gaussians staged per wavefront per step, 32 | 64 | 128.
- * near_z: near plane in metres, > 0 (0.2 is the documented default). */
+/* Launch options. tile: edge in pixels of the screen tile one compositing
+ * workgroup owns, 8 | 16 | 32. bin_tile: edge of the tiles whose
+ * (Gaussian, tile) lists are built and sorted, 0 (same as tile) or a multiple
+ * of tile in {8, ..., 256}; each compositing workgroup walks the list of the
+ * bin tile containing it. wave_batch: Gaussians staged per wavefront per
+ * step, 32 | 64 | 128. near_z: near plane in metres, > 0 (0.2 is the
+ * documented default). */
 typedef struct {
   int32_t tile;
   int32_t wave_batch;
   float near_z;
   uint32_t flags;
+  int32_t bin_tile;
 } ms_options;
 
 /* A Gaussian map (device pointers, float32 SoA, see Conventions). n >= 0. */
@@ -195,12 +205,15 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
                     void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* grad_out,
                     const ms_grads* grads, void* stream);
 
-/* Counters of the last forward on a workspace, copied to host memory
- * out[6]: visible Gaussians, (Gaussian, tile) pairs, pair-capacity overflow
- * flag (0/1), tiles, and two reserved entries (-1). Arguments as for
- * ms_forward. SYNCHRONISES the stream. */
+/* Counters of the last forward (and backward) on a workspace, copied to
+ * host memory out[7]: visible Gaussians, (Gaussian, bin tile) pairs,
+ * pair-capacity overflow flag (0/1), bin tiles, composited (pixel, Gaussian)
+ * pairs, list entries staged by the forward wavefronts, (wavefront,
+ * Gaussian) steps of the last backward that had an accepting pixel.
+ * Arguments as for ms_forward. SYNCHRONISES the stream. Returns MS_ERR_HIP
+ * when a bounded device wait gave up. */
 int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
-                      const ms_options* opts, int64_t pair_capacity, int64_t out[6], void* stream);
+                      const ms_options* opts, int64_t pair_capacity, int64_t out[7], void* stream);
 
 /* Device views of the forward state inside a workspace, for inspection and
  * testing (pointers into `workspace`, valid while it is not reused). */
@@ -208,22 +221,64 @@ typedef struct {
   uint32_t* depth_key;      /* [n] binary32 depth bits, 0xFFFFFFFF when culled */
   uint32_t* sorted_index;   /* [n] Gaussian index of depth rank r (first n_visible valid) */
   int32_t* rank_of;         /* [n] depth rank of Gaussian i, -1 when culled */
-  uint32_t* pair_tile;      /* [pair_capacity] tile id of each sorted pair */
-  uint32_t* pair_rank;      /* [pair_capacity] depth rank of each sorted pair */
-  uint32_t* tile_range;     /* [tiles][2] start, end into the sorted pairs */
+  uint32_t* pair_tile;      /* [pair_capacity] tile id of each sorted pair (packed: the pair word) */
+  uint32_t* pair_rank;      /* [pair_capacity] depth rank of each sorted pair (packed: the pair word) */
+  uint32_t* tile_range;     /* [bin tiles][2] start, end into the sorted pairs */
   float* records;           /* [n][16] per-rank projected record, see ms_record_layout */
   float* tfinal;            /* [H][W] final transmittance */
   uint32_t* last;           /* [H][W] last composited position (+1) in the pixel's tile list */
   uint64_t* counters;       /* [8] visible, pairs, overflow, ... */
   float* grad2d;            /* [n][10] per-rank screen-space gradient accumulators */
+  int32_t pair_rank_bits;   /* 0: separate arrays; > 0: each pair is one word tile << bits | rank */
 } ms_state_view;
 
 /* Record layout (16 x 32-bit words per visible Gaussian, in depth-rank order):
- * 0 ui (int32), 1 vi (int32), 2 uf, 3 vf, 4 a, 5 b, 6 c, 7 qcut,
+ * 0 floor(u), 1 floor(v) (integer-valued floats), 2 uf, 3 vf, 4 a, 5 b, 6 c, 7 qcut,
  * 8 log2(opacity), 9 z32, 10-12 colour, 13 xlo | xhi << 16, 14 ylo | yhi << 16,
  * 15 Gaussian index (uint32). */
 int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
                           const ms_options* opts, int64_t pair_capacity, ms_state_view* view);
+
+/* ------------------------------------------------------------ tracking helpers
+ * Gradient of the L1 loss  w_rgb mean|rgb - rgb*| + w_depth mean|D - D*| +
+ * w_sil mean|S - S*|  (the L1 terms of Eq. 7 used as a per-agent tracking
+ * loss; means over 3HW entries for RGB and HW for depth and silhouette).
+ * pred, target, grad: device images of intr's size; grad is written (sign(0) =
+ * 0). loss: device float receiving the loss value, or NULL. Enqueued on
+ * `stream`. */
+int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms_intrinsics* intr, float w_rgb,
+                        float w_depth, float w_sil, const ms_images* grad, float* loss, void* stream);
+
+/* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
+ * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
+ * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]
+ * (rho, phi) as written by ms_backward; state: device float[13] (m[6], v[6],
+ * step count), zero-initialised by the caller before the first step.
+ * Enqueued on `stream`. */
+int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state, float lr, float beta1, float beta2,
+                          float eps, void* stream);
+
+/* ------------------------------------------------------------------ profiling
+ * Optional per-stage timing with HIP events on the caller's stream. A
+ * profiler attached to the calling thread makes ms_forward / ms_backward
+ * record an event pair around every stage selected by stage_mask (bit s for
+ * stage s). Events are created once by ms_profiler_create (no device memory);
+ * at most `capacity` pairs are kept until ms_profiler_read, which waits for
+ * them, returns the summed milliseconds and launch counts per stage, and
+ * resets the profiler. */
+enum {
+  MS_STAGE_PROJECT = 0,        /* projection forward */
+  MS_STAGE_BIN = 1,            /* compaction, depth sort, pair emission, tile sort, ranges */
+  MS_STAGE_COMPOSITE = 2,      /* compositing forward */
+  MS_STAGE_COMPOSITE_BWD = 3,  /* compositing backward (includes zeroing its accumulators) */
+  MS_STAGE_PROJECT_BWD = 4,    /* projection backward and pose reduction */
+  MS_STAGE_COUNT = 5
+};
+typedef struct ms_profiler ms_profiler;
+int32_t ms_profiler_create(uint32_t stage_mask, int32_t capacity, ms_profiler** out);
+int32_t ms_profiler_destroy(ms_profiler* prof);
+int32_t ms_profiler_attach(ms_profiler* prof);   /* NULL detaches */
+int32_t ms_profiler_read(ms_profiler* prof, double total_ms[MS_STAGE_COUNT], int64_t launches[MS_STAGE_COUNT]);
 
 #ifdef __cplusplus
 }

@@ -20,11 +20,18 @@ MS_ERR_HIP = 4
 MS_ERR_UNSUPPORTED = 5
 MS_FLAG_POSE_GRAD_ONLY = 1
 MS_FLAG_NO_POSE_GRAD = 2
+MS_FLAG_SCALAR_FWD = 4
+MS_FLAG_SCALAR_BWD = 8
+MS_FLAG_MFMA_BWD = 16
 
 EXPORTED = [
     "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes",
     "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
+    "ms_l1_loss_grad", "ms_pose_adam_step",
+    "ms_profiler_create", "ms_profiler_destroy", "ms_profiler_attach", "ms_profiler_read",
 ]
+
+STAGES = ["project", "bin", "composite", "composite_bwd", "project_bwd"]
 
 
 class MsIntrinsics(ctypes.Structure):
@@ -34,7 +41,7 @@ class MsIntrinsics(ctypes.Structure):
 
 class MsOptions(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("wave_batch", ctypes.c_int32), ("near_z", ctypes.c_float),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("bin_tile", ctypes.c_int32)]
 
 
 class MsMap(ctypes.Structure):
@@ -55,7 +62,7 @@ class MsGrads(ctypes.Structure):
 class MsStateView(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in (
         "depth_key", "sorted_index", "rank_of", "pair_tile", "pair_rank", "tile_range", "records",
-        "tfinal", "last", "counters", "grad2d")]
+        "tfinal", "last", "counters", "grad2d")] + [("pair_rank_bits", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,6 +98,19 @@ def load():
     lib.ms_read_stats.restype = ctypes.c_int32
     lib.ms_state_view_get.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int64, P]
     lib.ms_state_view_get.restype = ctypes.c_int32
+    F = ctypes.c_float
+    lib.ms_l1_loss_grad.argtypes = [P, P, P, F, F, F, P, P, P]
+    lib.ms_l1_loss_grad.restype = ctypes.c_int32
+    lib.ms_pose_adam_step.argtypes = [P, P, P, F, F, F, F, P]
+    lib.ms_pose_adam_step.restype = ctypes.c_int32
+    lib.ms_profiler_create.argtypes = [ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.ms_profiler_create.restype = ctypes.c_int32
+    lib.ms_profiler_destroy.argtypes = [P]
+    lib.ms_profiler_destroy.restype = ctypes.c_int32
+    lib.ms_profiler_attach.argtypes = [P]
+    lib.ms_profiler_attach.restype = ctypes.c_int32
+    lib.ms_profiler_read.argtypes = [P, P, P]
+    lib.ms_profiler_read.restype = ctypes.c_int32
     _lib = lib
     return lib
 
@@ -103,3 +123,39 @@ def check(status: int):
 
 def ref(s):
     return ctypes.byref(s)
+
+
+class Profiler:
+    """Per-stage HIP-event timing of the library's launches on the calling
+    thread (see ms_profiler_* in the header)."""
+
+    def __init__(self, stages=tuple(STAGES), capacity: int = 8192):
+        mask = 0
+        for st in stages:
+            mask |= 1 << STAGES.index(st)
+        self._h = ctypes.c_void_p()
+        check(load().ms_profiler_create(mask, capacity, ctypes.byref(self._h)))
+
+    def attach(self):
+        load().ms_profiler_attach(self._h)
+        return self
+
+    def detach(self):
+        load().ms_profiler_attach(None)
+
+    def read(self) -> dict:
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        check(load().ms_profiler_read(self._h, ms, cnt))
+        return {st: (ms[i], cnt[i]) for i, st in enumerate(STAGES)}
+
+    def close(self):
+        if self._h:
+            load().ms_profiler_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self.attach()
+
+    def __exit__(self, *exc):
+        self.detach()

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ms_internal.h"
 
@@ -50,9 +51,14 @@ int32_t check_common(const ms_intrinsics* intr, const ms_options* opts, int64_t 
   if (opts->wave_batch != 32 && opts->wave_batch != 64 && opts->wave_batch != 128)
     return fail(MS_ERR_UNSUPPORTED, "wave_batch %d not in {32, 64, 128}", opts->wave_batch);
   if (!valid_options(opts)) return fail(MS_ERR_INVALID_ARG, "near_z must be finite and > 0");
+  if (opts->bin_tile != 0) {
+    const int b = opts->bin_tile;
+    if (b < opts->tile || b > 256 || (b & (b - 1)) != 0)
+      return fail(MS_ERR_UNSUPPORTED, "bin_tile %d must be 0 or a power of two in [tile, 256]", b);
+  }
   if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(MS_ERR_INVALID_ARG, "n = %lld outside [0, 2^31)", (long long)n);
-  if (cap < 0 || cap > (int64_t)0xFFFFFFFF)
-    return fail(MS_ERR_INVALID_ARG, "pair capacity %lld outside [0, 2^32)", (long long)cap);
+  if (cap < 0 || cap > ((int64_t)1 << 31))
+    return fail(MS_ERR_INVALID_ARG, "pair capacity %lld outside [0, 2^31]", (long long)cap);
   return MS_OK;
 }
 
@@ -85,7 +91,43 @@ Camera make_cam(const ms_intrinsics* intr, const ms_options* opts) {
 
 }  // namespace
 
-bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p) {
+}  // namespace ms
+
+struct ms_profiler {
+  uint32_t mask = 0;
+  int cap = 0;
+  int used = 0;
+  std::vector<hipEvent_t> ev;   // 2 * cap
+  std::vector<int> stage;       // cap
+};
+
+namespace ms {
+namespace {
+
+thread_local ms_profiler* g_prof = nullptr;
+
+// Records the start (open) or end (close) event of a stage on `st` when the
+// attached profiler selects it.
+struct StageTimer {
+  int slot = -1;
+  hipStream_t st;
+  StageTimer(int stage, hipStream_t s) : st(s) {
+    ms_profiler* p = g_prof;
+    if (!p || !(p->mask & (1u << stage)) || p->used >= p->cap) return;
+    slot = p->used++;
+    p->stage[slot] = stage;
+    hipEventRecord(p->ev[2 * slot], st);
+  }
+  void close() {
+    if (slot >= 0 && g_prof) hipEventRecord(g_prof->ev[2 * slot + 1], st);
+    slot = -1;
+  }
+  ~StageTimer() { close(); }
+};
+
+}  // namespace
+
+bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p) {
   std::memset(&p, 0, sizeof(p));
   p.n = n;
   p.cap = cap;
@@ -93,14 +135,20 @@ bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p) {
   p.tx = (W + tile - 1) / tile;
   p.ty = (H + tile - 1) / tile;
   p.tiles = p.tx * p.ty;
+  p.bin = bin > 0 ? bin : tile;
+  p.bshift = 0;
+  while ((tile << p.bshift) < p.bin) p.bshift++;
+  p.bx = (W + p.bin - 1) / p.bin;
+  p.by = (H + p.bin - 1) / p.bin;
+  p.bins = p.bx * p.by;
   p.pixels = (int64_t)W * H;
   const int64_t nn = n > 0 ? n : 1;
   const int64_t cc = cap > 0 ? cap : 1;
   p.scan_blocks_n = (int)((nn + 2047) / 2048);
-  auto clampi = [](int64_t v, int64_t lo, int64_t hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); };
-  p.sort_blocks_v = clampi((nn + 4095) / 4096, 1, 512);
-  p.sort_blocks_p = clampi((cc + 8191) / 8192, 1, 512);
   p.pose_blocks = (int)((nn + 255) / 256);
+  p.rank_bits = 1;
+  while (p.rank_bits < 31 && ((int64_t)1 << p.rank_bits) < nn) p.rank_bits++;
+  p.packed = p.rank_bits + tile_bits(p.bins) <= 32;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -108,6 +156,14 @@ bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p) {
     return r;
   };
   p.counters = take(sizeof(uint64_t) * C_COUNT);
+  p.tickets = take(4 * 8);                       // 2 sorts x 4 passes
+  p.digit_hist = take(4 * 256 * 8);              // 2 sorts x 4 passes x 256 digits
+  {
+    const int64_t os_tile = 2048;
+    const int64_t tiles_v = (nn + os_tile - 1) / os_tile, tiles_p = (cc + os_tile - 1) / os_tile;
+    p.lookback = take(8 * 256 * (size_t)(tiles_v > tiles_p ? tiles_v : tiles_p));
+  }
+  p.ctrl_end = o;
   p.key = take(4 * nn);
   p.vis_pos = take(4 * nn);
   p.ntiles = take(4 * nn);
@@ -122,15 +178,13 @@ bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p) {
   p.cnt_off = take(8 * nn);
   p.scan_part = take(8 * (size_t)(p.scan_blocks_n + 1));
   p.pkey = take(4 * cc);
-  p.pval = take(4 * cc);
+  p.pval = p.packed ? p.pkey : take(4 * cc);
   p.pkey2 = take(4 * cc);
-  p.pval2 = take(4 * cc);
-  p.trange = take(8 * (size_t)p.tiles);
+  p.pval2 = p.packed ? p.pkey2 : take(4 * cc);
+  p.trange = take(8 * (size_t)p.bins);
   p.tfinal = take(4 * (size_t)p.pixels);
   p.last = take(4 * (size_t)p.pixels);
   p.g2d = take(4 * (size_t)kGradFields * nn);
-  const int sb = p.sort_blocks_v > p.sort_blocks_p ? p.sort_blocks_v : p.sort_blocks_p;
-  p.hist = take(4 * 256 * (size_t)sb);
   p.pose_part = take(8 * 12 * (size_t)p.pose_blocks);
   p.total = o;
   return true;
@@ -161,7 +215,7 @@ const char* ms_last_error(void) { return g_last_error.c_str(); }
 size_t ms_workspace_bytes(int64_t n, const ms_intrinsics* intr, const ms_options* opts, int64_t pair_capacity) {
   if (check_common(intr, opts, n, pair_capacity) != MS_OK) return 0;
   Plan p;
-  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   return p.total;
 }
 
@@ -174,19 +228,28 @@ int32_t ms_forward(const ms_map* map, const float* viewmat, const ms_intrinsics*
   if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
   if (!out || !out->rgb || !out->depth || !out->silhouette) return fail(MS_ERR_INVALID_ARG, "null output image");
   Plan p;
-  make_plan(map->n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  make_plan(map->n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const Camera cam = make_cam(intr, opts);
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, 2 * C_COUNT, st);
+  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, (int64_t)((p.ctrl_end - p.counters) / 4), st);
   if (e != hipSuccess) return hip_fail(e, "counters");
-  e = launch_project_fwd(*map, viewmat, cam, p, ws, st);
+  {
+    StageTimer t(MS_STAGE_PROJECT, st);
+    e = launch_project_fwd(*map, viewmat, cam, p, ws, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "project");
-  e = launch_bin(p, ws, st);
+  {
+    StageTimer t(MS_STAGE_BIN, st);
+    e = launch_bin(p, ws, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "bin");
-  e = launch_composite_fwd(cam, p, opts->wave_batch, ws, *out, st);
+  {
+    StageTimer t(MS_STAGE_COMPOSITE, st);
+    e = launch_composite_fwd(cam, p, opts->wave_batch, opts->flags, ws, *out, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "composite");
   return MS_OK;
 }
@@ -209,28 +272,34 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
     return fail(MS_ERR_INVALID_ARG, "null map gradient array");
   if (pose_g && (!grads->viewmat || !grads->twist)) return fail(MS_ERR_INVALID_ARG, "null pose gradient");
   Plan p;
-  make_plan(map->n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  make_plan(map->n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const Camera cam = make_cam(intr, opts);
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * map->n, st);
-  if (e != hipSuccess) return hip_fail(e, "zero");
-  e = launch_composite_bwd(cam, p, opts->wave_batch, ws, *grad_out, st);
+  hipError_t e;
+  {
+    StageTimer t(MS_STAGE_COMPOSITE_BWD, st);
+    e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * map->n, st);
+    if (e == hipSuccess) e = launch_composite_bwd(cam, p, opts->wave_batch, opts->flags, ws, *grad_out, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "composite backward");
-  e = launch_project_bwd(*map, viewmat, cam, p, ws, *grads, opts->flags, st);
+  {
+    StageTimer t(MS_STAGE_PROJECT_BWD, st);
+    e = launch_project_bwd(*map, viewmat, cam, p, ws, *grads, opts->flags, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "project backward");
   return MS_OK;
 }
 
 int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
-                      const ms_options* opts, int64_t pair_capacity, int64_t out[6], void* stream) {
+                      const ms_options* opts, int64_t pair_capacity, int64_t out[7], void* stream) {
   int32_t s = check_common(intr, opts, n, pair_capacity);
   if (s != MS_OK) return s;
   if (!out) return fail(MS_ERR_INVALID_ARG, "null output");
   Plan p;
-  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   uint64_t c[C_COUNT];
@@ -241,9 +310,11 @@ int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const m
   out[0] = (int64_t)c[C_VISIBLE];
   out[1] = (int64_t)c[C_PAIRS];
   out[2] = (int64_t)c[C_OVERFLOW];
-  out[3] = p.tiles;
-  out[4] = -1;
-  out[5] = -1;
+  out[3] = p.bins;
+  out[4] = (int64_t)c[C_COMPOSITED];
+  out[5] = (int64_t)c[C_STAGED];
+  out[6] = (int64_t)c[C_REDUCED];
+  if (c[C_ERROR]) return fail(MS_ERR_HIP, "a bounded device wait gave up %llu time(s)", (unsigned long long)c[C_ERROR]);
   return MS_OK;
 }
 
@@ -253,7 +324,7 @@ int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_
   if (s != MS_OK) return s;
   if (!v) return fail(MS_ERR_INVALID_ARG, "null view");
   Plan p;
-  make_plan(n, intr->width, intr->height, opts->tile, pair_capacity, p);
+  make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   char* ws = (char*)workspace;
@@ -268,6 +339,90 @@ int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_
   v->last = at<uint32_t>(ws, p.last);
   v->counters = at<uint64_t>(ws, p.counters);
   v->grad2d = at<float>(ws, p.g2d);
+  v->pair_rank_bits = p.packed ? p.rank_bits : 0;
+  return MS_OK;
+}
+
+int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms_intrinsics* intr, float w_rgb,
+                        float w_depth, float w_sil, const ms_images* grad, float* loss, void* stream) {
+  if (!pred || !target || !grad || !intr) return fail(MS_ERR_INVALID_ARG, "null argument");
+  if (!pred->rgb || !pred->depth || !pred->silhouette || !target->rgb || !target->depth || !target->silhouette ||
+      !grad->rgb || !grad->depth || !grad->silhouette)
+    return fail(MS_ERR_INVALID_ARG, "null image");
+  if (intr->width < 1 || intr->width > 16384 || intr->height < 1 || intr->height > 16384)
+    return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", intr->width, intr->height);
+  if (!std::isfinite(w_rgb) || !std::isfinite(w_depth) || !std::isfinite(w_sil))
+    return fail(MS_ERR_INVALID_ARG, "non-finite loss weight");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = (int64_t)intr->width * intr->height;
+  hipError_t e = hipSuccess;
+  if (loss) e = launch_zero_scalar(loss, st);
+  if (e == hipSuccess) e = launch_l1_grad(pred->rgb, target->rgb, grad->rgb, 3 * P, w_rgb / (3.0f * (float)P), loss, st);
+  if (e == hipSuccess) e = launch_l1_grad(pred->depth, target->depth, grad->depth, P, w_depth / (float)P, loss, st);
+  if (e == hipSuccess)
+    e = launch_l1_grad(pred->silhouette, target->silhouette, grad->silhouette, P, w_sil / (float)P, loss, st);
+  if (e != hipSuccess) return hip_fail(e, "l1 loss");
+  return MS_OK;
+}
+
+int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state, float lr, float beta1, float beta2,
+                          float eps, void* stream) {
+  if (!viewmat || !twist_grad || !state) return fail(MS_ERR_INVALID_ARG, "null argument");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(MS_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+  hipError_t e = launch_pose_adam(viewmat, twist_grad, state, lr, beta1, beta2, eps, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pose step");
+  return MS_OK;
+}
+
+int32_t ms_profiler_create(uint32_t stage_mask, int32_t capacity, ms_profiler** out) {
+  if (!out || capacity < 1 || capacity > (1 << 20)) return fail(MS_ERR_INVALID_ARG, "bad profiler arguments");
+  ms_profiler* p = new ms_profiler();
+  p->mask = stage_mask;
+  p->cap = capacity;
+  p->ev.resize(2 * (size_t)capacity);
+  p->stage.resize(capacity);
+  for (auto& e : p->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      ms_profiler_destroy(p);
+      return hip_fail(r, "hipEventCreate");
+    }
+  }
+  *out = p;
+  return MS_OK;
+}
+
+int32_t ms_profiler_destroy(ms_profiler* p) {
+  if (!p) return MS_OK;
+  if (g_prof == p) g_prof = nullptr;
+  for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  delete p;
+  return MS_OK;
+}
+
+int32_t ms_profiler_attach(ms_profiler* p) {
+  g_prof = p;
+  return MS_OK;
+}
+
+int32_t ms_profiler_read(ms_profiler* p, double total_ms[MS_STAGE_COUNT], int64_t launches[MS_STAGE_COUNT]) {
+  if (!p || !total_ms || !launches) return fail(MS_ERR_INVALID_ARG, "null argument");
+  for (int s = 0; s < MS_STAGE_COUNT; s++) {
+    total_ms[s] = 0.0;
+    launches[s] = 0;
+  }
+  for (int i = 0; i < p->used; i++) {
+    hipError_t e = hipEventSynchronize(p->ev[2 * i + 1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "profiler read");
+    total_ms[p->stage[i]] += ms;
+    launches[p->stage[i]] += 1;
+  }
+  p->used = 0;
   return MS_OK;
 }
 

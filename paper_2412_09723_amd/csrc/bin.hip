@@ -24,7 +24,6 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;   // 2048 items per block
-constexpr int kSortThreads = 256;
 
 // Inclusive block-wide sum scan of one value per thread (256 threads).
 template <typename T>
@@ -140,114 +139,6 @@ __device__ inline int64_t sort_count(const uint64_t* counters, int which, int64_
   return c > limit ? 0 : c;
 }
 
-// Per-block digit histogram of keys[0..count), digit = (key >> shift) & mask.
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __restrict__ keys,
-                                                             const uint64_t* __restrict__ counters, int which,
-                                                             int64_t limit, int shift, int bits, int nblocks,
-                                                             uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  const int64_t count = sort_count(counters, which, limit);
-  const int bins = 1 << bits;
-  const uint32_t mask = (uint32_t)bins - 1u;
-  for (int d = threadIdx.x; d < bins; d += blockDim.x) h[d] = 0u;
-  __syncthreads();
-  const int64_t per = (count + nblocks - 1) / nblocks;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < count ? lo + per : count;
-  for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
-  __syncthreads();
-  for (int d = threadIdx.x; d < bins; d += blockDim.x) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
-}
-
-// Exclusive scan over hist laid out [digit][block] (one block, 1024 threads).
-__global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* __restrict__ hist, int total_entries) {
-  __shared__ uint32_t sh[1024 / 64];
-  __shared__ uint32_t carry_sh;
-  if (threadIdx.x == 0) carry_sh = 0u;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int base = 0; base < total_entries; base += 1024) {
-    const int j = base + threadIdx.x;
-    uint32_t v = j < total_entries ? hist[j] : 0u;
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-      uint32_t y = __shfl_up(x, off, 64);
-      if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wave] = x;
-    __syncthreads();
-    uint32_t pre = 0u, tot = 0u;
-    for (int w = 0; w < 1024 / 64; w++) {
-      if (w < wave) pre += sh[w];
-      tot += sh[w];
-    }
-    const uint32_t carry = carry_sh;
-    if (j < total_entries) hist[j] = carry + pre + x - v;
-    __syncthreads();
-    if (threadIdx.x == 0) carry_sh = carry + tot;
-    __syncthreads();
-  }
-}
-
-// Stable scatter. Each block walks its contiguous range in tiles of 256 keys;
-// a key's destination is the block's running offset for its digit plus the
-// number of equal digits before it in the tile (earlier waves, then earlier
-// lanes of the same wave, found by matching the digit bits with ballots).
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                                const uint32_t* __restrict__ vals_in,
-                                                                uint32_t* __restrict__ keys_out,
-                                                                uint32_t* __restrict__ vals_out,
-                                                                const uint64_t* __restrict__ counters, int which,
-                                                                int64_t limit, int shift, int bits, int nblocks,
-                                                                const uint32_t* __restrict__ hist) {
-  constexpr int W = kSortThreads / 64;
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[W][256];
-  const int64_t count = sort_count(counters, which, limit);
-  const int bins = 1 << bits;
-  const uint32_t mask = (uint32_t)bins - 1u;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < bins; d += blockDim.x) base[d] = hist[(int64_t)d * nblocks + blockIdx.x];
-  const int64_t per = (count + nblocks - 1) / nblocks;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < count ? lo + per : count;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t t0 = lo; t0 < hi; t0 += kSortThreads) {
-    for (int d = threadIdx.x; d < W * 256; d += blockDim.x) (&wcnt[0][0])[d] = 0u;
-    __syncthreads();
-    const int64_t j = t0 + threadIdx.x;
-    const bool ok = j < hi;
-    uint32_t k = 0u, v = 0u, dg = 0u;
-    if (ok) {
-      k = keys_in[j];
-      v = vals_in[j];
-      dg = (k >> shift) & mask;
-    }
-    uint64_t peers = __ballot(ok);
-    for (int b = 0; b < bits; b++) {
-      const uint64_t m = __ballot(ok && ((dg >> b) & 1u));
-      peers &= ((dg >> b) & 1u) ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    if (ok && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (ok) {
-      uint32_t pre = 0u;
-      for (int w = 0; w < wave; w++) pre += wcnt[w][dg];
-      const uint32_t dst = base[dg] + pre + rank;
-      keys_out[dst] = k;
-      vals_out[dst] = v;
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < bins; d += blockDim.x) {
-      uint32_t s = 0u;
-      for (int w = 0; w < W; w++) s += wcnt[w][d];
-      base[d] += s;
-    }
-    __syncthreads();
-  }
-}
-
 // ------------------------------------------------------------------ binning
 // Rank-order gather: records, tile counts and the inverse permutation.
 __global__ void __launch_bounds__(256) k_rank_gather(const uint32_t* __restrict__ sidx,
@@ -274,32 +165,244 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ dst, ui
     dst[j] = value;
 }
 
-// Emit (tile, rank) pairs in rank-major order at the scanned offsets.
+// Emit the (tile, rank) pairs in rank-major order. Work is balanced over
+// the output: each thread writes kEmitPerThread consecutive pairs, finding
+// the rank that owns its first pair by binary search over the offsets, so a
+// splat covering thousands of tiles is spread over many threads. Packed mode
+// writes key = tile << rank_bits | rank; otherwise separate tile and rank
+// arrays.
+constexpr int kEmitPerThread = 8;
+
 __global__ void __launch_bounds__(256) k_emit(const uint4* __restrict__ rec, const uint64_t* __restrict__ off,
-                                              uint64_t* __restrict__ counters, int tile, int tx,
-                                              uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)counters[C_VISIBLE] || counters[C_OVERFLOW]) return;
-  const uint4 b = rec[4 * r + 3];
-  const int x0 = (int)(b.y & 0xFFFFu) / tile, x1 = (int)(b.y >> 16) / tile;
-  const int y0 = (int)(b.z & 0xFFFFu) / tile, y1 = (int)(b.z >> 16) / tile;
-  uint64_t o = off[r];
-  for (int ty = y0; ty <= y1; ty++)
-    for (int txx = x0; txx <= x1; txx++) {
-      pkey[o] = (uint32_t)(ty * tx + txx);
-      pval[o] = (uint32_t)r;
-      o++;
+                                              const uint64_t* __restrict__ counters, int64_t cap, int tile, int tx,
+                                              int rank_bits, uint32_t* __restrict__ pkey,
+                                              uint32_t* __restrict__ pval) {
+  const int64_t nv = (int64_t)counters[C_VISIBLE];
+  const int64_t K = (int64_t)counters[C_PAIRS];
+  if (K > cap || nv == 0) return;
+  for (int64_t o0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kEmitPerThread; o0 < K;
+       o0 += (int64_t)gridDim.x * blockDim.x * kEmitPerThread) {
+    // largest r with off[r] <= o0
+    int64_t lo = 0, hi = nv - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)off[mid] <= o0) lo = mid;
+      else hi = mid - 1;
     }
+    int64_t r = lo;
+    int64_t base = (int64_t)off[r];
+    int64_t next = r + 1 < nv ? (int64_t)off[r + 1] : K;
+    uint4 b = rec[4 * r + 3];
+    int x0 = (int)(b.y & 0xFFFFu) / tile, x1 = (int)(b.y >> 16) / tile;
+    int y0 = (int)(b.z & 0xFFFFu) / tile;
+    int w = x1 - x0 + 1;
+    const int64_t oend = o0 + kEmitPerThread < K ? o0 + kEmitPerThread : K;
+    for (int64_t o = o0; o < oend; o++) {
+      while (o >= next) {
+        r++;
+        base = next;
+        next = r + 1 < nv ? (int64_t)off[r + 1] : K;
+        b = rec[4 * r + 3];
+        x0 = (int)(b.y & 0xFFFFu) / tile;
+        x1 = (int)(b.y >> 16) / tile;
+        y0 = (int)(b.z & 0xFFFFu) / tile;
+        w = x1 - x0 + 1;
+      }
+      const int pos = (int)(o - base);
+      const uint32_t t = (uint32_t)((y0 + pos / w) * tx + x0 + pos % w);
+      if (pval) {
+        pkey[o] = t;
+        pval[o] = (uint32_t)r;
+      } else {
+        pkey[o] = (t << rank_bits) | (uint32_t)r;
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ pkey,
-                                                const uint64_t* __restrict__ counters,
+                                                const uint64_t* __restrict__ counters, int shift,
                                                 uint32_t* __restrict__ trange) {
   const int64_t K = counters[C_OVERFLOW] ? 0 : (int64_t)counters[C_PAIRS];
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = pkey[k];
-    if (k == 0 || pkey[k - 1] != t) trange[2 * (int64_t)t] = (uint32_t)k;
-    if (k == K - 1 || pkey[k + 1] != t) trange[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+    const uint32_t t = pkey[k] >> shift;
+    if (k == 0 || (pkey[k - 1] >> shift) != t) trange[2 * (int64_t)t] = (uint32_t)k;
+    if (k == K - 1 || (pkey[k + 1] >> shift) != t) trange[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+  }
+}
+
+// ------------------------------------------------------- onesweep radix pass
+// One launch per digit pass. Blocks take tiles of kOsTile keys in ticket
+// order; each ranks its keys stably per digit in LDS, publishes its per-digit
+// counts, and obtains the exclusive per-digit prefix of all earlier tiles by
+// decoupled look-back: the predecessors' published words are summed until one
+// carries an inclusive prefix. Every block publishes its aggregate before it
+// waits, and only waits on tiles whose blocks are already running (they took
+// earlier tickets), so the waits end; a spin limit turns a pathological wait
+// into an error counter instead of a hang. Look-back words pack
+// (epoch:8 | flag:2 | value:54); the region is zeroed at every forward and
+// each pass uses its own epoch, so stale words never match.
+constexpr int kOsThreads = 256;
+constexpr int kOsItems = 32;   // 8192 keys per tile: few tiles, short look-back chains
+constexpr int kOsTile = kOsThreads * kOsItems;
+constexpr uint64_t kLbAgg = 1, kLbPre = 2;
+constexpr uint64_t kLbValMask = (1ull << 54) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLbWindow = 16;   // predecessors read per look-back round trip
+
+__device__ inline uint64_t lb_word(uint32_t epoch, uint64_t flag, uint64_t v) {
+  return ((uint64_t)epoch << 56) | (flag << 54) | v;
+}
+
+// Global digit histograms of every pass, in one read of the keys.
+__global__ void __launch_bounds__(1024) k_digit_hist(const uint32_t* __restrict__ keys,
+                                                     const uint64_t* __restrict__ counters, int which,
+                                                     int64_t limit, int first_bit, int bits_per, int total_bits,
+                                                     int passes, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4][256];
+  const int64_t count = sort_count(counters, which, limit);
+  for (int d = threadIdx.x; d < 4 * 256; d += blockDim.x) (&h[0][0])[d] = 0u;
+  __syncthreads();
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[j];
+    for (int p = 0; p < passes; p++) {
+      const int done = p * bits_per;
+      const int bits = done + bits_per <= total_bits ? bits_per : total_bits - done;
+      atomicAdd(&h[p][(k >> (first_bit + done)) & ((1u << bits) - 1u)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < passes * 256; d += blockDim.x) {
+    const uint32_t v = (&h[0][0])[d];
+    if (v) atomicAdd(&hist[d], v);
+  }
+}
+
+// Persistent grid: each block repeatedly takes the next tile ticket. Within a
+// tile, wave w owns the contiguous keys [w*512, (w+1)*512) in 8 rounds of 64,
+// so (wave, round, lane) is the key order; a wave ranks its keys against a
+// wave-private digit counter in LDS (ballot matching of the digit bits, no
+// block barrier), and the waves are combined once per tile.
+__global__ void __launch_bounds__(kOsThreads) k_onesweep(const uint32_t* __restrict__ keys_in,
+                                                         const uint32_t* __restrict__ vals_in,
+                                                         uint32_t* __restrict__ keys_out,
+                                                         uint32_t* __restrict__ vals_out,
+                                                         uint64_t* __restrict__ counters, int which, int64_t limit,
+                                                         int shift, int bits, const uint32_t* __restrict__ hist,
+                                                         uint64_t* __restrict__ lookback,
+                                                         uint32_t* __restrict__ ticket, uint32_t epoch) {
+  constexpr int NW = kOsThreads / 64;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_scan[NW];
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t base[NW][256];
+  const int64_t count = sort_count(counters, which, limit);
+  const int64_t ntiles = (count + kOsTile - 1) / kOsTile;
+  const int t = threadIdx.x;
+  const int bins = 1 << bits;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  const int lane = t & 63, wave = t >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  {
+    const uint32_t h = t < bins ? hist[t] : 0u;
+    uint32_t total;
+    const uint32_t inc = block_inclusive_scan<uint32_t>(h, s_scan, total);
+    goff[t] = inc - h;
+  }
+  while (true) {
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int d = t; d < NW * 256; d += kOsThreads) (&wcnt[0][0])[d] = 0u;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const int64_t j0 = tile * kOsTile + (int64_t)wave * (kOsItems * 64);
+    uint32_t k[kOsItems], v[kOsItems], rnk[kOsItems];
+#pragma unroll
+    for (int i = 0; i < kOsItems; i++) {
+      const int64_t j = j0 + (int64_t)i * 64 + lane;
+      const bool ok = j < count;
+      k[i] = ok ? keys_in[j] : 0u;
+      v[i] = (ok && vals_in) ? vals_in[j] : 0u;
+    }
+    uint32_t* my = wcnt[wave];
+#pragma unroll
+    for (int i = 0; i < kOsItems; i++) {
+      const bool ok = j0 + (int64_t)i * 64 + lane < count;
+      const uint32_t dg = (k[i] >> shift) & mask;
+      uint64_t peers = __ballot(ok);
+      for (int b = 0; b < bits; b++) {
+        const uint64_t m = __ballot(ok && ((dg >> b) & 1u));
+        peers &= ((dg >> b) & 1u) ? m : ~m;
+      }
+      // all lanes of a digit group read the wave's running count, then the
+      // group's lowest lane advances it (same wave: LDS ops stay in order)
+      const uint32_t old = ok ? my[dg] : 0u;
+      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+      rnk[i] = old + below;
+      __builtin_amdgcn_wave_barrier();
+      if (ok && below == 0) my[dg] = old + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: prefix over waves, tile aggregate, publish, look back
+    if (t < bins) {
+      uint32_t run = 0u;
+      for (int w = 0; w < NW; w++) {
+        base[w][t] = run;
+        run += wcnt[w][t];
+      }
+      const uint64_t agg = run;
+      uint64_t* slot = lookback + tile * 256 + t;
+      uint64_t excl = 0;
+      if (tile == 0) {
+        __hip_atomic_store(slot, lb_word(epoch, kLbPre, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(slot, lb_word(epoch, kLbAgg, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // walk back kLbWindow predecessors per round trip: issue the loads,
+        // then consume them in order until one is not yet published
+        int64_t jt = tile - 1;
+        uint32_t spins = 0;
+        bool found = false;
+        while (!found) {
+          uint64_t w8[kLbWindow];
+#pragma unroll
+          for (int q = 0; q < kLbWindow; q++) {
+            const int64_t jq = jt - q >= 0 ? jt - q : 0;
+            w8[q] = __hip_atomic_load(lookback + jq * 256 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          int used = 0;
+#pragma unroll
+          for (int q = 0; q < kLbWindow; q++) {
+            if (found || used != q || jt - q < 0) continue;
+            const uint64_t flag = (w8[q] >> 54) & 3u;
+            if ((uint32_t)(w8[q] >> 56) != epoch || flag == 0) continue;   // not ready: stop here
+            excl += w8[q] & kLbValMask;
+            used = q + 1;
+            if (flag == kLbPre || jt - q == 0) found = true;
+          }
+          jt -= used;
+          if (!found && used == 0 && ++spins > kSpinLimit) {
+            atomicAdd((unsigned long long*)&counters[C_ERROR], 1ull);
+            break;
+          }
+        }
+        __hip_atomic_store(slot, lb_word(epoch, kLbPre, excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const uint32_t g = goff[t] + (uint32_t)excl;
+      for (int w = 0; w < NW; w++) base[w][t] += g;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kOsItems; i++) {
+      const int64_t j = j0 + (int64_t)i * 64 + lane;
+      if (j < count) {
+        const uint32_t dst = base[wave][(k[i] >> shift) & mask] + rnk[i];
+        keys_out[dst] = k[i];
+        if (vals_out) vals_out[dst] = v[i];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -307,18 +410,27 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ pke
 // most 8 bits, ping-ponging between buffer a and buffer b. The data start in
 // a; after an even number of passes they end in a, after an odd number in b
 // (the caller places the input so that the result lands where it wants it).
-hipError_t radix_sort(uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, const uint64_t* counters, int which,
-                      int64_t limit, int total_bits, int nblocks, uint32_t* hist, hipStream_t st) {
+hipError_t radix_sort(uint32_t* ak, uint32_t* av, uint32_t* bk, uint32_t* bv, uint64_t* counters, int which,
+                      int64_t limit, int first_bit, int total_bits, const Plan& p, char* ws, int slot,
+                      hipStream_t st) {
   const int passes = sort_passes(total_bits);
-  const int bits_per = passes > 0 ? (total_bits + passes - 1) / passes : 0;
+  if (passes == 0) return hipSuccess;
+  const int bits_per = (total_bits + passes - 1) / passes;
+  uint32_t* hist = at<uint32_t>(ws, p.digit_hist) + (size_t)slot * 4 * 256;
+  uint32_t* tickets = at<uint32_t>(ws, p.tickets) + (size_t)slot * 4;
+  int64_t hblocks = (limit + 1024 * 16 - 1) / (1024 * 16);
+  if (hblocks > 128) hblocks = 128;
+  if (hblocks < 1) hblocks = 1;
+  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)hblocks), dim3(1024), 0, st, ak, counters, which, limit, first_bit,
+                     bits_per, total_bits, passes, hist);
+  int64_t tiles = (limit + kOsTile - 1) / kOsTile;
+  if (tiles > 2048) tiles = 2048;   // persistent blocks; tiles are taken by ticket
   uint32_t *ki = ak, *vi = av, *ko = bk, *vo = bv;
-  for (int p = 0, shift = 0; p < passes; p++, shift += bits_per) {
-    const int bits = (shift + bits_per <= total_bits) ? bits_per : total_bits - shift;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, st, ki, counters, which, limit, shift,
-                       bits, nblocks, hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, hist, (1 << bits) * nblocks);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, st, ki, vi, ko, vo, counters, which,
-                       limit, shift, bits, nblocks, hist);
+  for (int q = 0, done = 0; q < passes; q++, done += bits_per) {
+    const int bits = (done + bits_per <= total_bits) ? bits_per : total_bits - done;
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)(tiles > 0 ? tiles : 1)), dim3(kOsThreads), 0, st, ki, vi, ko, vo,
+                       counters, which, limit, first_bit + done, bits, hist + (size_t)q * 256,
+                       at<uint64_t>(ws, p.lookback), tickets + q, (uint32_t)(slot * 4 + q + 1));
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
@@ -338,7 +450,7 @@ hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStre
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
   uint64_t* counters = at<uint64_t>(ws, p.counters);
   uint32_t* trange = at<uint32_t>(ws, p.trange);
-  hipError_t e = launch_fill_u32(trange, 0u, 2 * (int64_t)p.tiles, st);
+  hipError_t e = launch_fill_u32(trange, 0u, 2 * (int64_t)p.bins, st);
   if (e != hipSuccess) return e;
   if (p.n == 0) return hipSuccess;
   // 1. compaction of the visible Gaussians, placed so that the depth sort
@@ -356,8 +468,8 @@ hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
                      counters, -1, part, (uint64_t*)nullptr, at<uint32_t>(ws, p.key), dodd ? ck2 : ck,
                      dodd ? cv2 : cv);
   // 2. depth sort (32-bit keys, index values)
-  e = dodd ? radix_sort(ck2, cv2, ck, cv, counters, C_VISIBLE, p.n, 32, p.sort_blocks_v, at<uint32_t>(ws, p.hist), st)
-           : radix_sort(ck, cv, ck2, cv2, counters, C_VISIBLE, p.n, 32, p.sort_blocks_v, at<uint32_t>(ws, p.hist), st);
+  e = dodd ? radix_sort(ck2, cv2, ck, cv, counters, C_VISIBLE, p.n, 0, 32, p, ws, 0, st)
+           : radix_sort(ck, cv, ck2, cv2, counters, C_VISIBLE, p.n, 0, 32, p, ws, 0, st);
   if (e != hipSuccess) return e;
   // 3. gather in rank order, scan tile counts, capacity check
   uint32_t* cnt = at<uint32_t>(ws, p.cnt);
@@ -373,18 +485,22 @@ hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
                      counters, (int)C_VISIBLE, part, off, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                      (uint32_t*)nullptr);
   // 4. emission, placed so that the tile sort ends in (pkey, pval)
-  const int tbits = tile_bits(p.tiles);
+  const int tbits = tile_bits(p.bins);
   const bool podd = sort_passes(tbits) & 1;
-  uint32_t *pk = at<uint32_t>(ws, p.pkey), *pv = at<uint32_t>(ws, p.pval);
-  uint32_t *pk2 = at<uint32_t>(ws, p.pkey2), *pv2 = at<uint32_t>(ws, p.pval2);
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, at<uint4>(ws, p.rec), off,
-                     counters, p.tile, p.tx, podd ? pk2 : pk, podd ? pv2 : pv);
-  // 5. stable sort of the pairs by tile id
-  e = podd ? radix_sort(pk2, pv2, pk, pv, counters, C_PAIRS, p.cap, tbits, p.sort_blocks_p, at<uint32_t>(ws, p.hist), st)
-           : radix_sort(pk, pv, pk2, pv2, counters, C_PAIRS, p.cap, tbits, p.sort_blocks_p, at<uint32_t>(ws, p.hist), st);
+  uint32_t *pk = at<uint32_t>(ws, p.pkey), *pv = p.packed ? nullptr : at<uint32_t>(ws, p.pval);
+  uint32_t *pk2 = at<uint32_t>(ws, p.pkey2), *pv2 = p.packed ? nullptr : at<uint32_t>(ws, p.pval2);
+  int64_t emit_blocks = (p.cap + 256 * 8 - 1) / (256 * 8);
+  if (emit_blocks > 4096) emit_blocks = 4096;
+  if (emit_blocks < 1) emit_blocks = 1;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(256), 0, st, at<uint4>(ws, p.rec), off, counters,
+                     p.cap, p.bin, p.bx, p.rank_bits, podd ? pk2 : pk, podd ? pv2 : pv);
+  // 5. stable sort of the pairs by tile id (the bits above the rank when packed)
+  const int first = p.packed ? p.rank_bits : 0;
+  e = podd ? radix_sort(pk2, pv2, pk, pv, counters, C_PAIRS, p.cap, first, tbits, p, ws, 1, st)
+           : radix_sort(pk, pv, pk2, pv2, counters, C_PAIRS, p.cap, first, tbits, p, ws, 1, st);
   if (e != hipSuccess) return e;
   // 6. tile ranges
-  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, st, pk, counters, trange);
+  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, st, pk, counters, first, trange);
   return hipGetLastError();
 }
 

@@ -37,8 +37,14 @@ constexpr int kGradFields = 10;   // per-rank screen-space adjoint accumulators
 // 3 P1x = sum t1 e dx, 4 P1y = sum t1 e dy, 5 P2y = sum t2 e dy,
 // 6-8 sum G_rgb alpha T, 9 sum G_depth alpha T.
 
-// Device counters (uint64): visible, pairs, overflow, tiles, visited.
-enum Counter { C_VISIBLE = 0, C_PAIRS = 1, C_OVERFLOW = 2, C_TILES = 3, C_VISITED = 4, C_COUNT = 8 };
+// Device counters (uint64).
+// C_COMPOSITED: composited (pixel, Gaussian) pairs of the last forward;
+// C_STAGED: list entries staged into LDS, summed over wavefronts.
+// C_ERROR: bounded waits that gave up (0 in every correct run).
+// C_REDUCED: (wavefront, Gaussian) steps of the backward with an accepting lane.
+enum Counter {
+  C_VISIBLE = 0, C_PAIRS = 1, C_OVERFLOW = 2, C_COMPOSITED = 3, C_STAGED = 4, C_ERROR = 5, C_REDUCED = 6, C_COUNT = 8
+};
 
 struct Camera {
   int W, H;
@@ -49,19 +55,26 @@ struct Camera {
 // ------------------------------------------------------------ workspace plan
 struct Plan {
   int64_t n, cap;
-  int tile, tx, ty, tiles;
+  int tile, tx, ty, tiles;          // compositing tiles
+  int bin, bx, by, bins, bshift;    // binning tiles: bin = tile << bshift
   int64_t pixels;
   int scan_blocks_n;     // blocks of the length-n scans
-  int sort_blocks_v;     // blocks of the depth sort
-  int sort_blocks_p;     // blocks of the pair sort
   int pose_blocks;
+  int rank_bits;         // bits of a depth rank (n - 1)
+  bool packed;           // pairs stored as one word: tile << rank_bits | rank
   // byte offsets
-  size_t counters, key, vis_pos, ntiles, rec_i, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part,
-      pkey, pval, pkey2, pval2, trange, tfinal, last, g2d, hist, pose_part;
+  // control region (zeroed by one fill at every forward): counters, sort
+  // tickets, digit histograms, look-back words
+  size_t counters, tickets, digit_hist, lookback, ctrl_end;
+  size_t key, vis_pos, ntiles, rec_i, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part,
+      pkey, pval, pkey2, pval2, trange, tfinal, last, g2d, pose_part;
   size_t total;
 };
 
-bool make_plan(int64_t n, int W, int H, int tile, int64_t cap, Plan& p);
+bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p);
+
+// Mask extracting the depth rank from a sorted pair word.
+inline uint32_t rank_mask(const Plan& p) { return p.packed ? ((1u << p.rank_bits) - 1u) : 0xFFFFFFFFu; }
 
 // Number of LSD passes (<= 8 bits each) for keys of `bits` significant bits.
 inline int sort_passes(int bits) { return (bits + 7) / 8; }
@@ -77,13 +90,18 @@ inline int tile_bits(int tiles) {
 hipError_t launch_project_fwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p,
                               char* ws, hipStream_t st);
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st);
-hipError_t launch_composite_fwd(const Camera& cam, const Plan& p, int wave_batch, char* ws, const ms_images& out,
-                                hipStream_t st);
-hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch, char* ws, const ms_images& gout,
-                                hipStream_t st);
+hipError_t launch_composite_fwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
+                                const ms_images& out, hipStream_t st);
+hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
+                                const ms_images& gout, hipStream_t st);
 hipError_t launch_project_bwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p, char* ws,
                               const ms_grads& g, uint32_t flags, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStream_t st);
+hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, int64_t count, float scale,
+                          float* loss, hipStream_t st);
+hipError_t launch_zero_scalar(float* p, hipStream_t st);
+hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,
+                            hipStream_t st);
 
 template <typename T>
 __host__ __device__ inline T* at(char* ws, size_t off) {

@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(256) k_project_fwd(int64_t n, const float* __r
   vis[i] = 1u;
   ntiles[i] = ntx * nty;
   uint4 r0, r1, r2, r3;
-  r0.x = (uint32_t)(int32_t)ufl;
-  r0.y = (uint32_t)(int32_t)vfl;
+  r0.x = __float_as_uint((float)ufl);   // integer-valued, |floor(u)| <= 2^22: exact
+  r0.y = __float_as_uint((float)vfl);
   r0.z = __float_as_uint((float)(u - ufl));
   r0.w = __float_as_uint((float)(v - vfl));
   r1.x = __float_as_uint((float)(kKappa * l11));
@@ -421,7 +421,7 @@ hipError_t launch_project_fwd(const ms_map& map, const float* viewmat, const Cam
   if (map.n == 0) return hipSuccess;
   const int64_t blocks = (map.n + 255) / 256;
   hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)blocks), dim3(256), 0, st, map.n, map.means, map.scales,
-                     map.quats, map.opacity, map.colors, viewmat, cam, p.tile, at<uint32_t>(ws, p.key),
+                     map.quats, map.opacity, map.colors, viewmat, cam, p.bin, at<uint32_t>(ws, p.key),
                      at<uint32_t>(ws, p.vis_pos), at<uint32_t>(ws, p.ntiles), at<int32_t>(ws, p.rank_of),
                      at<uint4>(ws, p.rec_i));
   return hipGetLastError();

@@ -1,0 +1,111 @@
+// Tracking-loop helpers around the render: the gradient of the L1
+// photometric/depth loss (the loss form of Eq. 7's L1 terms, used here for
+// per-agent tracking), and one Adam step on the left SE(3) twist of the pose
+// (Sec. 3.1 poses in SE(3)), applied as [R|t] <- exp(-step^) [R|t]. Both stay
+// on the device so a tracking step needs no host round trip.
+#include "ms_internal.h"
+
+namespace ms {
+namespace {
+
+constexpr int kLossThreads = 256;
+
+// grad = w * sign(pred - target) / count for each plane; optional loss sum
+// (sum of w |pred - target| / count) accumulated with one atomic per block.
+__global__ void __launch_bounds__(kLossThreads) k_l1_grad(const float* __restrict__ pred,
+                                                          const float* __restrict__ target, float* __restrict__ grad,
+                                                          int64_t count, float scale, float* __restrict__ loss) {
+  __shared__ float red[kLossThreads / 64];
+  float acc = 0.f;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
+    const float d = pred[j] - target[j];
+    grad[j] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    acc += fabsf(d) * scale;
+  }
+  if (!loss) return;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int w = 0; w < kLossThreads / 64; w++) s += red[w];
+    unsafeAtomicAdd(loss, s);
+  }
+}
+
+__global__ void k_zero_f32(float* p) { *p = 0.f; }
+
+// Adam on the twist xi = (rho, phi), then V <- exp(-step^) V in binary64.
+// state: m[6], v[6], t.
+__global__ void k_pose_adam(float* __restrict__ viewmat, const float* __restrict__ g, float* __restrict__ state,
+                            float lr, float b1, float b2, float eps) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const float t = state[12] + 1.f;
+  state[12] = t;
+  double xi[6];
+  for (int k = 0; k < 6; k++) {
+    const float m = b1 * state[k] + (1.f - b1) * g[k];
+    const float v = b2 * state[6 + k] + (1.f - b2) * g[k] * g[k];
+    state[k] = m;
+    state[6 + k] = v;
+    const double mh = m / (1.0 - pow((double)b1, (double)t));
+    const double vh = v / (1.0 - pow((double)b2, (double)t));
+    xi[k] = -(double)lr * mh / (sqrt(vh) + (double)eps);
+  }
+  // exp of the se(3) element (rho = xi[0..2], phi = xi[3..5]), Rodrigues form
+  const double px = xi[3], py = xi[4], pz = xi[5];
+  const double th2 = px * px + py * py + pz * pz, th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-8) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[3][3] = {{0, -pz, py}, {pz, 0, -px}, {-py, px, 0}};
+  double K2[3][3], Rx[3][3], Vm[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      K2[a][b] = K[a][0] * K[0][b] + K[a][1] * K[1][b] + K[a][2] * K[2][b];
+      Rx[a][b] = (a == b ? 1.0 : 0.0) + A * K[a][b] + B * K2[a][b];
+      Vm[a][b] = (a == b ? 1.0 : 0.0) + B * K[a][b] + C * K2[a][b];
+    }
+  double V[3][4], out[3][4];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 4; b++) V[a][b] = viewmat[4 * a + b];
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 4; b++) out[a][b] = Rx[a][0] * V[0][b] + Rx[a][1] * V[1][b] + Rx[a][2] * V[2][b];
+    out[a][3] += Vm[a][0] * xi[0] + Vm[a][1] * xi[1] + Vm[a][2] * xi[2];
+  }
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 4; b++) viewmat[4 * a + b] = (float)out[a][b];
+}
+
+}  // namespace
+
+hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, int64_t count, float scale,
+                          float* loss, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + kLossThreads - 1) / kLossThreads;
+  const int64_t max_blocks = loss ? 128 : 2048;   // one atomic per block on the loss
+  if (blocks > max_blocks) blocks = max_blocks;
+  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, pred, target, grad, count, scale,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_scalar(float* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(1), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_adam, dim3(1), dim3(64), 0, st, viewmat, g, state, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+}  // namespace ms

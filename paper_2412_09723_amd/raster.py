@@ -23,16 +23,23 @@ NEAR_Z = 0.2
 @dataclasses.dataclass(frozen=True)
 class RenderOptions:
     tile: int = 16
+    bin_tile: int = 128                  # 0: bin at `tile`; else a power of two in [tile, 256]
     wave_batch: int = 64
     near_z: float = NEAR_Z
     pair_capacity: int | None = None     # None: sized from the map (see default_capacity)
     check: bool = False                  # read the device counters after the forward (synchronises)
+    fwd_records: str = "lds"             # forward compositing record path: "lds" staging or "scalar" (SGPR)
+    bwd_records: str = "mfma"            # backward compositing: "lds", "scalar" or "mfma" (scalar records,
+                                         # pixel reduction on the matrix cores; tile 8 or 16)
+    grow: bool = True                    # with check: enlarge the pair capacity and redo on overflow
 
 
 def default_capacity(n: int, width: int, height: int, tile: int) -> int:
-    """Pair capacity heuristic: 16 tiles per Gaussian plus 64 per tile."""
+    """Pair capacity heuristic: (8 + 512/tile) pairs per Gaussian plus 64 per
+    tile (a 1M-Gaussian room at 1200x680 needs about 7 pairs per Gaussian at
+    tile 16 and 24 at tile 8). A checked forward grows it when exceeded."""
     tiles = ((width + tile - 1) // tile) * ((height + tile - 1) // tile)
-    return int(min(16 * n + 64 * tiles + 4096, 0xFFFFFFFF))
+    return int(min((8 + 512 // tile) * n + 64 * tiles + 4096, 0xFFFFFFFF))
 
 
 def to_soa(t: torch.Tensor) -> torch.Tensor:
@@ -46,7 +53,13 @@ def intr_struct(intr) -> MsIntrinsics:
 
 
 def opts_struct(opts: RenderOptions, flags: int = 0) -> MsOptions:
-    return MsOptions(int(opts.tile), int(opts.wave_batch), float(opts.near_z), int(flags))
+    if opts.fwd_records == "scalar":
+        flags |= _lib.MS_FLAG_SCALAR_FWD
+    if opts.bwd_records == "scalar":
+        flags |= _lib.MS_FLAG_SCALAR_BWD
+    if opts.bwd_records == "mfma":
+        flags |= _lib.MS_FLAG_MFMA_BWD
+    return MsOptions(int(opts.tile), int(opts.wave_batch), float(opts.near_z), int(flags), int(opts.bin_tile))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -90,7 +103,7 @@ class Job:
         self.intr = intr
         self.opts = opts
         self.cap = opts.pair_capacity if opts.pair_capacity is not None else default_capacity(
-            self.n, intr.width, intr.height, opts.tile)
+            self.n, intr.width, intr.height, opts.bin_tile or opts.tile)
         self.c_intr = intr_struct(intr)
         self.c_map = MsMap(self.n, m["means"].data_ptr(), m["scales"].data_ptr(), m["quats"].data_ptr(),
                            m["opacity"].data_ptr(), m["colors"].data_ptr())
@@ -119,9 +132,21 @@ class Job:
         if self.opts.check:
             st = self.stats()
             if st["overflow"]:
-                raise _lib.MacsplatError(_lib.MS_ERR_CAPACITY,
-                                         f"{st['pairs']} pairs exceed the capacity {self.cap}")
+                if not self.opts.grow:
+                    raise _lib.MacsplatError(_lib.MS_ERR_CAPACITY,
+                                             f"{st['pairs']} pairs exceed the capacity {self.cap}")
+                self._resize(int(min(st["pairs"] * 5 // 4 + 4096, 0xFFFFFFFF)))
+                return self.forward(out=(rgb, depth, sil))
         return rgb, depth, sil
+
+    def _resize(self, cap: int):
+        lib = _lib.load()
+        self.cap = cap
+        self.ws_bytes = lib.ms_workspace_bytes(self.n, ref(self.c_intr), ref(opts_struct(self.opts)), self.cap)
+        if self.ws_bytes == 0:
+            check(_lib.MS_ERR_INVALID_ARG)
+        if self.ws.numel() < self.ws_bytes:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.m["means"].device)
 
     # -- backward ----------------------------------------------------------
     def backward(self, g_rgb, g_depth, g_sil, map_grads: bool = True, pose_grads: bool = True,
@@ -150,11 +175,12 @@ class Job:
 
     # -- inspection ---------------------------------------------------------
     def stats(self) -> dict:
-        out = (ctypes.c_int64 * 6)()
+        out = (ctypes.c_int64 * 7)()
         lib = _lib.load()
         check(lib.ms_read_stats(_ptr(self.ws), self.ws_bytes, self.n, ref(self.c_intr), ref(opts_struct(self.opts)),
                                 self.cap, out, _stream_ptr(self.m["means"].device)))
-        return dict(visible=out[0], pairs=out[1], overflow=bool(out[2]), tiles=out[3])
+        return dict(visible=out[0], pairs=out[1], overflow=bool(out[2]), tiles=out[3], composited=out[4],
+                    staged=out[5], reduced=out[6])
 
     def state(self) -> dict:
         """Device views of the forward state (see ms_state_view in the header)."""
@@ -165,7 +191,7 @@ class Job:
         base = self.ws.data_ptr()
         n = max(self.n, 1)
         H, W = self.intr.height, self.intr.width
-        t = self.opts.tile
+        t = self.opts.bin_tile or self.opts.tile
         tiles = ((W + t - 1) // t) * ((H + t - 1) // t)
 
         def view(ptr, count, dtype):
@@ -173,18 +199,26 @@ class Job:
             nbytes = count * torch.empty((), dtype=dtype).element_size()
             return self.ws[off:off + nbytes].view(dtype)
 
+        pair_tile = view(v.pair_tile, max(self.cap, 1), torch.int32)
+        pair_rank = view(v.pair_rank, max(self.cap, 1), torch.int32)
+        if v.pair_rank_bits > 0:       # packed pair words: tile << bits | rank
+            bits = v.pair_rank_bits
+            words = pair_tile.to(torch.int64) & 0xFFFFFFFF
+            pair_tile = (words >> bits).to(torch.int32)
+            pair_rank = (words & ((1 << bits) - 1)).to(torch.int32)
         return dict(
             depth_key=view(v.depth_key, n, torch.int32),
             sorted_index=view(v.sorted_index, n, torch.int32),
             rank_of=view(v.rank_of, n, torch.int32),
-            pair_tile=view(v.pair_tile, max(self.cap, 1), torch.int32),
-            pair_rank=view(v.pair_rank, max(self.cap, 1), torch.int32),
+            pair_tile=pair_tile,
+            pair_rank=pair_rank,
             tile_range=view(v.tile_range, 2 * tiles, torch.int32).view(tiles, 2),
             records=view(v.records, 16 * n, torch.float32).view(n, 16),
             tfinal=view(v.tfinal, H * W, torch.float32).view(H, W),
             last=view(v.last, H * W, torch.int32).view(H, W),
             counters=view(v.counters, 8, torch.int64),
             grad2d=view(v.grad2d, 10 * n, torch.float32).view(n, 10),
+            pair_rank_bits=int(v.pair_rank_bits),
         )
 
 

@@ -13,9 +13,11 @@ def to_dev(sc, device="cuda"):
     return m, t(sc.viewmat)
 
 
-def run_job(sc, tile=16, wave_batch=64, cap=None, check=True):
+def run_job(sc, tile=16, wave_batch=64, cap=None, check=True, scalar=False, bin_tile=0, bwd=None):
     m, vm = to_dev(sc)
-    opts = raster.RenderOptions(tile=tile, wave_batch=wave_batch, pair_capacity=cap, check=check)
+    mode = "scalar" if scalar else "lds"
+    opts = raster.RenderOptions(tile=tile, wave_batch=wave_batch, pair_capacity=cap, check=check,
+                                fwd_records=mode, bwd_records=bwd or mode, bin_tile=bin_tile)
     job = raster.Job(m, vm, sc.intr, opts)
     rgb, depth, sil = job.forward()
     return job, (rgb, depth, sil)
@@ -29,7 +31,7 @@ def expected_order(pr):
 def check_structure(job, sc, tile):
     """Keys, records, depth order and tile lists: bit-exact with the oracle."""
     pr = oracle.project(sc)
-    st = {k: v.cpu().numpy() for k, v in job.state().items()}
+    st = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in job.state().items()}
     nv, K = int(st["counters"][0]), int(st["counters"][1])
     assert not st["counters"][2], "pair capacity overflow"
     assert nv == int(pr["visible"].sum())
@@ -40,8 +42,8 @@ def check_structure(job, sc, tile):
     rec = st["records"][:nv].view(np.uint32)
     idx = rec[:, 15].astype(np.int64)
     assert np.array_equal(idx, order)
-    assert np.array_equal(rec[:, 0].view(np.int32), pr["ctr"][0][idx])
-    assert np.array_equal(rec[:, 1].view(np.int32), pr["ctr"][1][idx])
+    assert np.array_equal(rec[:, 0].view(np.float32), pr["ctr"][0][idx].astype(np.float32))
+    assert np.array_equal(rec[:, 1].view(np.float32), pr["ctr"][1][idx].astype(np.float32))
     for w, k in ((2, 0), (3, 1), (4, 2), (5, 3), (6, 4), (7, 5)):
         assert np.array_equal(rec[:, w], pr["rec"][k][idx].view(np.uint32)), f"record word {w}"
     assert np.array_equal(rec[:, 9], pr["zkey"][idx])

@@ -54,6 +54,10 @@ def test_workspace_bytes(lib):
     assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(12, 64, 0.2, 0)), 1 << 20) == 0
     assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 48, 0.2, 0)), 1 << 20) == 0
     assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 64, 0.0, 0)), 1 << 20) == 0
+    assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 64, 0.2, 0, 8)), 1 << 20) == 0
+    assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 64, 0.2, 0, 48)), 1 << 20) == 0
+    assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 64, 0.2, 0, 512)), 1 << 20) == 0
+    assert lib.ms_workspace_bytes(4096, ref(INTR), ref(MsOptions(16, 64, 0.2, 0, 128)), 1 << 20) > 0
     assert lib.ms_workspace_bytes(-1, ref(INTR), ref(OPTS), 1 << 20) == 0
     assert lib.ms_workspace_bytes(4096, ref(MsIntrinsics(0, 120, 150, 150, 80, 60)), ref(OPTS), 1 << 20) == 0
     assert lib.ms_workspace_bytes(4096, ref(MsIntrinsics(160, 120, -1, 150, 80, 60)), ref(OPTS), 1 << 20) == 0
@@ -109,7 +113,7 @@ def test_backward_rejects_bad_arguments(lib):
 
 
 def test_read_stats_and_view_reject_bad_workspace(lib):
-    out = (ctypes.c_int64 * 6)()
+    out = (ctypes.c_int64 * 7)()
     assert lib.ms_read_stats(ctypes.c_void_p(FAKE + 4), 1 << 40, 10, ref(INTR), ref(OPTS), 100, out, None) \
         == _lib.MS_ERR_WORKSPACE
     v = _lib.MsStateView()

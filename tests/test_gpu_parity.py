@@ -30,12 +30,16 @@ def _dev_grads(g):
     return [torch.from_numpy(a).cuda() for a in g]
 
 
-@pytest.mark.parametrize("tile,wb", [(16, 64), (8, 32), (32, 128), (16, 128), (8, 64), (32, 32)])
-def test_config0_forward_backward(tile, wb):
-    _log(f"config0 tile={tile} wb={wb}")
+@pytest.mark.parametrize("tile,wb,scalar,bin_tile,bwd", [
+    (16, 64, False, 0, None), (8, 32, False, 0, None), (32, 128, False, 0, None), (16, 128, False, 0, None),
+    (8, 64, False, 0, None), (32, 32, False, 0, None), (8, 64, True, 0, None), (16, 64, True, 0, None),
+    (32, 64, True, 0, None), (16, 64, False, 64, None), (16, 64, True, 128, None), (32, 64, False, 128, None),
+    (8, 32, True, 32, None), (16, 64, False, 128, "mfma"), (8, 64, False, 0, "mfma"), (16, 64, True, 0, "mfma")])
+def test_config0_forward_backward(tile, wb, scalar, bin_tile, bwd):
+    _log(f"config0 tile={tile} wb={wb} scalar={scalar} bin={bin_tile} bwd={bwd}")
     sc = scenes.config0()
-    job, imgs = run_job(sc, tile=tile, wave_batch=wb)
-    check_structure(job, sc, tile)
+    job, imgs = run_job(sc, tile=tile, wave_batch=wb, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
+    check_structure(job, sc, bin_tile or tile)
     ref = oracle.forward(sc)
     errs, flagged = check_images(imgs, ref)
     _log(f"  image max rel err {errs}, flagged {flagged}")
@@ -56,8 +60,9 @@ def test_config0_rotated_pose_and_ragged_image():
     sc = scenes.frustum_scene(700, intr, scenes.rng_for(9, 77), viewmat=vm)
     sc.means[0, :20] *= 2.5           # some centres off-screen
     sc.means[2, 20:25] = 0.1          # behind the near plane
-    for tile in (8, 16, 32):
-        job, imgs = run_job(sc, tile=tile, wave_batch=32)
+    for tile, scalar, bwd in ((8, False, None), (16, False, None), (32, False, None), (8, True, None),
+                              (16, True, None), (32, True, None), (8, False, "mfma"), (16, False, "mfma")):
+        job, imgs = run_job(sc, tile=tile, wave_batch=32, scalar=scalar, bwd=bwd)
         check_structure(job, sc, tile)
         ref = oracle.forward(sc)
         check_images(imgs, ref)
@@ -66,12 +71,14 @@ def test_config0_rotated_pose_and_ragged_image():
         check_grads(g, oracle.backward(sc, *up))
 
 
-def test_config1_full_size():
-    """1200x680, 1M Gaussians (the benchmark workload), tile 16, batch 64."""
-    _log("config1 full size")
+@pytest.mark.parametrize("scalar,tile,bin_tile,bwd", [(False, 16, 0, None), (True, 16, 0, None),
+                                                     (False, 32, 128, None), (False, 16, 128, "mfma")])
+def test_config1_full_size(scalar, tile, bin_tile, bwd):
+    """1200x680, 1M Gaussians (the benchmark workload)."""
+    _log(f"config1 full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")
     sc = scenes.config1()
-    job, imgs = run_job(sc, tile=16, wave_batch=64)
-    check_structure(job, sc, 16)
+    job, imgs = run_job(sc, tile=tile, wave_batch=64, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
+    check_structure(job, sc, bin_tile or tile)
     ref = oracle.forward(sc)
     errs, flagged = check_images(imgs, ref)
     _log(f"  image max rel err {errs}, flagged {flagged}")
@@ -112,7 +119,10 @@ def test_capacity_overflow_is_reported_not_truncated():
     g = job.backward(*_dev_grads(_up(sc)))
     assert torch.isnan(g["twist"]).all()
     with pytest.raises(_lib.MacsplatError):
-        raster.Job(m, vm, sc.intr, raster.RenderOptions(pair_capacity=1000, check=True)).forward()
+        raster.Job(m, vm, sc.intr, raster.RenderOptions(pair_capacity=1000, check=True, grow=False)).forward()
+    grown = raster.Job(m, vm, sc.intr, raster.RenderOptions(pair_capacity=1000, check=True))
+    rgb2, _, _ = grown.forward()
+    assert grown.cap >= st["pairs"] and not grown.stats()["overflow"] and torch.isfinite(rgb2).all()
 
 
 def test_repeat_determinism_of_forward():
