@@ -50,10 +50,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy three times (scale for HBM byte counters) and exit")
     return ap.parse_args()
 
 
-def kernel_source_hash(files=("composite.hip",)) -> str:
+def kernel_source_hash(files=("composite.hip", "ms_internal.h")) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2412_09723_amd", "csrc", f), "rb") as fh:
@@ -102,8 +104,26 @@ def cpu_baseline(scene, target_s: float):
                          "accepted": int(fwd["counters"][2]), "composited": int(fwd["counters"][3])}}
 
 
+COPY_BYTES = 512 << 20
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of COPY_BYTES: its FETCH_SIZE/WRITE_SIZE
+    counters give the factor between counted and moved bytes."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,13 +173,17 @@ def main():
     # timed region; the dominant kernel's launches carry HIP events on the
     # stream they run on (the current torch stream)
     prof = _lib.Profiler(stages=(dominant,))
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     with prof:
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        marks[0].record()
+        for i in range(args.steps):
             tracker.step(args.iters)
+            marks[i + 1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+    step_ms = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)])
     dom = prof.read()[dominant]
     prof.close()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -196,7 +220,8 @@ def main():
     out = {
         "metric": "Mpix/s RGB-D fwd+bwd @1M Gaussians 1200x680; served frames/s + p99 vs plain",
         "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": round(ms_per_step, 3), "step_ms_median": round(float(np.median(step_ms)), 3),
+        "step_ms_p90": round(float(np.percentile(step_ms, 90)), 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "tracking step: 10 x (RGB-D forward + L1 loss grad + full backward + pose Adam), "
                                f"1M-Gaussian 6x4x3 m room, 1200x680, tile {args.tile}, wave batch {args.wave_batch}, "

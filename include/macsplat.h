@@ -31,7 +31,7 @@
  *   Projection, IEEE binary64, round to nearest, no fused multiply-add,
  *   sums left to right as written; float inputs widened exactly.
  *     p_i = ((R_i0 m_0 + R_i1 m_1) + R_i2 m_2) + t_i
- *     culled unless p_2 > near, p finite, o and s finite;
+ *     culled unless p_2 > near, p finite, o, s and the colour finite;
  *     n2 = ((w w + x x) + y y) + z z, culled unless 0 < n2 < inf;
  *     r = 1/sqrt(n2); (w,x,y,z) *= r; Rq from the products xx, yy, zz, xy,
  *       xz, yz, wx, wy, wz as Rq00 = 1 - 2(yy+zz), Rq01 = 2(xy-wz),
@@ -128,8 +128,8 @@ typedef struct {
 #define MS_FLAG_SCALAR_FWD 4u       /* forward compositing reads each Gaussian's record with wave-uniform
                                        scalar loads instead of staging wave_batch records through LDS */
 #define MS_FLAG_SCALAR_BWD 8u       /* the same for backward compositing */
-#define MS_FLAG_MFMA_BWD 16u        /* backward compositing with scalar records and the per-Gaussian pixel
-                                       reduction done as a matrix-core product (tile 8 or 16) */
+#define MS_FLAG_MFMA_BWD 16u        /* backward compositing with the per-Gaussian reduction over each 8x8
+                                       sub-block done as a matrix-core product */
 
 /* Launch options. tile: edge in pixels of the screen tile one compositing
  * workgroup owns, 8 | 16 | 32. bin_tile: edge of the tiles whose

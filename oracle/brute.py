@@ -98,6 +98,8 @@ def pinned(scene, near_z=0.2):
             continue
         if not math.isfinite(o) or not all(math.isfinite(v) for v in s):
             continue
+        if not all(math.isfinite(float(scene.colors[k, i])) for k in range(3)):
+            continue
         n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]
         if not (n2 > 0.0) or not math.isfinite(n2):
             continue

@@ -120,7 +120,8 @@ struct Pinned {
 
 // The pinned recipe. Binary64, round to nearest, no fused multiply-add,
 // each sum evaluated left to right as written.
-Pinned pinned_project(const double mu[3], const double s[3], const double q[4], double o, const Cam& cam) {
+Pinned pinned_project(const double mu[3], const double s[3], const double q[4], double o, const double col[3],
+                      const Cam& cam) {
   Pinned P;
   std::memset(&P, 0, sizeof(P));
   P.visible = false;
@@ -130,6 +131,8 @@ Pinned pinned_project(const double mu[3], const double s[3], const double q[4], 
   if (!(p[2] > cam.near_z)) return P;
   if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2])) return P;
   if (!std::isfinite(o) || !std::isfinite(s[0]) || !std::isfinite(s[1]) || !std::isfinite(s[2])) return P;
+  // a Gaussian with a non-finite attribute is culled, colour included
+  if (!std::isfinite(col[0]) || !std::isfinite(col[1]) || !std::isfinite(col[2])) return P;
   double n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
   if (!(n2 > 0.0) || !std::isfinite(n2)) return P;
   double rn = 1.0 / std::sqrt(n2);
@@ -342,7 +345,7 @@ void prepare(const Inputs& in, const Cam& cam, Prepared& pr, const int8_t* froze
   for (int64_t i = 0; i < n; i++) {
     double mu[3], s[3], q[4], o, col[3];
     gather(in, i, mu, s, q, o, col);
-    pr.pin[i] = pinned_project(mu, s, q, o, cam);
+    pr.pin[i] = pinned_project(mu, s, q, o, col, cam);
     for (int k = 0; k < 3; k++) pr.col[3 * i + k] = col[k];
     pr.opac[i] = o;
     if (pr.pin[i].visible) {
@@ -615,20 +618,21 @@ extern "C" {
 int or_version(void) { return 1; }
 
 // Pinned projection of every Gaussian (the discrete structure).
+// Inputs as in the C ABI (colours only decide culling here).
 // Outputs, length n each: visible (0/1), zkey (bits of binary32 depth),
 // bbox [4][n] (xlo, xhi, ylo, yhi; clamped pixel box), ctr [2][n] (ui, vi),
 // rec [6][n] (uf, vf, a, b, c, qcut), z32 [n]. Culled entries are zero.
 int or_project(int64_t n, const float* means, const float* scales, const float* quats, const float* opac,
-               const float* viewmat, int W, int H, float fx, float fy, float cx, float cy, float near_z,
+               const float* colors, const float* viewmat, int W, int H, float fx, float fy, float cx, float cy, float near_z,
                uint8_t* visible, uint32_t* zkey, int32_t* bbox, int32_t* ctr, float* rec, float* z32, int nthreads) {
   Cam cam = cam_from_float(viewmat, W, H, fx, fy, cx, cy, near_z);
   nthreads = threads_or_default(nthreads);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
   for (int64_t i = 0; i < n; i++) {
-    double mu[3], s[3], q[4];
-    for (int k = 0; k < 3; k++) { mu[k] = means[k * n + i]; s[k] = scales[k * n + i]; }
+    double mu[3], s[3], q[4], col[3];
+    for (int k = 0; k < 3; k++) { mu[k] = means[k * n + i]; s[k] = scales[k * n + i]; col[k] = colors[k * n + i]; }
     for (int k = 0; k < 4; k++) q[k] = quats[k * n + i];
-    Pinned P = pinned_project(mu, s, q, (double)opac[i], cam);
+    Pinned P = pinned_project(mu, s, q, (double)opac[i], col, cam);
     visible[i] = P.visible ? 1 : 0;
     zkey[i] = P.zkey;
     bbox[0 * n + i] = P.xlo; bbox[1 * n + i] = P.xhi; bbox[2 * n + i] = P.ylo; bbox[3 * n + i] = P.yhi;

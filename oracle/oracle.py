@@ -47,7 +47,7 @@ F64 = ctypes.c_double
 
 
 def _declare(lib):
-    lib.or_project.argtypes = [I64, P, P, P, P, P, I32, I32, F32, F32, F32, F32, F32,
+    lib.or_project.argtypes = [I64, P, P, P, P, P, P, I32, I32, F32, F32, F32, F32, F32,
                                P, P, P, P, P, P, I32]
     lib.or_project.restype = I32
     lib.or_pinned_log2.argtypes = [F64]
@@ -102,12 +102,12 @@ def project(scene, near_z: float = NEAR_Z, nthreads: int = 0) -> dict:
     """Pinned projection: visible, zkey, bbox[4,n], ctr[2,n], rec[6,n], z32."""
     lib = load()
     n = scene.n
-    means, scales, quats, opac, _ = _scene_args(scene)
+    means, scales, quats, opac, colors = _scene_args(scene)
     vm = _f32(scene.viewmat)
     out = dict(visible=np.zeros(n, np.uint8), zkey=np.zeros(n, np.uint32),
                bbox=np.zeros((4, n), np.int32), ctr=np.zeros((2, n), np.int32),
                rec=np.zeros((6, n), np.float32), z32=np.zeros(n, np.float32))
-    lib.or_project(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(vm),
+    lib.or_project(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(colors), _ptr(vm),
                    *_cam_args(scene), float(near_z),
                    _ptr(out["visible"]), _ptr(out["zkey"]), _ptr(out["bbox"]), _ptr(out["ctr"]),
                    _ptr(out["rec"]), _ptr(out["z32"]), int(nthreads))

@@ -155,7 +155,7 @@ bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p)
     o += align_up(bytes);
     return r;
   };
-  p.counters = take(sizeof(uint64_t) * C_COUNT);
+  p.counters = take(kCounterBytes);
   p.tickets = take(4 * 8);                       // 2 sorts x 4 passes
   p.digit_hist = take(4 * 256 * 8);              // 2 sorts x 4 passes x 256 digits
   {
@@ -302,18 +302,21 @@ int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const m
   make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
   s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
-  uint64_t c[C_COUNT];
+  std::vector<uint64_t> c(kCounterBytes / 8);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(c, (const char*)workspace + p.counters, sizeof(c), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(c.data(), (const char*)workspace + p.counters, kCounterBytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "read stats");
+  uint64_t w[3] = {0, 0, 0};
+  for (int slot = 0; slot < kWorkSlots; slot++)
+    for (int k = 0; k < 3; k++) w[k] += c[kWorkBase + slot * kWorkStride + k];
   out[0] = (int64_t)c[C_VISIBLE];
   out[1] = (int64_t)c[C_PAIRS];
   out[2] = (int64_t)c[C_OVERFLOW];
   out[3] = p.bins;
-  out[4] = (int64_t)c[C_COMPOSITED];
-  out[5] = (int64_t)c[C_STAGED];
-  out[6] = (int64_t)c[C_REDUCED];
+  out[4] = (int64_t)w[W_COMPOSITED];
+  out[5] = (int64_t)w[W_STAGED];
+  out[6] = (int64_t)w[W_REDUCED];
   if (c[C_ERROR]) return fail(MS_ERR_HIP, "a bounded device wait gave up %llu time(s)", (unsigned long long)c[C_ERROR]);
   return MS_OK;
 }

@@ -3,14 +3,16 @@
 //
 // Work decomposition (CDNA4, wave64). A workgroup owns one screen tile of
 // TILE x TILE pixels; each of its (TILE/8)^2 wavefronts owns one 8x8 pixel
-// sub-block (one pixel per lane) and walks the tile's depth-ordered list on
-// its own: it stages WB records at a time from HBM/L2 into its private LDS
-// slot (one record per lane, converted to sub-block-local form), then every
-// lane evaluates the staged Gaussians against its pixel with the staged
-// values read as LDS broadcasts. There is no workgroup barrier: each wave
-// stops as soon as all 64 of its pixels are done (ballot), and Gaussians
-// whose pixel box misses the wave's sub-block are skipped with a scalar
-// branch (their staged acceptance bound is -inf).
+// sub-block (one pixel per lane) and walks the depth-ordered list of the bin
+// tile containing it on its own, with no workgroup barrier. The list is read
+// in chunks of 64 entries: each lane loads one pair word and one 64-byte
+// record with vector loads, tests the record's pixel box against the
+// sub-block, and a ballot plus a masked bit count packs the entries that meet
+// it, in list order, into the wave's private LDS slot. The per-pixel loop then
+// reads those entries as LDS broadcasts. The forward evaluates four entries at
+// a time (their acceptance values and alphas are independent) and applies the
+// sequential transmittance updates with predication rather than branches;
+// each wave stops as soon as all 64 of its pixels are done (ballot).
 //
 // Per pixel and Gaussian the acceptance value q follows the pinned binary32
 // recipe (two fused multiply-adds), so accept/reject decisions are
@@ -31,24 +33,107 @@ namespace ms {
 namespace {
 
 struct Staged {
-  float4 geo;    // cu = X0 - ui, cv = Y0 - vi, uf, vf
-  float4 conic;  // a, b, c, qcut (-inf when the box misses the sub-block)
+  float4 geo;    // gx = X0 - ui, gy = Y0 - vi (exact), uf, vf
+  float4 conic;  // a, b, c, qcut
   float4 app;    // log2 o, z, r, g
-  float4 misc;   // b(lue), rank bits, 0, 0
+  float4 misc;   // b(lue), rank bits, list position + 1 (bits), 0
 };
 
-__device__ inline void stage_record(const uint4* __restrict__ rec, uint32_t r, int X0, int Y0, Staged& s) {
-  const uint4* src = rec + 4 * (int64_t)r;
-  const uint4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
-  const float ui = __uint_as_float(q0.x), vi = __uint_as_float(q0.y);
-  const int bx0 = (int)(q3.y & 0xFFFFu), bx1 = (int)(q3.y >> 16);
-  const int by0 = (int)(q3.z & 0xFFFFu), by1 = (int)(q3.z >> 16);
-  const bool touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
-  s.geo = make_float4((float)X0 - ui, (float)Y0 - vi, __uint_as_float(q0.z), __uint_as_float(q0.w));
-  s.conic = make_float4(__uint_as_float(q1.x), __uint_as_float(q1.y), __uint_as_float(q1.z),
-                        touch ? __uint_as_float(q1.w) : -INFINITY);
-  s.app = make_float4(__uint_as_float(q2.x), __uint_as_float(q2.y), __uint_as_float(q2.z), __uint_as_float(q2.w));
-  s.misc = make_float4(__uint_as_float(q3.x), __uint_as_float(r), 0.f, 0.f);
+// An entry that accepts no pixel, with finite fields (pads a packed chunk to
+// a multiple of the evaluation group).
+__device__ inline Staged inert_entry() {
+  Staged s;
+  s.geo = make_float4(0.f, 0.f, 0.f, 0.f);
+  s.conic = make_float4(0.f, 0.f, 0.f, -INFINITY);
+  s.app = make_float4(0.f, 0.f, 0.f, 0.f);
+  s.misc = make_float4(0.f, 0.f, 0.f, 0.f);
+  return s;
+}
+
+#ifndef MS_STAGE_CPOL
+#define MS_STAGE_CPOL -1
+#endif
+
+// Packs the bin-list entries at list positions [lo, lo + n) (n <= 64) whose
+// pixel box meets the 8x8 sub-block at (X0, Y0) into dst[0 ..), in list
+// order, and returns how many there are (wave-uniform). Lane j reads pair
+// word j (coalesced); the records are then read four lanes per 64-byte
+// record, so each load instruction covers 16 whole records rather than 64
+// scattered 16-byte pieces. The quad's last lane holds the record's pixel
+// box; its decision selects the quad, and a ballot plus a masked bit count
+// gives each packed record its slot.
+__device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
+                                  uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
+                                  Staged* __restrict__ dst) {
+  const uint32_t rank = lane < n ? (pval[start + lo + (uint32_t)lane] & rank_mask) : 0u;
+  const int part = lane & 3, sub = lane >> 2;
+  uint4 v[4];
+  uint32_t rk[4];
+#if MS_STAGE_CPOL >= 0
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)rec, (short)0, 0x7FFFFFFF, 0x00020000);
+#endif
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int e = 16 * k + sub;
+    rk[k] = (uint32_t)__shfl((int)rank, e, 64);
+    v[k] = make_uint4(0u, 0u, 0u, 0u);
+#if MS_STAGE_CPOL >= 0
+    if (e < n) {
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      const v4u t = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(rk[k] * 64u + (uint32_t)part * 16u), 0, MS_STAGE_CPOL);
+      v[k] = make_uint4(t.x, t.y, t.z, t.w);
+    }
+#else
+    if (e < n) v[k] = rec[4 * (int64_t)rk[k] + part];
+#endif
+  }
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int e = 16 * k + sub;
+    bool touch = false;
+    if (part == 3 && e < n) {
+      const int bx0 = (int)(v[k].y & 0xFFFFu), bx1 = (int)(v[k].y >> 16);
+      const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
+      touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(touch);
+    if ((m >> (4 * sub + 3)) & 1u) {
+      // packed records before this one: their box lanes lie below this quad
+      const int slot =
+          base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      float4 o = make_float4(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z),
+                             __uint_as_float(v[k].w));
+      if (part == 0) {
+        o.x = (float)X0 - o.x;   // exact: both are integers below 2^24
+        o.y = (float)Y0 - o.y;
+      } else if (part == 3) {
+        o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u), 0.f);
+      }
+      reinterpret_cast<float4*>(dst + slot)[part] = o;
+    }
+    base += __builtin_popcountll(m);
+  }
+  return base;
+}
+
+// Packs a chunk of up to WB entries (WB / 64 rounds of stage_chunk) and pads
+// the packed count to a multiple of `group` with inert entries; returns the
+// padded count.
+template <int WB>
+__device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
+                                         uint32_t rank_mask, uint32_t start, uint32_t lo, int nb, int X0, int Y0,
+                                         int lane, Staged* __restrict__ dst, int group, int& packed) {
+  int cnt = 0;
+#pragma unroll
+  for (int h = 0; h < WB; h += 64) {
+    const int n = nb - h;
+    if (n > 0) cnt += stage_chunk(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane, dst + cnt);
+  }
+  const int padded = (cnt + group - 1) / group * group;
+  if (lane < padded - cnt) dst[cnt + lane] = inert_entry();
+  packed = cnt;
+  return padded;
 }
 
 // Pinned acceptance value (binary32; the fused operations are explicit).
@@ -60,19 +145,22 @@ __device__ inline float accept_q(const Staged& s, float xf, float yf, float& dx,
   return __builtin_fmaf(t1, t1, t2 * t2);
 }
 
-__device__ inline bool wave_skips(const Staged& s) {
-  // wave-uniform: all lanes read the same staged value
-  return __builtin_amdgcn_readfirstlane(__float_as_int(s.conic.w)) == (int)0xFF800000u;
-}
-
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int kFwdGroup = 4;   // entries evaluated together in the forward
+#ifndef MS_FWD_WAVES
+#define MS_FWD_WAVES 8
+#endif
+#ifndef MS_BWDM_WAVES
+#define MS_BWDM_WAVES 5
+#endif
+
 template <int TILE, int WB>
-__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
     k_composite_fwd(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
                     const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H, int TX, int BX, int bshift,
                     float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ sil,
@@ -80,7 +168,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   __shared__ Staged stage[NW][WB];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int tile_id = blockIdx.x;
   const int tx = tile_id % TX, ty = tile_id / TX;
   const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
@@ -98,58 +186,62 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   bool done = !inside;
   Staged* my = stage[wave];
   for (uint32_t b0 = start; b0 < end; b0 += WB) {
-    if (!__any(!done)) break;
+    if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
     const int nb = (int)min((uint32_t)WB, end - b0);
     staged += (uint32_t)nb;
     wave_sync();
-    for (int j = lane; j < nb; j += 64) {
-      Staged s;
-      stage_record(rec, pval[b0 + j] & rank_mask, X0, Y0, s);
-      my[j] = s;
-    }
+    int packed;
+    const int cnt = stage_chunk_padded<WB>(rec, pval, rank_mask, start, b0 - start, nb, X0, Y0, lane, my, kFwdGroup,
+                                           packed);
     wave_sync();
-    for (int j = 0; j < nb; j++) {
-      // read only what each step needs: the bound (skip test), then the
-      // geometry, then colour and depth when some lane accepted
-      const float4 cn = my[j].conic;
-      if (__builtin_amdgcn_readfirstlane(__float_as_int(cn.w)) == (int)0xFF800000u) continue;
-      const float4 ge = my[j].geo;
-      const float dx = (xf + ge.x) - ge.z;
-      const float dy = (yf + ge.y) - ge.w;
-      const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
-      const float t2 = cn.z * dy;
-      const float q = __builtin_fmaf(t1, t1, t2 * t2);
-      const bool acc = !done && q <= cn.w;
-      if (__builtin_amdgcn_ballot_w64(acc) == 0) continue;
-      if (acc) {
-        const float4 ap = my[j].app;
-        const float cb = my[j].misc.x;
-        const float at = __builtin_amdgcn_exp2f(ap.x - q);
-        const float alpha = fminf(kAlphaMax, at);
-        const float Tn = T * (1.f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-        } else {
-          const float w = alpha * T;
-          C0 = __builtin_fmaf(w, ap.z, C0);
-          C1 = __builtin_fmaf(w, ap.w, C1);
-          C2 = __builtin_fmaf(w, cb, C2);
-          D = __builtin_fmaf(w, ap.y, D);
-          T = Tn;
-          lastpos = (b0 - start) + (uint32_t)j + 1u;
-          ncomp++;
-        }
+    for (int g = 0; g < cnt; g += kFwdGroup) {
+      // acceptance values and alphas of the group: independent of each other
+      float al[kFwdGroup];
+      bool ac[kFwdGroup];
+#pragma unroll
+      for (int i = 0; i < kFwdGroup; i++) {
+        const float4 ge = my[g + i].geo;
+        const float4 cn = my[g + i].conic;
+        const float lo2 = my[g + i].app.x;
+        const float dx = (xf + ge.x) - ge.z;   // (x - ui) exactly, then - uf
+        const float dy = (yf + ge.y) - ge.w;
+        const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
+        const float t2 = cn.z * dy;
+        const float q = __builtin_fmaf(t1, t1, t2 * t2);
+        ac[i] = q <= cn.w;
+        al[i] = fminf(kAlphaMax, __builtin_amdgcn_exp2f(lo2 - q));
       }
+      // front-to-back updates in list order; colours and depths are finite
+      // (non-finite Gaussians are culled), so a zero weight leaves the sums
+      // unchanged
+#pragma unroll
+      for (int i = 0; i < kFwdGroup; i++) {
+        const float4 ap = my[g + i].app;
+        const float2 mi = make_float2(my[g + i].misc.x, my[g + i].misc.z);
+        const bool a = ac[i] && !done;
+        const float Tn = T * (1.f - al[i]);
+        const bool low = Tn < kTMin;
+        const bool upd = a && !low;
+        const float w = upd ? al[i] * T : 0.f;
+        C0 = __builtin_fmaf(w, ap.z, C0);
+        C1 = __builtin_fmaf(w, ap.w, C1);
+        C2 = __builtin_fmaf(w, mi.x, C2);
+        D = __builtin_fmaf(w, ap.y, D);
+        T = upd ? Tn : T;
+        lastpos = upd ? __float_as_uint(mi.y) : lastpos;
+        ncomp += upd ? 1u : 0u;
+        done = done || (a && low);
+      }
+      if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
     }
-    if (!__any(!done)) break;
   }
   // work counters: one atomic per wave
   uint32_t wsum = ncomp;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += (uint32_t)__shfl_xor((int)wsum, off, 64);
   if (lane == 0) {
-    atomicAdd((unsigned long long*)&counters_rw[C_COMPOSITED], (unsigned long long)wsum);
-    atomicAdd((unsigned long long*)&counters_rw[C_STAGED], (unsigned long long)staged);
+    work_add(counters_rw, blockIdx.x * NW + wave, W_COMPOSITED, wsum);
+    work_add(counters_rw, blockIdx.x * NW + wave, W_STAGED, staged);
   }
   if (!inside) return;
   const int64_t P = (int64_t)W * H;
@@ -283,8 +375,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += (uint32_t)__shfl_xor((int)wsum, off, 64);
   if (lane == 0) {
-    atomicAdd((unsigned long long*)&counters_rw[C_COMPOSITED], (unsigned long long)wsum);
-    atomicAdd((unsigned long long*)&counters_rw[C_STAGED], (unsigned long long)staged);
+    work_add(counters_rw, blockIdx.x * (SB * SB) + wave, W_COMPOSITED, wsum);
+    work_add(counters_rw, blockIdx.x * (SB * SB) + wave, W_STAGED, staged);
   }
   if (!inside) return;
   const int64_t P = (int64_t)W * H;
@@ -365,19 +457,15 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     const uint32_t lo = hi > (uint32_t)WB ? hi - WB : 0u;
     const int nb = (int)(hi - lo);
     wave_sync();
-    for (int j = lane; j < nb; j += 64) {
-      Staged s;
-      stage_record(rec, pval[start + lo + j] & rank_mask, X0, Y0, s);
-      my[j] = s;
-    }
+    int packed;
+    stage_chunk_padded<WB>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, 1, packed);
     wave_sync();
-    for (int j = nb - 1; j >= 0; j--) {
+    for (int j = packed - 1; j >= 0; j--) {
       const Staged s = my[j];
-      if (wave_skips(s)) continue;
-      const uint32_t pos = lo + (uint32_t)j;
+      const uint32_t pos1 = __float_as_uint(s.misc.z);   // list position + 1
       float dx, dy, t1, t2;
       const float q = accept_q(s, xf, yf, dx, dy, t1, t2);
-      const bool acc = pos < L && q <= s.conic.w;
+      const bool acc = pos1 <= L && q <= s.conic.w;
       if (!__any(acc)) continue;
       float f[kGradFields];
 #pragma unroll
@@ -526,26 +614,33 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     }
     hi = lo;
   }
-  if (lane == 0) atomicAdd((unsigned long long*)&counters_rw[C_REDUCED], (unsigned long long)reduced);
+  if (lane == 0) work_add(counters_rw, blockIdx.x * (SB * SB) + wave, W_REDUCED, reduced);
 }
 
 // Backward with the per-Gaussian reduction over the wave's 64 pixels done on
-// the matrix cores. For a group of 16 Gaussians with accepting pixels, each
-// pixel lane stores e = dL/dalpha * alpha~ and w = alpha T to LDS. All ten
-// screen-space sums of a Gaussian are linear in the moments
+// the matrix cores. All ten screen-space sums of a Gaussian are linear in the
+// moments
 //   sum_p e_p (1, x, y, x^2, xy, y^2)   and   sum_p w_p (G_r, G_g, G_b, G_D)
-// (x, y pixel coordinates about the sub-block centre), i.e. a (16 Gaussians x
-// 64 pixels) x (64 pixels x 16 columns) product: sixteen
-// v_mfma_f32_16x16x4_f32 steps per product, K = 4 pixels per step. One lane
-// per Gaussian then forms the ten sums from the moments and issues the
-// atomics. This replaces ten full-wave reductions per Gaussian.
+// of e = dL/dalpha * alpha~ and w = alpha T over the pixels p (x, y pixel
+// coordinates about the sub-block centre). For a group of 8 Gaussians, each
+// pixel lane writes its e values to rows 0-7 and its w values to rows 8-15 of
+// a 16 x 64 LDS matrix A; B (64 x 16) holds the six moment monomials in
+// columns 0-5 and the four upstream values in columns 6-9, so the
+// (16 x 64) x (64 x 16) product -- sixteen v_mfma_f32_16x16x4_f32 steps, K = 4
+// pixels per step -- yields both sets of sums. One lane per Gaussian then
+// forms the ten sums and the wave issues them as whole-Gaussian atomics.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kGrp = 16;
-constexpr int kRow = 68;                               // padded row of 64 pixel values (bank spread)
-constexpr int kWaveLds = 2 * kGrp * kRow + kGrp * 8;   // floats per wave: E, W, parameters
+constexpr int kGrp = 8;                        // Gaussians per product
+constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
+constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
+#ifndef MS_BWD_CHUNK
+#define MS_BWD_CHUNK 32
+#endif
+constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per staging round
+constexpr int kBwdStep = 4;                    // entries whose alphas are evaluated together
 
 template <int TILE>
-__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     k_composite_bwd_m(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
                       const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H,
                       int TX, int BX, int bshift, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
@@ -554,6 +649,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   __shared__ __attribute__((aligned(16))) float lds[NW * kWaveLds];
+  __shared__ Staged stage[NW][kBwdChunk];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int tile_id = blockIdx.x;
@@ -562,10 +658,10 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   if (counters_rw[C_OVERFLOW] != 0) return;
-  float* Ew = lds + wave * kWaveLds;   // [16 Gaussians][4 k][16 s] (row stride kRow), pixel p = 4 s + k
-  float* Ww = Ew + kGrp * kRow;
-  float* Pw = Ww + kGrp * kRow;        // [16][8]: rank bits, U, V, a, b, c
-  const int x = X0 + (lane & 7), y = Y0 + (lane >> 3);
+  float* A = lds + wave * kWaveLds;    // [16 rows][4 k][16 s] (row stride kRow), pixel p = 4 s + k
+  Staged* my = stage[wave];
+  const int xl = lane & 7, yl = lane >> 3;
+  const int x = X0 + xl, y = Y0 + yl;
   const bool inside = x < W && y < H;
   const int64_t P = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
@@ -580,14 +676,14 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     Tf = tfinal[pix];
     L = last[pix];
   }
-  // B operands (constant per wave): lane holds B[k = lane / 16][j = lane % 16]
+  // B operand (constant per wave): lane holds B[k = lane / 16][j = lane % 16]
   // of step s, i.e. column j for pixel 4 s + k.
   const int pk = lane >> 4, pj = lane & 15;
-  float Bm[16], Bu[16];
-  Ew[lane * 4 + 0] = G0;
-  Ew[lane * 4 + 1] = G1;
-  Ew[lane * 4 + 2] = G2;
-  Ew[lane * 4 + 3] = GD;
+  float Bv[16];
+  A[lane * 4 + 0] = G0;
+  A[lane * 4 + 1] = G1;
+  A[lane * 4 + 2] = G2;
+  A[lane * 4 + 3] = GD;
   wave_sync();
 #pragma unroll
   for (int st = 0; st < 16; st++) {
@@ -600,52 +696,49 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     m = pj == 3 ? px * px : m;
     m = pj == 4 ? px * py : m;
     m = pj == 5 ? py * py : m;
-    Bm[st] = m;
-    Bu[st] = pj < 4 ? Ew[p * 4 + (pj & 3)] : 0.f;
+    m = (pj >= 6 && pj < 10) ? A[p * 4 + (pj - 6)] : m;
+    Bv[st] = m;
   }
   wave_sync();
   const uint32_t Lmax = __builtin_amdgcn_readfirstlane(wave_max_u32(L));
   const uint32_t start = trange[2 * bin_id];
-  const float xa = (float)x, ya = (float)y;
+  const float xf = (float)xl, yf = (float)yl;
   const float GST = GS * Tf;
   float T = Tf;
   float R = 0.f;
   uint32_t reduced = 0u;
-  int ng = 0;
   const int eaddr = (lane & 3) * 16 + (lane >> 2);
-  auto flush = [&](int count) {
+  // Rows i < count (and 8 + i) of A hold the packed entry my[top - i]; rows
+  // whose entry index reaches `real` are padding (all zero).
+  auto flush = [&](int count, int top, int real) {
     wave_sync();
-    float a1[16], a2[16];
-    const float4* e4 = reinterpret_cast<const float4*>(Ew + pj * kRow + pk * 16);
-    const float4* w4 = reinterpret_cast<const float4*>(Ww + pj * kRow + pk * 16);
+    float a1[16];
+    const float4* e4 = reinterpret_cast<const float4*>(A + pj * kRow + pk * 16);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const float4 ev = e4[q], wv = w4[q];
+      const float4 ev = e4[q];
       a1[4 * q] = ev.x; a1[4 * q + 1] = ev.y; a1[4 * q + 2] = ev.z; a1[4 * q + 3] = ev.w;
-      a2[4 * q] = wv.x; a2[4 * q + 1] = wv.y; a2[4 * q + 2] = wv.z; a2[4 * q + 3] = wv.w;
     }
-    f32x4 d1 = {0.f, 0.f, 0.f, 0.f}, d2 = {0.f, 0.f, 0.f, 0.f};
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int st = 0; st < 16; st++) {
-      d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st], Bm[st], d1, 0, 0, 0);
-      d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st], Bu[st], d2, 0, 0, 0);
-    }
+    for (int st = 0; st < 16; st++) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st], Bv[st], d, 0, 0, 0);
     wave_sync();
+    float* Dm = A;                     // the 16 x 16 product, row-major
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      Ew[(4 * pk + r) * 16 + pj] = d1[r];
-      Ww[(4 * pk + r) * 16 + pj] = d2[r];
-    }
+    for (int r = 0; r < 4; r++) Dm[(4 * pk + r) * 16 + pj] = d[r];
     wave_sync();
     // one lane per Gaussian forms the ten sums; they go back to LDS so that
     // each atomic instruction covers whole Gaussians (10 consecutive floats)
-    float* F = Ww + kGrp * 16;         // [16][10], after the 16x16 D2 block
-    if (lane < count) {
-      const float* m = Ew + lane * 16;
-      const float* u = Ww + lane * 16;
-      const float* pr = Pw + lane * 8;
+    float* F = A + 256;                // [8][10], after the product
+    const int skip = top + 1 > real ? top + 1 - real : 0;   // leading padding rows
+    if (lane >= skip && lane < count) {
+      const Staged& sg = my[top - lane];
+      const float* m = Dm + lane * 16;
+      const float* u = Dm + (kGrp + lane) * 16 + 6;
       const float S1 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
-      const float U = pr[1], V = pr[2], a = pr[3], b = pr[4], c = pr[5];
+      const float U = ((-sg.geo.x) - 3.5f) + sg.geo.z;   // ui - X0 - 3.5 + uf
+      const float V = ((-sg.geo.y) - 3.5f) + sg.geo.w;
+      const float a = sg.conic.x, b = sg.conic.y, c = sg.conic.z;
       const float Edx = Sx - U * S1, Edy = Sy - V * S1;
       const float Edxx = Sxx - 2.f * U * Sx + U * U * S1;
       const float Edxy = Sxy - V * Sx - U * Sy + U * V * S1;
@@ -663,63 +756,62 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
       f[9] = u[3];
     }
     wave_sync();
-    for (int idx = lane; idx < count * kGradFields; idx += 64) {
+    for (int idx = lane + skip * kGradFields; idx < count * kGradFields; idx += 64) {
       const int g = idx / kGradFields, fi = idx - g * kGradFields;
-      unsafeAtomicAdd(g2d + (int64_t)__float_as_uint(Pw[g * 8]) * kGradFields + fi, F[idx]);
+      const float v = F[idx];
+      if (v != 0.f)
+        unsafeAtomicAdd(g2d + (int64_t)__float_as_uint(my[top - g].misc.y) * kGradFields + fi, v);
     }
     wave_sync();
   };
   for (uint32_t hi = Lmax; hi > 0;) {
-    const uint32_t nb = hi < 8u ? hi : 8u;
-    const uint32_t lo = hi - nb;
-    uint32_t rk[8];
+    const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
+    const int nb = (int)(hi - lo);
+    wave_sync();
+    int packed;
+    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, kBwdStep,
+                                                  packed);
+    wave_sync();
+    reduced += (uint32_t)packed;
+    for (int top = cnt - 1; top >= 0; top -= kGrp) {
+      const int gn = top + 1 < kGrp ? top + 1 : kGrp;   // a multiple of kBwdStep
+      for (int i = 0; i < gn; i += kBwdStep) {
+        float at[kBwdStep], alpha[kBwdStep], inv[kBwdStep], gcz[kBwdStep];
+        bool acc[kBwdStep];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const uint32_t k = (uint32_t)i < nb ? start + lo + (uint32_t)i : start + lo;
-      rk[i] = pval[k] & rank_mask;
-    }
-    for (int i = (int)nb - 1; i >= 0; i--) {
-      const RecS s = load_rec_uniform(rec, rk[i]);
-      if (box_misses(s, X0, Y0)) continue;
-      const uint32_t pos = lo + (uint32_t)i;
-      float dx, dy, t1, t2;
-      const float q = accept_q_abs(s, xa, ya, dx, dy, t1, t2);
-      const bool acc = pos < L && q <= s.qcut;
-      if (__builtin_amdgcn_ballot_w64(acc) == 0) continue;
-      reduced++;
-      float e = 0.f, w = 0.f;
-      if (acc) {
-        const float at = __builtin_amdgcn_exp2f(s.lo2 - q);
-        const float alpha = fminf(kAlphaMax, at);
-        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-        const float Tk = T * inv;
-        w = alpha * Tk;
-        const float gcz = __builtin_fmaf(G0, s.cr, __builtin_fmaf(G1, s.cg, __builtin_fmaf(G2, s.cb, GD * s.z)));
-        const float dalpha = __builtin_fmaf(Tk, gcz, -(R - GST) * inv);
-        e = at > kAlphaMax ? 0.f : dalpha * at;
-        R = __builtin_fmaf(gcz, w, R);
-        T = Tk;
+        for (int k = 0; k < kBwdStep; k++) {
+          const Staged& sk = my[top - i - k];
+          const float4 ge = sk.geo, cn = sk.conic, ap = sk.app;
+          const float2 mi = make_float2(sk.misc.x, sk.misc.z);
+          const float dx = (xf + ge.x) - ge.z;
+          const float dy = (yf + ge.y) - ge.w;
+          const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
+          const float t2 = cn.z * dy;
+          const float q = __builtin_fmaf(t1, t1, t2 * t2);
+          acc[k] = __float_as_uint(mi.y) <= L && q <= cn.w;   // list position < last
+          at[k] = __builtin_amdgcn_exp2f(ap.x - q);
+          alpha[k] = fminf(kAlphaMax, at[k]);
+          inv[k] = __builtin_amdgcn_rcpf(1.f - alpha[k]);
+          gcz[k] = __builtin_fmaf(G0, ap.z, __builtin_fmaf(G1, ap.w, __builtin_fmaf(G2, mi.x, GD * ap.y)));
+        }
+        // back-to-front recursion, predicated on acceptance
+#pragma unroll
+        for (int k = 0; k < kBwdStep; k++) {
+          const float Tk = T * inv[k];
+          const float w = alpha[k] * Tk;
+          const float dalpha = __builtin_fmaf(Tk, gcz[k], -(R - GST) * inv[k]);
+          const float e = at[k] > kAlphaMax ? 0.f : dalpha * at[k];
+          A[(i + k) * kRow + eaddr] = acc[k] ? e : 0.f;
+          A[(kGrp + i + k) * kRow + eaddr] = acc[k] ? w : 0.f;
+          R = acc[k] ? __builtin_fmaf(gcz[k], w, R) : R;
+          T = acc[k] ? Tk : T;
+        }
       }
-      Ew[ng * kRow + eaddr] = e;
-      Ww[ng * kRow + eaddr] = w;
-      if (lane == 0) {
-        float* pr = Pw + ng * 8;
-        pr[0] = __uint_as_float(rk[i]);
-        pr[1] = ((s.ui - (float)X0) - 3.5f) + s.uf;
-        pr[2] = ((s.vi - (float)Y0) - 3.5f) + s.vf;
-        pr[3] = s.a;
-        pr[4] = s.b;
-        pr[5] = s.c;
-      }
-      if (++ng == kGrp) {
-        flush(kGrp);
-        ng = 0;
-      }
+      flush(gn, top, packed);
     }
     hi = lo;
   }
-  if (ng > 0) flush(ng);
-  if (lane == 0) atomicAdd((unsigned long long*)&counters_rw[C_REDUCED], (unsigned long long)reduced);
+  if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
 }
 
 template <int TILE>
@@ -807,6 +899,7 @@ hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch
     switch (p.tile) {
       case 8: return bwd_mfma<8>(cam, p, ws, gout, st);
       case 16: return bwd_mfma<16>(cam, p, ws, gout, st);
+      case 32: return bwd_mfma<32>(cam, p, ws, gout, st);
       default: return hipErrorInvalidValue;
     }
   }

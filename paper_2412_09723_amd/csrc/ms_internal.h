@@ -38,13 +38,27 @@ constexpr int kGradFields = 10;   // per-rank screen-space adjoint accumulators
 // 6-8 sum G_rgb alpha T, 9 sum G_depth alpha T.
 
 // Device counters (uint64).
-// C_COMPOSITED: composited (pixel, Gaussian) pairs of the last forward;
-// C_STAGED: list entries staged into LDS, summed over wavefronts.
 // C_ERROR: bounded waits that gave up (0 in every correct run).
-// C_REDUCED: (wavefront, Gaussian) steps of the backward with an accepting lane.
-enum Counter {
-  C_VISIBLE = 0, C_PAIRS = 1, C_OVERFLOW = 2, C_COMPOSITED = 3, C_STAGED = 4, C_ERROR = 5, C_REDUCED = 6, C_COUNT = 8
-};
+enum Counter { C_VISIBLE = 0, C_PAIRS = 1, C_OVERFLOW = 2, C_ERROR = 5, C_COUNT = 8 };
+
+// Work counters, added to once per wavefront by the compositing kernels:
+// W_COMPOSITED: composited (pixel, Gaussian) pairs of the last forward;
+// W_STAGED: bin-list entries walked by the forward, summed over wavefronts;
+// W_REDUCED: packed list entries walked by the backward, summed over wavefronts.
+// Thousands of wavefronts adding to one address serialise at the memory side
+// and back up the vector memory pipeline of every CU, so each counter is
+// spread over kWorkSlots 64-byte lines (slot = wavefront index mod
+// kWorkSlots) and summed when the statistics are read.
+enum WorkCounter { W_COMPOSITED = 0, W_STAGED = 1, W_REDUCED = 2 };
+constexpr int kWorkSlots = 256;
+constexpr int kWorkStride = 8;     // uint64 per slot
+constexpr int kWorkBase = 32;      // uint64 offset of slot 0 from the counters array
+constexpr size_t kCounterBytes = 8 * (size_t)(kWorkBase + kWorkSlots * kWorkStride);
+
+__device__ inline void work_add(uint64_t* counters, int slot, int which, uint64_t v) {
+  atomicAdd((unsigned long long*)&counters[kWorkBase + (slot & (kWorkSlots - 1)) * kWorkStride + which],
+            (unsigned long long)v);
+}
 
 struct Camera {
   int W, H;

@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(256) k_project_fwd(int64_t n, const float* __r
   const double o = opac[i];
   const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
   if (!isfinite(o) || !isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) return;
+  if (!isfinite(colors[i]) || !isfinite(colors[n + i]) || !isfinite(colors[2 * n + i])) return;
   const double qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
   const double n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   if (!(n2 > 0.0) || !isfinite(n2)) return;

@@ -34,7 +34,8 @@ def _dev_grads(g):
     (16, 64, False, 0, None), (8, 32, False, 0, None), (32, 128, False, 0, None), (16, 128, False, 0, None),
     (8, 64, False, 0, None), (32, 32, False, 0, None), (8, 64, True, 0, None), (16, 64, True, 0, None),
     (32, 64, True, 0, None), (16, 64, False, 64, None), (16, 64, True, 128, None), (32, 64, False, 128, None),
-    (8, 32, True, 32, None), (16, 64, False, 128, "mfma"), (8, 64, False, 0, "mfma"), (16, 64, True, 0, "mfma")])
+    (8, 32, True, 32, None), (16, 64, False, 128, "mfma"), (8, 64, False, 0, "mfma"), (16, 64, True, 0, "mfma"),
+    (32, 64, False, 128, "mfma"), (32, 128, False, 0, "mfma")])
 def test_config0_forward_backward(tile, wb, scalar, bin_tile, bwd):
     _log(f"config0 tile={tile} wb={wb} scalar={scalar} bin={bin_tile} bwd={bwd}")
     sc = scenes.config0()
@@ -61,7 +62,8 @@ def test_config0_rotated_pose_and_ragged_image():
     sc.means[0, :20] *= 2.5           # some centres off-screen
     sc.means[2, 20:25] = 0.1          # behind the near plane
     for tile, scalar, bwd in ((8, False, None), (16, False, None), (32, False, None), (8, True, None),
-                              (16, True, None), (32, True, None), (8, False, "mfma"), (16, False, "mfma")):
+                              (16, True, None), (32, True, None), (8, False, "mfma"), (16, False, "mfma"),
+                              (32, False, "mfma")):
         job, imgs = run_job(sc, tile=tile, wave_batch=32, scalar=scalar, bwd=bwd)
         check_structure(job, sc, tile)
         ref = oracle.forward(sc)
@@ -72,7 +74,8 @@ def test_config0_rotated_pose_and_ragged_image():
 
 
 @pytest.mark.parametrize("scalar,tile,bin_tile,bwd", [(False, 16, 0, None), (True, 16, 0, None),
-                                                     (False, 32, 128, None), (False, 16, 128, "mfma")])
+                                                     (False, 32, 128, None), (False, 16, 128, "mfma"),
+                                                     (False, 32, 128, "mfma")])
 def test_config1_full_size(scalar, tile, bin_tile, bwd):
     """1200x680, 1M Gaussians (the benchmark workload)."""
     _log(f"config1 full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")

@@ -329,6 +329,22 @@ def test_empty_and_culled_inputs():
     assert not oracle.project(zeroq)["visible"].any()
 
 
+def test_non_finite_colour_is_culled():
+    """A Gaussian with a non-finite colour is culled like one with a
+    non-finite mean, scale or opacity: the image equals the image without it
+    (brute force agrees)."""
+    intr = scenes.Intrinsics(24, 20, 22.0, 22.0, 12.0, 10.0)
+    sc = scenes.frustum_scene(12, intr, scenes.rng_for(9, 31))
+    sc.colors[:, 3] = [np.inf, 0.5, 0.5]
+    sc.colors[:, 7] = [0.2, np.nan, 0.1]
+    pr = oracle.project(sc)
+    assert not pr["visible"][3] and not pr["visible"][7]
+    keep = np.array([i for i in range(12) if i not in (3, 7)])
+    full, ref = oracle.forward(sc), oracle.forward(sc.subset(keep))
+    assert np.array_equal(full["rgb"], ref["rgb"]) and np.array_equal(full["depth"], ref["depth"])
+    assert np.abs(brute.render(sc)["rgb"] - ref["rgb"]).max() < 1e-12
+
+
 # ------------------------------------------------------------- gradients
 
 def _fd_scene(seed=4):
