@@ -243,7 +243,10 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ pke
 // (epoch:8 | flag:2 | value:54); the region is zeroed at every forward and
 // each pass uses its own epoch, so stale words never match.
 constexpr int kOsThreads = 256;
-constexpr int kOsItems = 32;   // 8192 keys per tile: few tiles, short look-back chains
+#ifndef MS_OS_ITEMS
+#define MS_OS_ITEMS 8
+#endif
+constexpr int kOsItems = MS_OS_ITEMS;   // keys per thread of a tile (the look-back region holds tiles of >= 2048)
 constexpr int kOsTile = kOsThreads * kOsItems;
 constexpr uint64_t kLbAgg = 1, kLbPre = 2;
 constexpr uint64_t kLbValMask = (1ull << 54) - 1;

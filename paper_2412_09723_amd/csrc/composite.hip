@@ -638,6 +638,10 @@ constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
 #endif
 constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per staging round
 constexpr int kBwdStep = 4;                    // entries whose alphas are evaluated together
+#ifndef MS_ACC_ROWS
+#define MS_ACC_ROWS 256
+#endif
+constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
 
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
@@ -656,8 +660,18 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   const int tx = tile_id % TX, ty = tile_id / TX;
   const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
-  if (X0 >= W || Y0 >= H) return;
-  if (counters_rw[C_OVERFLOW] != 0) return;
+  if (counters_rw[C_OVERFLOW] != 0) return;   // uniform over the launch
+  // Sums of the block's waves for the same Gaussian meet in LDS, indexed by
+  // the entry's position in the bin list (the same in every wave of the
+  // block); the block then issues one global atomic per (tile, Gaussian,
+  // field) instead of one per wave. Positions past kAcc go straight to HBM.
+  constexpr int kAcc = NW > 1 ? kAccRows : 0;
+  __shared__ float acc[kAcc > 0 ? kAcc * kGradFields : 1];
+  if (kAcc > 0) {
+    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
+    __syncthreads();
+  }
+  if (X0 < W && Y0 < H) {   // wave-uniform: sub-blocks wholly outside the image do nothing
   float* A = lds + wave * kWaveLds;    // [16 rows][4 k][16 s] (row stride kRow), pixel p = 4 s + k
   Staged* my = stage[wave];
   const int xl = lane & 7, yl = lane >> 3;
@@ -759,8 +773,14 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     for (int idx = lane + skip * kGradFields; idx < count * kGradFields; idx += 64) {
       const int g = idx / kGradFields, fi = idx - g * kGradFields;
       const float v = F[idx];
-      if (v != 0.f)
-        unsafeAtomicAdd(g2d + (int64_t)__float_as_uint(my[top - g].misc.y) * kGradFields + fi, v);
+      if (v != 0.f) {
+        const Staged& sg = my[top - g];
+        const uint32_t pos = __float_as_uint(sg.misc.z) - 1u;   // list position
+        if (kAcc > 0 && pos < (uint32_t)kAcc)
+          atomicAdd(&acc[pos * kGradFields + fi], v);
+        else
+          unsafeAtomicAdd(g2d + (int64_t)__float_as_uint(sg.misc.y) * kGradFields + fi, v);
+      }
     }
     wave_sync();
   };
@@ -812,6 +832,19 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     hi = lo;
   }
   if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
+  }
+  if (kAcc > 0) {
+    __syncthreads();
+    const uint32_t start = trange[2 * bin_id];
+    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) {
+      const float v = acc[i];
+      if (v != 0.f) {   // only rows of list entries some wave packed
+        const int pos = i / kGradFields, fi = i - pos * kGradFields;
+        const uint32_t r = pval[start + (uint32_t)pos] & rank_mask;
+        unsafeAtomicAdd(g2d + (int64_t)r * kGradFields + fi, v);
+      }
+    }
+  }
 }
 
 template <int TILE>
