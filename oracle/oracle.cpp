@@ -720,7 +720,8 @@ int or_forward(int64_t n, const float* means, const float* scales, const float* 
 // Outputs (double): d_means [3][n], d_scales [3][n], d_quats [4][n],
 // d_opac [n], d_colors [3][n], d_viewmat [12] (dL/d[R|t], row-major),
 // d_twist [6] (rho, phi) for the left perturbation exp(xi^) [R|t];
-// gflags [n]: 1 where a Gaussian sits at a margin-flagged decision.
+// gflags [n]: 1 where a Gaussian is composited at a pixel with a
+// margin-flagged decision, or sits at that decision.
 int or_backward(int64_t n, const float* means, const float* scales, const float* quats, const float* opac,
                 const float* colors, const float* viewmat, int W, int H, float fx, float fy, float cx, float cy,
                 float near_z, const float* g_rgb, const float* g_depth, const float* g_sil, double* d_means,
@@ -749,8 +750,16 @@ int or_backward(int64_t n, const float* means, const float* scales, const float*
         const int64_t p = (int64_t)y * W + x;
         double GC[3] = {g_rgb[p], g_rgb[P + p], g_rgb[2 * P + p]};
         accumulate_pixel(pr, hits, r.T, GC, g_depth[p], g_sil[p], accs[tid]);
-        if (r.stop_id >= 0) flagged[tid].push_back(r.stop_id);
-        if (r.clamp_id >= 0) flagged[tid].push_back(r.clamp_id);
+        // A decision inside its margin may go the other way in binary32. A
+        // different stop point changes T_final, and a different clamp state
+        // changes (1 - alpha) by up to 1%, for the whole pixel: so every
+        // Gaussian composited at the pixel is flagged, plus the one at the
+        // decision.
+        if (r.flags) {
+          for (const Hit& h : hits) flagged[tid].push_back(h.id);
+          if (r.stop_id >= 0) flagged[tid].push_back(r.stop_id);
+          if (r.clamp_id >= 0) flagged[tid].push_back(r.clamp_id);
+        }
       }
   }
   std::vector<Acc> acc(n);

@@ -431,6 +431,23 @@ def test_upstream_linearity():
         assert np.abs(r3[k] - ref).max() <= 1e-6 * max(np.abs(ref).max(), 1e-30), k
 
 
+def test_margin_flags_cover_every_gaussian_at_a_flagged_pixel():
+    """A decision inside its margin can change T for the whole pixel, so every
+    Gaussian composited at a flagged pixel is excluded from the elementwise
+    gradient comparison."""
+    sc = scenes.config0()
+    f = oracle.forward(sc)
+    rec = oracle.record(sc)
+    g = oracle.backward(sc, *scenes.upstream_grads(sc.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.5))
+    flags = f["flags"].reshape(-1)
+    assert flags.any()
+    owner = np.repeat(np.arange(sc.intr.pixels), np.diff(rec["offsets"]))
+    ids = rec["ids"][:rec["offsets"][-1]]
+    at_flagged = np.unique(ids[flags[owner] != 0])
+    assert len(at_flagged) and g["gflags"][at_flagged].all()
+    assert g["gflags"].sum() < 0.5 * sc.n
+
+
 def test_culled_gaussians_get_zero_gradient():
     sc = scenes.config0()
     sc.means[2, :10] = -1.0            # behind the camera
