@@ -105,7 +105,7 @@
 extern "C" {
 #endif
 
-#define MS_ABI_VERSION 1
+#define MS_ABI_VERSION 2
 
 typedef enum {
   MS_OK = 0,
@@ -208,12 +208,54 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
 /* Counters of the last forward (and backward) on a workspace, copied to
  * host memory out[7]: visible Gaussians, (Gaussian, bin tile) pairs,
  * pair-capacity overflow flag (0/1), bin tiles, composited (pixel, Gaussian)
- * pairs, list entries staged by the forward wavefronts, (wavefront,
- * Gaussian) steps of the last backward that had an accepting pixel.
+ * pairs, bin-list entries walked by the forward wavefronts, packed
+ * (wavefront, Gaussian) entries walked by the backward(s) since the forward.
  * Arguments as for ms_forward. SYNCHRONISES the stream. Returns MS_ERR_HIP
  * when a bounded device wait gave up. */
 int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
                       const ms_options* opts, int64_t pair_capacity, int64_t out[7], void* stream);
+
+/* ------------------------------------------------------------- batches
+ * Several jobs -- one map, one camera, one set of images each, e.g. the
+ * tracking or mapping iterations of different agents (Sec. 3.6: agents run
+ * their intra-agent processes independently and in parallel; inter-agent
+ * optimisation batches its rendering) -- rendered through ONE launch
+ * sequence: one projection launch over all jobs' Gaussians, one depth sort,
+ * one pair sort, one compositing launch over all jobs' tiles, one backward.
+ * Each job's result is the result of rendering it alone (the per-job
+ * lists, and so every decision, are the same).
+ * Every job shares `opts` (tile, wave_batch, bin_tile, near_z, kernel
+ * flags); intrinsics and sizes may differ. At most MS_MAX_BATCH jobs. */
+#define MS_MAX_BATCH 12
+
+typedef struct {
+  ms_map map;
+  const float* viewmat;     /* device [12] */
+  ms_intrinsics intr;
+  ms_images out;            /* forward: written in full */
+  ms_images grad_out;       /* backward: upstream gradients */
+  ms_grads grads;           /* backward: written as by ms_backward */
+  uint32_t flags;           /* backward: MS_FLAG_POSE_GRAD_ONLY / MS_FLAG_NO_POSE_GRAD for this job
+                               (ORed with those of opts) */
+} ms_job;
+
+/* Workspace bytes for a batch (0 on invalid arguments). */
+size_t ms_batch_workspace_bytes(int32_t njobs, const ms_job* jobs, const ms_options* opts, int64_t pair_capacity);
+
+/* Forward of every job of `jobs` (host array of njobs) into one workspace;
+ * pair_capacity bounds the (Gaussian, bin) pairs of all jobs together.
+ * Errors as ms_forward; an overflow NaN-fills every job's images. */
+int32_t ms_forward_batch(int32_t njobs, const ms_job* jobs, const ms_options* opts, void* workspace, size_t ws_bytes,
+                         int64_t pair_capacity, void* stream);
+
+/* Backward of the last ms_forward_batch on this workspace (same jobs, in
+ * the same order, with the same maps, cameras, options and capacity). */
+int32_t ms_backward_batch(int32_t njobs, const ms_job* jobs, const ms_options* opts, void* workspace,
+                          size_t ws_bytes, int64_t pair_capacity, void* stream);
+
+/* ms_read_stats for a batch workspace (counters summed over the jobs). */
+int32_t ms_batch_read_stats(int32_t njobs, const ms_job* jobs, const ms_options* opts, const void* workspace,
+                            size_t ws_bytes, int64_t pair_capacity, int64_t out[7], void* stream);
 
 /* Device views of the forward state inside a workspace, for inspection and
  * testing (pointers into `workspace`, valid while it is not reused). */

@@ -29,7 +29,9 @@ EXPORTED = [
     "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
     "ms_l1_loss_grad", "ms_pose_adam_step",
     "ms_profiler_create", "ms_profiler_destroy", "ms_profiler_attach", "ms_profiler_read",
+    "ms_batch_workspace_bytes", "ms_forward_batch", "ms_backward_batch", "ms_batch_read_stats",
 ]
+MS_MAX_BATCH = 12
 
 STAGES = ["project", "bin", "composite", "composite_bwd", "project_bwd"]
 
@@ -57,6 +59,11 @@ class MsGrads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
                 ("opacity", ctypes.c_void_p), ("colors", ctypes.c_void_p), ("viewmat", ctypes.c_void_p),
                 ("twist", ctypes.c_void_p)]
+
+
+class MsJob(ctypes.Structure):
+    _fields_ = [("map", MsMap), ("viewmat", ctypes.c_void_p), ("intr", MsIntrinsics), ("out", MsImages),
+                ("grad_out", MsImages), ("grads", MsGrads), ("flags", ctypes.c_uint32)]
 
 
 class MsStateView(ctypes.Structure):
@@ -111,6 +118,15 @@ def load():
     lib.ms_profiler_attach.restype = ctypes.c_int32
     lib.ms_profiler_read.argtypes = [P, P, P]
     lib.ms_profiler_read.restype = ctypes.c_int32
+    I32, I64, SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.ms_batch_workspace_bytes.argtypes = [I32, P, P, I64]
+    lib.ms_batch_workspace_bytes.restype = SZ
+    lib.ms_forward_batch.argtypes = [I32, P, P, P, SZ, I64, P]
+    lib.ms_forward_batch.restype = I32
+    lib.ms_backward_batch.argtypes = [I32, P, P, P, SZ, I64, P]
+    lib.ms_backward_batch.restype = I32
+    lib.ms_batch_read_stats.argtypes = [I32, P, P, P, SZ, I64, P, P]
+    lib.ms_batch_read_stats.restype = I32
     _lib = lib
     return lib
 

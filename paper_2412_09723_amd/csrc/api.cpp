@@ -77,17 +77,6 @@ int32_t check_ws(const void* ws, size_t ws_bytes, const Plan& p) {
   return MS_OK;
 }
 
-Camera make_cam(const ms_intrinsics* intr, const ms_options* opts) {
-  Camera c;
-  c.W = intr->width;
-  c.H = intr->height;
-  c.fx = intr->fx;
-  c.fy = intr->fy;
-  c.cx = intr->cx;
-  c.cy = intr->cy;
-  c.near_z = opts->near_z;
-  return c;
-}
 
 }  // namespace
 
@@ -127,21 +116,57 @@ struct StageTimer {
 
 }  // namespace
 
+bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, int& tiles, int& bins,
+                 int64_t& pixels) {
+  t.njobs = njobs;
+  int64_t g = 0, pix = 0;
+  int tl = 0, bn = 0, blk = 0;
+  for (int j = 0; j < njobs; j++) {
+    JobDesc& J = t.job[j];
+    J.g0 = g;
+    J.block0 = blk;
+    J.blocks = (int)((J.n + 255) / 256);
+    blk += J.blocks;
+    g += (int64_t)J.blocks * 256;
+    J.tx = (J.W + tile - 1) / tile;
+    J.tile0 = tl;
+    J.tiles = J.tx * ((J.H + tile - 1) / tile);
+    tl += J.tiles;
+    J.bx = (J.W + bin - 1) / bin;
+    J.bin0 = bn;
+    J.bins = J.bx * ((J.H + bin - 1) / bin);
+    bn += J.bins;
+    J.pix0 = pix;
+    pix += (int64_t)J.W * J.H;
+  }
+  n_virtual = g;
+  tiles = tl;
+  bins = bn;
+  pixels = pix;
+  return true;
+}
+
 bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p) {
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.job[0].n = n;
+  t.job[0].W = W;
+  t.job[0].H = H;
+  t.njobs = 1;
+  return make_plan(t, tile, bin, cap, p);
+}
+
+bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   std::memset(&p, 0, sizeof(p));
-  p.n = n;
-  p.cap = cap;
   p.tile = tile;
-  p.tx = (W + tile - 1) / tile;
-  p.ty = (H + tile - 1) / tile;
-  p.tiles = p.tx * p.ty;
   p.bin = bin > 0 ? bin : tile;
   p.bshift = 0;
   while ((tile << p.bshift) < p.bin) p.bshift++;
-  p.bx = (W + p.bin - 1) / p.bin;
-  p.by = (H + p.bin - 1) / p.bin;
-  p.bins = p.bx * p.by;
-  p.pixels = (int64_t)W * H;
+  int64_t n = 0;
+  layout_jobs(t.njobs, t, tile, p.bin, n, p.tiles, p.bins, p.pixels);
+  p.njobs = t.njobs;
+  p.n = n;
+  p.cap = cap;
   const int64_t nn = n > 0 ? n : 1;
   const int64_t cc = cap > 0 ? cap : 1;
   p.scan_blocks_n = (int)((nn + 2047) / 2048);
@@ -186,6 +211,7 @@ bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p)
   p.last = take(4 * (size_t)p.pixels);
   p.g2d = take(4 * (size_t)kGradFields * nn);
   p.pose_part = take(8 * 12 * (size_t)p.pose_blocks);
+  p.jobs = take(sizeof(JobTable));
   p.total = o;
   return true;
 }
@@ -219,6 +245,154 @@ size_t ms_workspace_bytes(int64_t n, const ms_intrinsics* intr, const ms_options
   return p.total;
 }
 
+}  // extern "C"
+
+namespace ms {
+namespace {
+
+JobDesc job_from_map(const ms_map& map, const float* viewmat, const ms_intrinsics& intr) {
+  JobDesc J;
+  std::memset(&J, 0, sizeof(J));
+  J.means = map.means;
+  J.scales = map.scales;
+  J.quats = map.quats;
+  J.opacity = map.opacity;
+  J.colors = map.colors;
+  J.viewmat = viewmat;
+  J.n = map.n;
+  J.W = intr.width;
+  J.H = intr.height;
+  J.fx = intr.fx;
+  J.fy = intr.fy;
+  J.cx = intr.cx;
+  J.cy = intr.cy;
+  return J;
+}
+
+// The forward launch sequence over a job table (outputs set in the table).
+int32_t run_forward(JobTable& t, const ms_options* opts, void* workspace, size_t ws_bytes, int64_t cap,
+                    hipStream_t st) {
+  Plan p;
+  make_plan(t, opts->tile, opts->bin_tile, cap, p);
+  int32_t s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  char* ws = (char*)workspace;
+  hipError_t e = launch_set_jobs(t, p, ws, st);
+  if (e == hipSuccess)
+    e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, (int64_t)((p.ctrl_end - p.counters) / 4), st);
+  if (e != hipSuccess) return hip_fail(e, "counters");
+  {
+    StageTimer tm(MS_STAGE_PROJECT, st);
+    e = launch_project_fwd(p, opts->near_z, ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "project");
+  {
+    StageTimer tm(MS_STAGE_BIN, st);
+    e = launch_bin(p, ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "bin");
+  {
+    StageTimer tm(MS_STAGE_COMPOSITE, st);
+    e = launch_composite_fwd(p, opts->wave_batch, opts->flags, ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "composite");
+  return MS_OK;
+}
+
+// The backward launch sequence over a job table (upstream and gradient
+// pointers and per-job flags set in the table).
+int32_t run_backward(JobTable& t, const ms_options* opts, void* workspace, size_t ws_bytes, int64_t cap,
+                     hipStream_t st) {
+  Plan p;
+  make_plan(t, opts->tile, opts->bin_tile, cap, p);
+  int32_t s = check_ws(workspace, ws_bytes, p);
+  if (s != MS_OK) return s;
+  char* ws = (char*)workspace;
+  bool any_pose = false;
+  for (int j = 0; j < t.njobs; j++) any_pose |= !(t.job[j].flags & MS_FLAG_NO_POSE_GRAD);
+  hipError_t e = launch_set_jobs(t, p, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "job table");
+  {
+    StageTimer tm(MS_STAGE_COMPOSITE_BWD, st);
+    e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * p.n, st);
+    if (e == hipSuccess) e = launch_composite_bwd(p, opts->wave_batch, opts->flags, ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "composite backward");
+  {
+    StageTimer tm(MS_STAGE_PROJECT_BWD, st);
+    e = launch_project_bwd(p, any_pose, ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "project backward");
+  return MS_OK;
+}
+
+int32_t check_backward_job(const ms_map& map, const ms_images* grad_out, const ms_grads* grads, uint32_t flags) {
+  if (!grad_out || !grad_out->rgb || !grad_out->depth || !grad_out->silhouette)
+    return fail(MS_ERR_INVALID_ARG, "null upstream gradient image");
+  if (!grads) return fail(MS_ERR_INVALID_ARG, "null gradients");
+  const bool map_g = !(flags & MS_FLAG_POSE_GRAD_ONLY);
+  const bool pose_g = !(flags & MS_FLAG_NO_POSE_GRAD);
+  if (map_g && map.n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->colors))
+    return fail(MS_ERR_INVALID_ARG, "null map gradient array");
+  if (pose_g && (!grads->viewmat || !grads->twist)) return fail(MS_ERR_INVALID_ARG, "null pose gradient");
+  return MS_OK;
+}
+
+void set_backward_job(JobDesc& J, const ms_images& grad_out, const ms_grads& g, uint32_t flags) {
+  J.g_rgb = grad_out.rgb;
+  J.g_depth = grad_out.depth;
+  J.g_sil = grad_out.silhouette;
+  J.gm = g.means;
+  J.gs = g.scales;
+  J.gq = g.quats;
+  J.go = g.opacity;
+  J.gc = g.colors;
+  J.gview = g.viewmat;
+  J.gtwist = g.twist;
+  J.flags = flags & (MS_FLAG_POSE_GRAD_ONLY | MS_FLAG_NO_POSE_GRAD);
+}
+
+constexpr uint32_t kPoseFlags = MS_FLAG_POSE_GRAD_ONLY | MS_FLAG_NO_POSE_GRAD;
+
+// Validates a batch and fills the job table (images of the forward, or
+// upstream and gradients of the backward).
+int32_t batch_table(int32_t njobs, const ms_job* jobs, const ms_options* opts, int64_t cap, bool backward,
+                    JobTable& t) {
+  if (njobs < 1 || njobs > kMaxJobs) return fail(MS_ERR_INVALID_ARG, "njobs %d outside [1, %d]", njobs, kMaxJobs);
+  if (!jobs) return fail(MS_ERR_INVALID_ARG, "null job array");
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = njobs;
+  for (int j = 0; j < njobs; j++) {
+    const ms_job& b = jobs[j];
+    int32_t s = check_map(&b.map);
+    if (s == MS_OK) s = check_common(&b.intr, opts, b.map.n, cap);
+    if (s != MS_OK) return s;
+    if (!b.viewmat) return fail(MS_ERR_INVALID_ARG, "job %d: null viewmat", j);
+    t.job[j] = job_from_map(b.map, b.viewmat, b.intr);
+    if (backward) {
+      const uint32_t flags = b.flags | (opts->flags & kPoseFlags);
+      s = check_backward_job(b.map, &b.grad_out, &b.grads, flags);
+      if (s != MS_OK) return s;
+      set_backward_job(t.job[j], b.grad_out, b.grads, flags);
+    } else {
+      if (!b.out.rgb || !b.out.depth || !b.out.silhouette)
+        return fail(MS_ERR_INVALID_ARG, "job %d: null output image", j);
+      t.job[j].rgb = b.out.rgb;
+      t.job[j].depth = b.out.depth;
+      t.job[j].sil = b.out.silhouette;
+    }
+  }
+  int64_t total = 0;
+  for (int j = 0; j < njobs; j++) total += (jobs[j].map.n + 255) / 256 * 256;
+  if (total > (int64_t)0x7FFFFFFF) return fail(MS_ERR_INVALID_ARG, "batch of %lld Gaussian slots", (long long)total);
+  return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" {
+
 int32_t ms_forward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
                    void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* out, void* stream) {
   int32_t s = check_map(map);
@@ -227,31 +401,14 @@ int32_t ms_forward(const ms_map* map, const float* viewmat, const ms_intrinsics*
   if (s != MS_OK) return s;
   if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
   if (!out || !out->rgb || !out->depth || !out->silhouette) return fail(MS_ERR_INVALID_ARG, "null output image");
-  Plan p;
-  make_plan(map->n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
-  s = check_ws(workspace, ws_bytes, p);
-  if (s != MS_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  const Camera cam = make_cam(intr, opts);
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, (int64_t)((p.ctrl_end - p.counters) / 4), st);
-  if (e != hipSuccess) return hip_fail(e, "counters");
-  {
-    StageTimer t(MS_STAGE_PROJECT, st);
-    e = launch_project_fwd(*map, viewmat, cam, p, ws, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "project");
-  {
-    StageTimer t(MS_STAGE_BIN, st);
-    e = launch_bin(p, ws, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "bin");
-  {
-    StageTimer t(MS_STAGE_COMPOSITE, st);
-    e = launch_composite_fwd(cam, p, opts->wave_batch, opts->flags, ws, *out, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "composite");
-  return MS_OK;
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = 1;
+  t.job[0] = job_from_map(*map, viewmat, *intr);
+  t.job[0].rgb = out->rgb;
+  t.job[0].depth = out->depth;
+  t.job[0].sil = out->silhouette;
+  return run_forward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
 }
 
 int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
@@ -262,48 +419,56 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
   s = check_common(intr, opts, map->n, pair_capacity);
   if (s != MS_OK) return s;
   if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
-  if (!grad_out || !grad_out->rgb || !grad_out->depth || !grad_out->silhouette)
-    return fail(MS_ERR_INVALID_ARG, "null upstream gradient image");
-  if (!grads) return fail(MS_ERR_INVALID_ARG, "null gradients");
-  const bool map_g = !(opts->flags & MS_FLAG_POSE_GRAD_ONLY);
-  const bool pose_g = !(opts->flags & MS_FLAG_NO_POSE_GRAD);
-  if (map_g && map->n > 0 &&
-      (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->colors))
-    return fail(MS_ERR_INVALID_ARG, "null map gradient array");
-  if (pose_g && (!grads->viewmat || !grads->twist)) return fail(MS_ERR_INVALID_ARG, "null pose gradient");
-  Plan p;
-  make_plan(map->n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
-  s = check_ws(workspace, ws_bytes, p);
+  s = check_backward_job(*map, grad_out, grads, opts->flags);
   if (s != MS_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  const Camera cam = make_cam(intr, opts);
-  hipError_t e;
-  {
-    StageTimer t(MS_STAGE_COMPOSITE_BWD, st);
-    e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * map->n, st);
-    if (e == hipSuccess) e = launch_composite_bwd(cam, p, opts->wave_batch, opts->flags, ws, *grad_out, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "composite backward");
-  {
-    StageTimer t(MS_STAGE_PROJECT_BWD, st);
-    e = launch_project_bwd(*map, viewmat, cam, p, ws, *grads, opts->flags, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "project backward");
-  return MS_OK;
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = 1;
+  t.job[0] = job_from_map(*map, viewmat, *intr);
+  set_backward_job(t.job[0], *grad_out, *grads, opts->flags);
+  return run_backward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
 }
 
-int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
-                      const ms_options* opts, int64_t pair_capacity, int64_t out[7], void* stream) {
-  int32_t s = check_common(intr, opts, n, pair_capacity);
-  if (s != MS_OK) return s;
-  if (!out) return fail(MS_ERR_INVALID_ARG, "null output");
+size_t ms_batch_workspace_bytes(int32_t njobs, const ms_job* jobs, const ms_options* opts, int64_t pair_capacity) {
+  if (!opts) return 0;
+  if (njobs < 1 || njobs > kMaxJobs || !jobs) return 0;
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = njobs;
+  for (int j = 0; j < njobs; j++) {
+    if (check_common(&jobs[j].intr, opts, jobs[j].map.n, pair_capacity) != MS_OK) return 0;
+    t.job[j] = job_from_map(jobs[j].map, jobs[j].viewmat, jobs[j].intr);
+  }
   Plan p;
-  make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
-  s = check_ws(workspace, ws_bytes, p);
+  make_plan(t, opts->tile, opts->bin_tile, pair_capacity, p);
+  return p.total;
+}
+
+int32_t ms_forward_batch(int32_t njobs, const ms_job* jobs, const ms_options* opts, void* workspace, size_t ws_bytes,
+                         int64_t pair_capacity, void* stream) {
+  JobTable t;
+  int32_t s = batch_table(njobs, jobs, opts, pair_capacity, false, t);
+  if (s != MS_OK) return s;
+  return run_forward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
+}
+
+int32_t ms_backward_batch(int32_t njobs, const ms_job* jobs, const ms_options* opts, void* workspace,
+                          size_t ws_bytes, int64_t pair_capacity, void* stream) {
+  JobTable t;
+  int32_t s = batch_table(njobs, jobs, opts, pair_capacity, true, t);
+  if (s != MS_OK) return s;
+  return run_backward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace ms {
+namespace {
+
+int32_t read_stats(const void* workspace, size_t ws_bytes, const Plan& p, int64_t out[7], hipStream_t st) {
+  int32_t s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   std::vector<uint64_t> c(kCounterBytes / 8);
-  hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(c.data(), (const char*)workspace + p.counters, kCounterBytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "read stats");
@@ -319,6 +484,38 @@ int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const m
   out[6] = (int64_t)w[W_REDUCED];
   if (c[C_ERROR]) return fail(MS_ERR_HIP, "a bounded device wait gave up %llu time(s)", (unsigned long long)c[C_ERROR]);
   return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" {
+
+int32_t ms_read_stats(const void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,
+                      const ms_options* opts, int64_t pair_capacity, int64_t out[7], void* stream) {
+  int32_t s = check_common(intr, opts, n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!out) return fail(MS_ERR_INVALID_ARG, "null output");
+  Plan p;
+  make_plan(n, intr->width, intr->height, opts->tile, opts->bin_tile, pair_capacity, p);
+  return read_stats(workspace, ws_bytes, p, out, (hipStream_t)stream);
+}
+
+int32_t ms_batch_read_stats(int32_t njobs, const ms_job* jobs, const ms_options* opts, const void* workspace,
+                            size_t ws_bytes, int64_t pair_capacity, int64_t out[7], void* stream) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "null output");
+  if (!opts || njobs < 1 || njobs > kMaxJobs || !jobs) return fail(MS_ERR_INVALID_ARG, "bad batch");
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = njobs;
+  for (int j = 0; j < njobs; j++) {
+    int32_t s = check_common(&jobs[j].intr, opts, jobs[j].map.n, pair_capacity);
+    if (s != MS_OK) return s;
+    t.job[j] = job_from_map(jobs[j].map, jobs[j].viewmat, jobs[j].intr);
+  }
+  Plan p;
+  make_plan(t, opts->tile, opts->bin_tile, pair_capacity, p);
+  return read_stats(workspace, ws_bytes, p, out, (hipStream_t)stream);
 }
 
 int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_intrinsics* intr,

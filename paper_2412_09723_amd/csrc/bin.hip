@@ -173,10 +173,34 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ dst, ui
 // arrays.
 constexpr int kEmitPerThread = 8;
 
+// Bins are global: a record's job (found from its virtual index) supplies the
+// job's first bin and bins per row.
+struct EmitJobs {
+  int njobs;
+  int64_t g0[kMaxJobs];
+  int bin0[kMaxJobs], bx[kMaxJobs];
+};
+
+__device__ inline void emit_bin_base(const EmitJobs& ej, uint32_t vidx, int& bin0, int& bx) {
+  int j = 0;
+  for (int k = 1; k < ej.njobs; k++)
+    if ((int64_t)vidx >= ej.g0[k]) j = k;
+  bin0 = ej.bin0[j];
+  bx = ej.bx[j];
+}
+
 __global__ void __launch_bounds__(256) k_emit(const uint4* __restrict__ rec, const uint64_t* __restrict__ off,
-                                              const uint64_t* __restrict__ counters, int64_t cap, int tile, int tx,
-                                              int rank_bits, uint32_t* __restrict__ pkey,
-                                              uint32_t* __restrict__ pval) {
+                                              const uint64_t* __restrict__ counters, int64_t cap, int tile,
+                                              const JobDesc* __restrict__ jobs, int njobs, int rank_bits,
+                                              uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  __shared__ EmitJobs ej;
+  if (threadIdx.x < (unsigned)njobs) {
+    ej.g0[threadIdx.x] = jobs[threadIdx.x].g0;
+    ej.bin0[threadIdx.x] = jobs[threadIdx.x].bin0;
+    ej.bx[threadIdx.x] = jobs[threadIdx.x].bx;
+  }
+  if (threadIdx.x == 0) ej.njobs = njobs;
+  __syncthreads();
   const int64_t nv = (int64_t)counters[C_VISIBLE];
   const int64_t K = (int64_t)counters[C_PAIRS];
   if (K > cap || nv == 0) return;
@@ -196,6 +220,8 @@ __global__ void __launch_bounds__(256) k_emit(const uint4* __restrict__ rec, con
     int x0 = (int)(b.y & 0xFFFFu) / tile, x1 = (int)(b.y >> 16) / tile;
     int y0 = (int)(b.z & 0xFFFFu) / tile;
     int w = x1 - x0 + 1;
+    int bin0, tx;
+    emit_bin_base(ej, b.w, bin0, tx);
     const int64_t oend = o0 + kEmitPerThread < K ? o0 + kEmitPerThread : K;
     for (int64_t o = o0; o < oend; o++) {
       while (o >= next) {
@@ -207,9 +233,10 @@ __global__ void __launch_bounds__(256) k_emit(const uint4* __restrict__ rec, con
         x1 = (int)(b.y >> 16) / tile;
         y0 = (int)(b.z & 0xFFFFu) / tile;
         w = x1 - x0 + 1;
+        emit_bin_base(ej, b.w, bin0, tx);
       }
       const int pos = (int)(o - base);
-      const uint32_t t = (uint32_t)((y0 + pos / w) * tx + x0 + pos % w);
+      const uint32_t t = (uint32_t)(bin0 + (y0 + pos / w) * tx + x0 + pos % w);
       if (pval) {
         pkey[o] = t;
         pval[o] = (uint32_t)r;
@@ -496,7 +523,8 @@ hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
   if (emit_blocks > 4096) emit_blocks = 4096;
   if (emit_blocks < 1) emit_blocks = 1;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(256), 0, st, at<uint4>(ws, p.rec), off, counters,
-                     p.cap, p.bin, p.bx, p.rank_bits, podd ? pk2 : pk, podd ? pv2 : pv);
+                     p.cap, p.bin, at<JobTable>(ws, p.jobs)->job, p.njobs, p.rank_bits, podd ? pk2 : pk,
+                     podd ? pv2 : pv);
   // 5. stable sort of the pairs by tile id (the bits above the rank when packed)
   const int first = p.packed ? p.rank_bits : 0;
   e = podd ? radix_sort(pk2, pv2, pk, pv, counters, C_PAIRS, p.cap, first, tbits, p, ws, 1, st)

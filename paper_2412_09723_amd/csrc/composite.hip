@@ -162,16 +162,20 @@ constexpr int kFwdGroup = 4;   // entries evaluated together in the forward
 template <int TILE, int WB>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
     k_composite_fwd(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                    const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H, int TX, int BX, int bshift,
-                    float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ sil,
+                    const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift,
                     float* __restrict__ tfinal, uint32_t* __restrict__ last) {
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   __shared__ Staged stage[NW][WB];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int tile_id = blockIdx.x;
-  const int tx = tile_id % TX, ty = tile_id / TX;
-  const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  float* __restrict__ rgb = J.rgb;
+  float* __restrict__ depth = J.depth;
+  float* __restrict__ sil = J.sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;   // whole sub-block outside the image (wave-uniform)
   const int xl = lane & 7, yl = lane >> 3;
@@ -250,8 +254,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
     const float nanv = __builtin_nanf("");
     rgb[pix] = rgb[P + pix] = rgb[2 * P + pix] = nanv;
     depth[pix] = sil[pix] = nanv;
-    tfinal[pix] = 1.f;
-    last[pix] = 0u;
+    tfinal[J.pix0 + pix] = 1.f;
+    last[J.pix0 + pix] = 0u;
     return;
   }
   rgb[pix] = C0;
@@ -259,8 +263,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
   rgb[2 * P + pix] = C2;
   depth[pix] = D;
   sil[pix] = 1.f - T;
-  tfinal[pix] = T;
-  last[pix] = lastpos;
+  tfinal[J.pix0 + pix] = T;
+  last[J.pix0 + pix] = lastpos;
 }
 
 // Scalar-record variant of the forward. The 64-byte record of the Gaussian
@@ -316,16 +320,19 @@ __device__ inline float accept_q_abs(const RecS& s, float xa, float ya, float& d
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     k_composite_fwd_s(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H, int TX,
-                      int BX, int bshift,
-                      float* __restrict__ rgb, float* __restrict__ depth, float* __restrict__ sil,
+                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift,
                       float* __restrict__ tfinal, uint32_t* __restrict__ last) {
   constexpr int SB = TILE / 8;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile_id = blockIdx.x;
-  const int tx = tile_id % TX, ty = tile_id / TX;
-  const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  float* __restrict__ rgb = J.rgb;
+  float* __restrict__ depth = J.depth;
+  float* __restrict__ sil = J.sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   const int x = X0 + (lane & 7), y = Y0 + (lane >> 3);
@@ -385,8 +392,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     const float nanv = __builtin_nanf("");
     rgb[pix] = rgb[P + pix] = rgb[2 * P + pix] = nanv;
     depth[pix] = sil[pix] = nanv;
-    tfinal[pix] = 1.f;
-    last[pix] = 0u;
+    tfinal[J.pix0 + pix] = 1.f;
+    last[J.pix0 + pix] = 0u;
     return;
   }
   rgb[pix] = C0;
@@ -394,8 +401,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   rgb[2 * P + pix] = C2;
   depth[pix] = D;
   sil[pix] = 1.f - T;
-  tfinal[pix] = T;
-  last[pix] = lastpos;
+  tfinal[J.pix0 + pix] = T;
+  last[J.pix0 + pix] = lastpos;
 }
 
 __device__ inline float wave_sum(float v) {
@@ -416,17 +423,20 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 template <int TILE, int WB>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     k_composite_bwd(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                    const uint32_t* __restrict__ trange, const uint64_t* __restrict__ counters, int W, int H, int TX, int BX, int bshift,
-                    const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-                    const float* __restrict__ g_sil, const float* __restrict__ tfinal,
+                    const uint32_t* __restrict__ trange, const uint64_t* __restrict__ counters, const JobDesc* __restrict__ jobs, int njobs, int bshift, const float* __restrict__ tfinal,
                     const uint32_t* __restrict__ last, float* __restrict__ g2d) {
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   __shared__ Staged stage[NW][WB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile_id = blockIdx.x;
-  const int tx = tile_id % TX, ty = tile_id / TX;
-  const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  const float* __restrict__ g_rgb = J.g_rgb;
+  const float* __restrict__ g_depth = J.g_depth;
+  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   if (counters[C_OVERFLOW] != 0) return;
@@ -443,8 +453,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     G2 = g_rgb[2 * P + pix];
     GD = g_depth[pix];
     GS = g_sil[pix];
-    Tf = tfinal[pix];
-    L = last[pix];
+    Tf = tfinal[J.pix0 + pix];
+    L = last[J.pix0 + pix];
   }
   const uint32_t Lmax = wave_max_u32(L);
   const uint32_t start = trange[2 * bin_id];
@@ -525,16 +535,19 @@ __device__ inline float wave_sum_dpp(float v) {
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     k_composite_bwd_s(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H,
-                      int TX, int BX, int bshift, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-                      const float* __restrict__ g_sil, const float* __restrict__ tfinal,
+                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift, const float* __restrict__ tfinal,
                       const uint32_t* __restrict__ last, float* __restrict__ g2d) {
   constexpr int SB = TILE / 8;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile_id = blockIdx.x;
-  const int tx = tile_id % TX, ty = tile_id / TX;
-  const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  const float* __restrict__ g_rgb = J.g_rgb;
+  const float* __restrict__ g_depth = J.g_depth;
+  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   if (counters_rw[C_OVERFLOW] != 0) return;
@@ -550,8 +563,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
     G2 = g_rgb[2 * P + pix];
     GD = g_depth[pix];
     GS = g_sil[pix];
-    Tf = tfinal[pix];
-    L = last[pix];
+    Tf = tfinal[J.pix0 + pix];
+    L = last[J.pix0 + pix];
   }
   const uint32_t Lmax = __builtin_amdgcn_readfirstlane(wave_max_u32(L));
   const uint32_t start = trange[2 * bin_id];
@@ -646,9 +659,7 @@ constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in L
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     k_composite_bwd_m(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, int W, int H,
-                      int TX, int BX, int bshift, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-                      const float* __restrict__ g_sil, const float* __restrict__ tfinal,
+                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift, const float* __restrict__ tfinal,
                       const uint32_t* __restrict__ last, float* __restrict__ g2d) {
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
@@ -656,9 +667,14 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   __shared__ Staged stage[NW][kBwdChunk];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile_id = blockIdx.x;
-  const int tx = tile_id % TX, ty = tile_id / TX;
-  const int bin_id = (tx >> bshift) + (ty >> bshift) * BX;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  const float* __restrict__ g_rgb = J.g_rgb;
+  const float* __restrict__ g_depth = J.g_depth;
+  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (counters_rw[C_OVERFLOW] != 0) return;   // uniform over the launch
   // Sums of the block's waves for the same Gaussian meet in LDS, indexed by
@@ -687,8 +703,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     G2 = g_rgb[2 * P + pix];
     GD = g_depth[pix];
     GS = g_sil[pix];
-    Tf = tfinal[pix];
-    L = last[pix];
+    Tf = tfinal[J.pix0 + pix];
+    L = last[J.pix0 + pix];
   }
   // B operand (constant per wave): lane holds B[k = lane / 16][j = lane % 16]
   // of step s, i.e. column j for pixel 4 s + k.
@@ -848,51 +864,51 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
 }
 
 template <int TILE>
-hipError_t bwd_mfma(const Camera& cam, const Plan& p, char* ws, const ms_images& g, hipStream_t st) {
+hipError_t bwd_mfma(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_bwd_m<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
-                     cam.W, cam.H, p.tx, p.bx, p.bshift, g.rgb, g.depth, g.silhouette, at<float>(ws, p.tfinal),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
   return hipGetLastError();
 }
 
 template <int TILE>
-hipError_t bwd_scalar(const Camera& cam, const Plan& p, char* ws, const ms_images& g, hipStream_t st) {
+hipError_t bwd_scalar(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_bwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
-                     cam.W, cam.H, p.tx, p.bx, p.bshift, g.rgb, g.depth, g.silhouette, at<float>(ws, p.tfinal),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
   return hipGetLastError();
 }
 
 template <int TILE, int WB>
-hipError_t fwd_one(const Camera& cam, const Plan& p, char* ws, const ms_images& out, hipStream_t st) {
+hipError_t fwd_one(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_fwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
-                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters), cam.W,
-                     cam.H, p.tx, p.bx, p.bshift, out.rgb, out.depth, out.silhouette, at<float>(ws, p.tfinal),
+                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last));
   return hipGetLastError();
 }
 
 template <int TILE, int WB>
-hipError_t bwd_one(const Camera& cam, const Plan& p, char* ws, const ms_images& g, hipStream_t st) {
+hipError_t bwd_one(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_bwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
-                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters), cam.W,
-                     cam.H, p.tx, p.bx, p.bshift, g.rgb, g.depth, g.silhouette, at<float>(ws, p.tfinal), at<uint32_t>(ws, p.last),
-                     at<float>(ws, p.g2d));
+                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
+                     at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
   return hipGetLastError();
 }
 
 template <int TILE>
-hipError_t fwd_scalar(const Camera& cam, const Plan& p, char* ws, const ms_images& out, hipStream_t st) {
+hipError_t fwd_scalar(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_fwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
-                     cam.W, cam.H, p.tx, p.bx, p.bshift, out.rgb, out.depth, out.silhouette, at<float>(ws, p.tfinal),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last));
   return hipGetLastError();
 }
@@ -913,38 +929,38 @@ hipError_t fwd_scalar(const Camera& cam, const Plan& p, char* ws, const ms_image
     default: return hipErrorInvalidValue;                                               \
   }
 
-hipError_t launch_composite_fwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
-                                const ms_images& out, hipStream_t st) {
+hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st) {
+  if (p.tiles == 0) return hipSuccess;
   if (flags & MS_FLAG_SCALAR_FWD) {
     switch (p.tile) {
-      case 8: return fwd_scalar<8>(cam, p, ws, out, st);
-      case 16: return fwd_scalar<16>(cam, p, ws, out, st);
-      case 32: return fwd_scalar<32>(cam, p, ws, out, st);
+      case 8: return fwd_scalar<8>(p, ws, st);
+      case 16: return fwd_scalar<16>(p, ws, st);
+      case 32: return fwd_scalar<32>(p, ws, st);
       default: return hipErrorInvalidValue;
     }
   }
-  MS_DISPATCH(fwd_one, cam, p, ws, out, st)
+  MS_DISPATCH(fwd_one, p, ws, st)
 }
 
-hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
-                                const ms_images& gout, hipStream_t st) {
+hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st) {
+  if (p.tiles == 0) return hipSuccess;
   if (flags & MS_FLAG_MFMA_BWD) {
     switch (p.tile) {
-      case 8: return bwd_mfma<8>(cam, p, ws, gout, st);
-      case 16: return bwd_mfma<16>(cam, p, ws, gout, st);
-      case 32: return bwd_mfma<32>(cam, p, ws, gout, st);
+      case 8: return bwd_mfma<8>(p, ws, st);
+      case 16: return bwd_mfma<16>(p, ws, st);
+      case 32: return bwd_mfma<32>(p, ws, st);
       default: return hipErrorInvalidValue;
     }
   }
   if (flags & MS_FLAG_SCALAR_BWD) {
     switch (p.tile) {
-      case 8: return bwd_scalar<8>(cam, p, ws, gout, st);
-      case 16: return bwd_scalar<16>(cam, p, ws, gout, st);
-      case 32: return bwd_scalar<32>(cam, p, ws, gout, st);
+      case 8: return bwd_scalar<8>(p, ws, st);
+      case 16: return bwd_scalar<16>(p, ws, st);
+      case 32: return bwd_scalar<32>(p, ws, st);
       default: return hipErrorInvalidValue;
     }
   }
-  MS_DISPATCH(bwd_one, cam, p, ws, gout, st)
+  MS_DISPATCH(bwd_one, p, ws, st)
 }
 
 }  // namespace ms

@@ -60,18 +60,58 @@ __device__ inline void work_add(uint64_t* counters, int slot, int which, uint64_
             (unsigned long long)v);
 }
 
-struct Camera {
+// ------------------------------------------------------------------ batches
+// A batch renders several jobs (a map, a camera, its images) through one
+// launch sequence. Job j's Gaussians take the virtual indices [g0, g0 + n)
+// (g0 a multiple of 256, so each projection block belongs to one job), its
+// compositing tiles the global tile ids [tile0, tile0 + tiles), its bins
+// [bin0, bin0 + bins) and its pixels [pix0, pix0 + W*H) of the per-pixel
+// arrays. The depth sort and the pair sort run once over all jobs: restricted
+// to one job's Gaussians, the global (depth, index) order is that job's own
+// order, and every bin belongs to one job. A single render is a batch of one.
+constexpr int kMaxJobs = 12;
+struct JobDesc {
+  const float *means, *scales, *quats, *opacity, *colors;   // map, SoA [k][n]
+  const float* viewmat;                                      // [12]
+  float *rgb, *depth, *sil;                                  // forward outputs
+  const float *g_rgb, *g_depth, *g_sil;                      // backward upstream
+  float *gm, *gs, *gq, *go, *gc, *gview, *gtwist;            // backward outputs
+  int64_t n, g0, pix0;
   int W, H;
   float fx, fy, cx, cy;
-  float near_z;
+  int tile0, tiles, tx;      // compositing tiles
+  int bin0, bins, bx;        // bins
+  int block0, blocks;        // projection blocks of 256 Gaussians
+  uint32_t flags;            // MS_FLAG_POSE_GRAD_ONLY / MS_FLAG_NO_POSE_GRAD for this job
 };
+struct JobTable {
+  int njobs, pad;
+  JobDesc job[kMaxJobs];
+};
+
+// Job owning global tile `t` (tile ranges ascend with the job index).
+__device__ inline int job_of_tile(const JobDesc* __restrict__ jobs, int njobs, int t) {
+  int j = 0;
+  for (int k = 1; k < njobs; k++)
+    if (t >= jobs[k].tile0) j = k;
+  return j;
+}
+
+// Job owning projection block `b`.
+__device__ inline int job_of_block(const JobDesc* __restrict__ jobs, int njobs, int b) {
+  int j = 0;
+  for (int k = 1; k < njobs; k++)
+    if (b >= jobs[k].block0) j = k;
+  return j;
+}
 
 // ------------------------------------------------------------ workspace plan
 struct Plan {
-  int64_t n, cap;
-  int tile, tx, ty, tiles;          // compositing tiles
-  int bin, bx, by, bins, bshift;    // binning tiles: bin = tile << bshift
-  int64_t pixels;
+  int64_t n, cap;                   // n: virtual Gaussian slots (all jobs, padded)
+  int njobs;
+  int tile, tiles;                  // compositing tile edge, tiles of all jobs
+  int bin, bins, bshift;            // binning tiles: bin = tile << bshift; bins of all jobs
+  int64_t pixels;                   // pixels of all jobs
   int scan_blocks_n;     // blocks of the length-n scans
   int pose_blocks;
   int rank_bits;         // bits of a depth rank (n - 1)
@@ -80,11 +120,18 @@ struct Plan {
   // control region (zeroed by one fill at every forward): counters, sort
   // tickets, digit histograms, look-back words
   size_t counters, tickets, digit_hist, lookback, ctrl_end;
+  size_t jobs;           // device JobTable
   size_t key, vis_pos, ntiles, rec_i, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part,
       pkey, pval, pkey2, pval2, trange, tfinal, last, g2d, pose_part;
   size_t total;
 };
 
+// Per-job layout (offsets of every job's slots) for options `tile`, `bin`.
+bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, int& tiles, int& bins,
+                 int64_t& pixels);
+// Workspace plan of a batch; lays the jobs out in `t` (their slot offsets).
+bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p);
+// Plan of a single render (a batch of one job of n Gaussians at W x H).
 bool make_plan(int64_t n, int W, int H, int tile, int bin, int64_t cap, Plan& p);
 
 // Mask extracting the depth rank from a sorted pair word.
@@ -100,16 +147,14 @@ inline int tile_bits(int tiles) {
 }
 
 // ---------------------------------------------------------------- launchers
-// Every launcher enqueues on `st` and returns the launch status.
-hipError_t launch_project_fwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p,
-                              char* ws, hipStream_t st);
+// Every launcher enqueues on `st` and returns the launch status. The job
+// table lives in the workspace (written by launch_set_jobs).
+hipError_t launch_set_jobs(const JobTable& t, const Plan& p, char* ws, hipStream_t st);
+hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st);
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st);
-hipError_t launch_composite_fwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
-                                const ms_images& out, hipStream_t st);
-hipError_t launch_composite_bwd(const Camera& cam, const Plan& p, int wave_batch, uint32_t flags, char* ws,
-                                const ms_images& gout, hipStream_t st);
-hipError_t launch_project_bwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p, char* ws,
-                              const ms_grads& g, uint32_t flags, hipStream_t st);
+hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);
+hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);
+hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, int64_t count, float scale,
                           float* loss, hipStream_t st);

@@ -52,34 +52,43 @@ __device__ inline void load_pose(const float* vm, Pose& P) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_project_fwd(int64_t n, const float* __restrict__ means,
-                                                     const float* __restrict__ scales,
-                                                     const float* __restrict__ quats,
-                                                     const float* __restrict__ opac,
-                                                     const float* __restrict__ colors,
-                                                     const float* __restrict__ viewmat, Camera cam, int tile,
-                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ vis,
-                                                     uint32_t* __restrict__ ntiles, int32_t* __restrict__ rank_of,
-                                                     uint4* __restrict__ rec_i) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  Pose P;
-  load_pose(viewmat, P);
+// One block of 256 virtual slots belongs to one job; slots past the job's n
+// are padding and stay invisible.
+__global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__ jobs, int njobs, float near_z,
+                                                     int tile, uint32_t* __restrict__ key,
+                                                     uint32_t* __restrict__ vis, uint32_t* __restrict__ ntiles,
+                                                     int32_t* __restrict__ rank_of, uint4* __restrict__ rec_i) {
+  const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
+  const int64_t li = (int64_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x;   // index within the job
+  const int64_t i = J.g0 + li;                                                     // virtual index
   key[i] = 0xFFFFFFFFu;
   vis[i] = 0u;
   ntiles[i] = 0u;
   rank_of[i] = -1;
-  const double m0 = means[i], m1 = means[n + i], m2 = means[2 * n + i];
+  if (li >= J.n) return;
+  const int64_t n = J.n;
+  const float* __restrict__ means = J.means;
+  const float* __restrict__ scales = J.scales;
+  const float* __restrict__ quats = J.quats;
+  const float* __restrict__ opac = J.opacity;
+  const float* __restrict__ colors = J.colors;
+  struct {
+    int W, H;
+    float fx, fy, cx, cy, near_z;
+  } cam = {J.W, J.H, J.fx, J.fy, J.cx, J.cy, near_z};
+  Pose P;
+  load_pose(J.viewmat, P);
+  const double m0 = means[li], m1 = means[n + li], m2 = means[2 * n + li];
   double p[3];
 #pragma unroll
   for (int r = 0; r < 3; r++) p[r] = ((P.R[r][0] * m0 + P.R[r][1] * m1) + P.R[r][2] * m2) + P.t[r];
   if (!(p[2] > (double)cam.near_z)) return;
   if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) return;
-  const double o = opac[i];
-  const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+  const double o = opac[li];
+  const double s[3] = {scales[li], scales[n + li], scales[2 * n + li]};
   if (!isfinite(o) || !isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) return;
-  if (!isfinite(colors[i]) || !isfinite(colors[n + i]) || !isfinite(colors[2 * n + i])) return;
-  const double qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
+  if (!isfinite(colors[li]) || !isfinite(colors[n + li]) || !isfinite(colors[2 * n + li])) return;
+  const double qw = quats[li], qx = quats[n + li], qy = quats[2 * n + li], qz = quats[3 * n + li];
   const double n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   if (!(n2 > 0.0) || !isfinite(n2)) return;
   const double rn = 1.0 / sqrt(n2);
@@ -157,9 +166,9 @@ __global__ void __launch_bounds__(256) k_project_fwd(int64_t n, const float* __r
   r1.w = __float_as_uint((float)qc);
   r2.x = __float_as_uint(log2f((float)o));
   r2.y = zbits;
-  r2.z = __float_as_uint(colors[i]);
-  r2.w = __float_as_uint(colors[n + i]);
-  r3.x = __float_as_uint(colors[2 * n + i]);
+  r2.z = __float_as_uint(colors[li]);
+  r2.w = __float_as_uint(colors[n + li]);
+  r3.x = __float_as_uint(colors[2 * n + li]);
   r3.y = (uint32_t)bx0 | ((uint32_t)bx1 << 16);
   r3.z = (uint32_t)by0 | ((uint32_t)by1 << 16);
   r3.w = (uint32_t)i;
@@ -174,24 +183,32 @@ __global__ void __launch_bounds__(256) k_project_fwd(int64_t n, const float* __r
 
 #pragma clang fp contract(fast)
 
-__global__ void __launch_bounds__(256) k_project_bwd(int64_t n, const float* __restrict__ means,
-                                                     const float* __restrict__ scales,
-                                                     const float* __restrict__ quats,
-                                                     const float* __restrict__ opac,
-                                                     const float* __restrict__ viewmat, Camera cam,
+__global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__ jobs, int njobs,
                                                      const uint32_t* __restrict__ key,
                                                      const int32_t* __restrict__ rank_of,
                                                      const float* __restrict__ g2d,
-                                                     const uint64_t* __restrict__ counters, ms_grads g,
-                                                     uint32_t flags, double* __restrict__ pose_part) {
+                                                     const uint64_t* __restrict__ counters,
+                                                     double* __restrict__ pose_part) {
   __shared__ double red[12][256 / 64];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool map_grads = !(flags & MS_FLAG_POSE_GRAD_ONLY);
-  const bool pose_grads = !(flags & MS_FLAG_NO_POSE_GRAD);
+  const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
+  const int64_t li = (int64_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x;   // index within the job
+  const int64_t i = J.g0 + li;                                                     // virtual index
+  const int64_t n = J.n;
+  const float* __restrict__ means = J.means;
+  const float* __restrict__ scales = J.scales;
+  const float* __restrict__ quats = J.quats;
+  const float* __restrict__ opac = J.opacity;
+  struct {
+    int W, H;
+    float fx, fy;
+  } cam = {J.W, J.H, J.fx, J.fy};
+  const float* viewmat = J.viewmat;
+  const bool map_grads = !(J.flags & MS_FLAG_POSE_GRAD_ONLY);
+  const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool overflow = counters[C_OVERFLOW] != 0;
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
   float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
-  const bool valid = i < n;
+  const bool valid = li < n;
   if (valid && key[i] != 0xFFFFFFFFu) {
     const int r = rank_of[i];
     const float* acc = g2d + (int64_t)r * kGradFields;
@@ -202,10 +219,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(int64_t n, const float* __r
     gc[2] = acc[8];
     Pose P;
     load_pose(viewmat, P);
-    const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
-    const double s[3] = {scales[i], scales[n + i], scales[2 * n + i]};
-    const double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
-    const double o = opac[i];
+    const double mu[3] = {means[li], means[n + li], means[2 * n + li]};
+    const double s[3] = {scales[li], scales[n + li], scales[2 * n + li]};
+    const double q[4] = {quats[li], quats[n + li], quats[2 * n + li], quats[3 * n + li]};
+    const double o = opac[li];
     double p[3];
     for (int a = 0; a < 3; a++) p[a] = P.R[a][0] * mu[0] + P.R[a][1] * mu[1] + P.R[a][2] * mu[2] + P.t[a];
     const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
@@ -328,14 +345,14 @@ __global__ void __launch_bounds__(256) k_project_bwd(int64_t n, const float* __r
   }
   if (valid && map_grads) {
     for (int k = 0; k < 3; k++) {
-      g.means[k * n + i] = gm[k];
-      g.scales[k * n + i] = gs[k];
-      g.colors[k * n + i] = gc[k];
+      J.gm[k * n + li] = gm[k];
+      J.gs[k * n + li] = gs[k];
+      J.gc[k * n + li] = gc[k];
     }
-    for (int k = 0; k < 4; k++) g.quats[k * n + i] = gq[k];
-    g.opacity[i] = go;
+    for (int k = 0; k < 4; k++) J.gq[k * n + li] = gq[k];
+    J.go[li] = go;
   }
-  if (!pose_grads) return;
+  if (!pose_grads) return;   // uniform over the block (one job per block)
   // block reduction of the 12 pose partials: wave shuffle, then LDS
   double v[12];
   for (int a = 0; a < 3; a++) {
@@ -356,12 +373,20 @@ __global__ void __launch_bounds__(256) k_project_bwd(int64_t n, const float* __r
   }
 }
 
-__global__ void __launch_bounds__(256) k_pose_final(const double* __restrict__ part, int nblocks,
-                                                    const float* __restrict__ viewmat,
-                                                    const uint64_t* __restrict__ counters, float* gview,
-                                                    float* gtwist) {
+// One block per job: folds the job's per-block pose partials in a fixed
+// order and writes dL/d[R|t] and the left-twist gradient.
+__global__ void __launch_bounds__(256) k_pose_final(const JobDesc* __restrict__ jobs,
+                                                    const double* __restrict__ part,
+                                                    const uint64_t* __restrict__ counters) {
   __shared__ double red[12][256 / 64];
   __shared__ double tot[12];
+  const JobDesc& J = jobs[blockIdx.x];
+  if (J.flags & MS_FLAG_NO_POSE_GRAD) return;   // uniform over the block
+  const float* viewmat = J.viewmat;
+  float* gview = J.gview;
+  float* gtwist = J.gtwist;
+  const int nblocks = J.n > 0 ? J.blocks : 0;
+  part += (int64_t)J.block0 * 12;
   double acc[12];
   for (int k = 0; k < 12; k++) acc[k] = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
@@ -417,31 +442,27 @@ __global__ void __launch_bounds__(256) k_pose_final(const double* __restrict__ p
 
 }  // namespace
 
-hipError_t launch_project_fwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p, char* ws,
-                              hipStream_t st) {
-  if (map.n == 0) return hipSuccess;
-  const int64_t blocks = (map.n + 255) / 256;
-  hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)blocks), dim3(256), 0, st, map.n, map.means, map.scales,
-                     map.quats, map.opacity, map.colors, viewmat, cam, p.bin, at<uint32_t>(ws, p.key),
+hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st,
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, near_z, p.bin, at<uint32_t>(ws, p.key),
                      at<uint32_t>(ws, p.vis_pos), at<uint32_t>(ws, p.ntiles), at<int32_t>(ws, p.rank_of),
                      at<uint4>(ws, p.rec_i));
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const ms_map& map, const float* viewmat, const Camera& cam, const Plan& p, char* ws,
-                              const ms_grads& g, uint32_t flags, hipStream_t st) {
-  const bool pose = !(flags & MS_FLAG_NO_POSE_GRAD);
-  if (map.n > 0) {
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)p.pose_blocks), dim3(256), 0, st, map.n, map.means,
-                       map.scales, map.quats, map.opacity, viewmat, cam, at<uint32_t>(ws, p.key),
-                       at<int32_t>(ws, p.rank_of), at<float>(ws, p.g2d), at<uint64_t>(ws, p.counters), g, flags,
-                       at<double>(ws, p.pose_part));
+hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_t st) {
+  const JobDesc* jobs = at<JobTable>(ws, p.jobs)->job;
+  if (p.n > 0) {
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st, jobs, p.njobs,
+                       at<uint32_t>(ws, p.key), at<int32_t>(ws, p.rank_of), at<float>(ws, p.g2d),
+                       at<uint64_t>(ws, p.counters), at<double>(ws, p.pose_part));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (pose) {
-    hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(256), 0, st, at<double>(ws, p.pose_part),
-                       map.n > 0 ? p.pose_blocks : 0, viewmat, at<uint64_t>(ws, p.counters), g.viewmat, g.twist);
+  if (any_pose) {
+    hipLaunchKernelGGL(k_pose_final, dim3((unsigned)p.njobs), dim3(256), 0, st, jobs, at<double>(ws, p.pose_part),
+                       at<uint64_t>(ws, p.counters));
     return hipGetLastError();
   }
   return hipSuccess;

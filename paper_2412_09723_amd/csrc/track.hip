@@ -35,6 +35,14 @@ __global__ void __launch_bounds__(kLossThreads) k_l1_grad(const float* __restric
 
 __global__ void k_zero_f32(float* p) { *p = 0.f; }
 
+// Copies a job table (passed by value in the kernel arguments) into the
+// workspace, so that it is stream-ordered with the launches that read it.
+__global__ void __launch_bounds__(256) k_set_jobs(JobTable t, JobTable* __restrict__ dst) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&t);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += blockDim.x) d[i] = src[i];
+}
+
 // Adam on the twist xi = (rho, phi), then V <- exp(-step^) V in binary64.
 // state: m[6], v[6], t.
 __global__ void k_pose_adam(float* __restrict__ viewmat, const float* __restrict__ g, float* __restrict__ state,
@@ -94,6 +102,12 @@ hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, i
   if (blocks > max_blocks) blocks = max_blocks;
   hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, pred, target, grad, count, scale,
                      loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_jobs(const JobTable& t, const Plan& p, char* ws, hipStream_t st) {
+  static_assert(sizeof(JobTable) % 4 == 0, "job table is copied in 32-bit words");
+  hipLaunchKernelGGL(k_set_jobs, dim3(1), dim3(256), 0, st, t, at<JobTable>(ws, p.jobs));
   return hipGetLastError();
 }
 

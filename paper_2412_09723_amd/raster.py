@@ -222,6 +222,107 @@ class Job:
         )
 
 
+class BatchJob:
+    """Several render jobs -- one map, pose and camera each, shapes and sizes
+    free -- rendered through one launch sequence per pass (ms_forward_batch /
+    ms_backward_batch). Every job's result equals rendering it alone. All
+    jobs share `opts`; the pair capacity covers all jobs together."""
+
+    def __init__(self, maps: list, viewmats: list, intrs: list, opts: RenderOptions = RenderOptions(),
+                 workspace: torch.Tensor | None = None):
+        k = len(maps)
+        if not 1 <= k <= _lib.MS_MAX_BATCH or len(viewmats) != k or len(intrs) != k:
+            raise ValueError(f"a batch holds 1..{_lib.MS_MAX_BATCH} jobs with one viewmat and intrinsics each")
+        self.maps, self.viewmats, self.intrs, self.opts = list(maps), list(viewmats), list(intrs), opts
+        self.ns = [_check_map(m) for m in maps]
+        dev = maps[0]["means"].device
+        for m, vm in zip(maps, viewmats):
+            if m["means"].device != dev or vm.shape != (12,) or vm.dtype != torch.float32 or vm.device != dev:
+                raise ValueError("all maps and viewmats must be float32 tensors on one device")
+        self.device = dev
+        b = opts.bin_tile or opts.tile
+        self.cap = opts.pair_capacity if opts.pair_capacity is not None else min(
+            sum(default_capacity(n, i.width, i.height, b) for n, i in zip(self.ns, intrs)), 0xFFFFFFFF)
+        self.c_jobs = (_lib.MsJob * k)()
+        for j, (m, vm, intr) in enumerate(zip(maps, viewmats, intrs)):
+            self.c_jobs[j].map = MsMap(self.ns[j], m["means"].data_ptr(), m["scales"].data_ptr(),
+                                       m["quats"].data_ptr(), m["opacity"].data_ptr(), m["colors"].data_ptr())
+            self.c_jobs[j].viewmat = vm.data_ptr()
+            self.c_jobs[j].intr = intr_struct(intr)
+        self.ws = workspace
+        self._size_workspace()
+
+    def _size_workspace(self):
+        lib = _lib.load()
+        self.ws_bytes = lib.ms_batch_workspace_bytes(len(self.maps), self.c_jobs, ref(opts_struct(self.opts)),
+                                                     self.cap)
+        if self.ws_bytes == 0:
+            check(_lib.MS_ERR_INVALID_ARG)
+        if self.ws is None or self.ws.numel() < self.ws_bytes:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def forward(self, outs: list | None = None) -> list:
+        """Renders every job; returns [(rgb, depth, silhouette)] in job order."""
+        if outs is None:
+            outs = []
+            for intr in self.intrs:
+                H, W = intr.height, intr.width
+                outs.append((torch.empty((3, H, W), dtype=torch.float32, device=self.device),
+                             torch.empty((H, W), dtype=torch.float32, device=self.device),
+                             torch.empty((H, W), dtype=torch.float32, device=self.device)))
+        for j, (rgb, depth, sil) in enumerate(outs):
+            self.c_jobs[j].out = MsImages(rgb.data_ptr(), depth.data_ptr(), sil.data_ptr())
+        lib = _lib.load()
+        check(lib.ms_forward_batch(len(self.maps), self.c_jobs, ref(opts_struct(self.opts)), _ptr(self.ws),
+                                   self.ws_bytes, self.cap, _stream_ptr(self.device)))
+        if self.opts.check:
+            st = self.stats()
+            if st["overflow"]:
+                if not self.opts.grow:
+                    raise _lib.MacsplatError(_lib.MS_ERR_CAPACITY,
+                                             f"{st['pairs']} pairs exceed the capacity {self.cap}")
+                self.cap = int(min(st["pairs"] * 5 // 4 + 4096, 0xFFFFFFFF))
+                self._size_workspace()
+                return self.forward(outs)
+        return outs
+
+    def backward(self, upstream: list, map_grads=True, pose_grads=True, outs: list | None = None) -> list:
+        """Backward of the last forward. upstream: [(g_rgb, g_depth, g_sil)] in
+        job order; map_grads / pose_grads: a bool or one bool per job.
+        Returns one gradient dict per job, as Job.backward."""
+        k = len(self.maps)
+        mg = [map_grads] * k if isinstance(map_grads, bool) else list(map_grads)
+        pg = [pose_grads] * k if isinstance(pose_grads, bool) else list(pose_grads)
+        res = []
+        for j in range(k):
+            g = outs[j] if outs is not None else {}
+            if mg[j] and outs is None:
+                for key in ("means", "scales", "quats", "opacity", "colors"):
+                    g[key] = torch.empty_like(self.maps[j][key])
+            if pg[j] and outs is None:
+                g["viewmat"] = torch.empty(12, dtype=torch.float32, device=self.device)
+                g["twist"] = torch.empty(6, dtype=torch.float32, device=self.device)
+            gr, gd, gs = upstream[j]
+            self.c_jobs[j].grad_out = MsImages(gr.data_ptr(), gd.data_ptr(), gs.data_ptr())
+            self.c_jobs[j].grads = MsGrads(*[g[key].data_ptr() if key in g else 0 for key in
+                                             ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist")])
+            self.c_jobs[j].flags = (0 if mg[j] else _lib.MS_FLAG_POSE_GRAD_ONLY) | \
+                (0 if pg[j] else _lib.MS_FLAG_NO_POSE_GRAD)
+            res.append(g)
+        lib = _lib.load()
+        check(lib.ms_backward_batch(k, self.c_jobs, ref(opts_struct(self.opts)), _ptr(self.ws), self.ws_bytes,
+                                    self.cap, _stream_ptr(self.device)))
+        return res
+
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * 7)()
+        lib = _lib.load()
+        check(lib.ms_batch_read_stats(len(self.maps), self.c_jobs, ref(opts_struct(self.opts)), _ptr(self.ws),
+                                      self.ws_bytes, self.cap, out, _stream_ptr(self.device)))
+        return dict(visible=out[0], pairs=out[1], overflow=bool(out[2]), tiles=out[3], composited=out[4],
+                    staged=out[5], reduced=out[6])
+
+
 class RasterizeRGBD(torch.autograd.Function):
     """Differentiable RGB-D render: (map, viewmat) -> (rgb, depth, silhouette).
 

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.ms_abi_version() == 1
+    assert lib.ms_abi_version() == 2
     for code in range(6):
         assert lib.ms_status_string(code)
     assert lib.ms_status_string(99) == b"unknown status"
@@ -132,3 +132,32 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_batch_rejects_bad_arguments(lib):
+    jobs = (_lib.MsJob * 2)()
+    for j in range(2):
+        jobs[j].map = MsMap(4096, FAKE, FAKE, FAKE, FAKE, FAKE)
+        jobs[j].viewmat = FAKE
+        jobs[j].intr = INTR
+        jobs[j].out = MsImages(FAKE, FAKE, FAKE)
+    assert lib.ms_batch_workspace_bytes(2, jobs, ref(OPTS), 1 << 20) > lib.ms_workspace_bytes(4096, ref(INTR), ref(OPTS), 1 << 20)
+    assert lib.ms_batch_workspace_bytes(0, jobs, ref(OPTS), 1 << 20) == 0
+    assert lib.ms_batch_workspace_bytes(_lib.MS_MAX_BATCH + 1, jobs, ref(OPTS), 1 << 20) == 0
+    fwd = lambda k, js, ws=FAKE, nb=1 << 40: lib.ms_forward_batch(k, js, ref(OPTS), ctypes.c_void_p(ws), nb, 1 << 20, None)
+    assert fwd(0, jobs) == _lib.MS_ERR_INVALID_ARG
+    assert fwd(_lib.MS_MAX_BATCH + 1, jobs) == _lib.MS_ERR_INVALID_ARG
+    assert fwd(2, None) == _lib.MS_ERR_INVALID_ARG
+    assert fwd(2, jobs, nb=1024) == _lib.MS_ERR_WORKSPACE
+    jobs[1].out = MsImages(FAKE, 0, FAKE)
+    assert fwd(2, jobs) == _lib.MS_ERR_INVALID_ARG and b"job 1" in lib.ms_last_error()
+    jobs[1].out = MsImages(FAKE, FAKE, FAKE)
+    jobs[1].viewmat = 0
+    assert fwd(2, jobs) == _lib.MS_ERR_INVALID_ARG
+    jobs[1].viewmat = FAKE
+    jobs[0].intr = MsIntrinsics(0, 10, 1, 1, 0, 0)
+    assert fwd(2, jobs) == _lib.MS_ERR_INVALID_ARG
+    jobs[0].intr = INTR
+    # backward: a job that wants map gradients needs the arrays
+    assert lib.ms_backward_batch(2, jobs, ref(OPTS), ctypes.c_void_p(FAKE), 1 << 40, 1 << 20, None) \
+        == _lib.MS_ERR_INVALID_ARG

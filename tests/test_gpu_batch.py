@@ -1,0 +1,130 @@
+"""Batched rendering (several agents' maps through one launch sequence):
+every job's images equal rendering it alone bit for bit (identical lists and
+per-pixel arithmetic), its gradients equal the lone backward up to the order
+of floating-point atomics, and every job meets the oracle bar."""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2412_09723_amd import raster, scenes
+from tests.gpu_util import check_grads, check_images, to_dev
+from tests.helpers import make_scene
+
+pytestmark = pytest.mark.gpu
+KEYS = ("means", "scales", "quats", "opacity", "colors")
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _mixed_scenes():
+    out = [scenes.config0()]
+    intr = scenes.Intrinsics(37, 23, 30.0, 31.0, 18.3, 11.1)
+    R0 = Rotation.from_euler("xyz", [6, -4, 9], degrees=True).as_matrix()
+    vm = np.concatenate([R0, np.array([[0.04], [-0.03], [0.1]])], axis=1).reshape(12).astype(np.float32)
+    out.append(scenes.frustum_scene(700, intr, scenes.rng_for(9, 77), viewmat=vm))
+    intr2 = scenes.Intrinsics(200, 150, 180.0, 175.0, 99.5, 76.0)
+    R1 = Rotation.from_euler("xyz", [-3, 8, -2], degrees=True).as_matrix()
+    vm2 = np.concatenate([R1, np.array([[-0.1], [0.05], [0.2]])], axis=1).reshape(12).astype(np.float32)
+    out.append(scenes.frustum_scene(6000, intr2, scenes.rng_for(9, 78), viewmat=vm2))
+    empty_intr = scenes.Intrinsics(24, 16, 20.0, 20.0, 12.0, 8.0)
+    out.append(make_scene(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((4, 0)), np.zeros(0), np.zeros((3, 0)),
+                          empty_intr))
+    return out
+
+
+def _upstream(sc, salt):
+    return scenes.upstream_grads(sc.intr, scenes.rng_for(7, salt, salt=2), 1.0, 0.5)
+
+
+def _dev(arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def _compare_grads(gb, ga, keys):
+    """The same terms summed by atomics in another order: compared at the
+    gradient tolerance, 1e-3 elementwise with a floor of 1e-2 of the tensor
+    maximum, and 1e-3 normwise."""
+    for k in keys:
+        a, b = ga[k].cpu().numpy().astype(np.float64), gb[k].cpu().numpy().astype(np.float64)
+        scale = max(np.abs(a).max(), 1e-30)
+        err = np.abs(b - a) / np.maximum(np.abs(a), 1e-2 * scale)
+        assert err.max() <= 1e-3, (k, float(err.max()))
+        assert np.linalg.norm(b - a) <= 1e-3 * max(np.linalg.norm(a), 1e-30), k
+
+
+@pytest.mark.parametrize("tile,bin_tile,bwd", [(16, 0, "mfma"), (8, 32, "lds"), (32, 128, "mfma"),
+                                               (16, 64, "scalar")])
+def test_batch_equals_alone_and_oracle(tile, bin_tile, bwd):
+    _log(f"batch of mixed jobs tile={tile} bin={bin_tile} bwd={bwd}")
+    scs = _mixed_scenes()
+    opts = raster.RenderOptions(tile=tile, bin_tile=bin_tile, bwd_records=bwd, check=True)
+    devs = [to_dev(sc) for sc in scs]
+    batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)
+    outs = batch.forward()
+    ups = [_dev(_upstream(sc, j)) for j, sc in enumerate(scs)]
+    gbs = batch.backward(ups)
+    torch.cuda.synchronize()
+    for j, sc in enumerate(scs):
+        m, vm = devs[j]
+        alone = raster.Job(m, vm, sc.intr, opts)
+        ref_imgs = alone.forward()
+        for x, y in zip(outs[j], ref_imgs):
+            assert torch.equal(x, y), j
+        ga = alone.backward(*ups[j])
+        torch.cuda.synchronize()
+        if sc.n:
+            _compare_grads(gbs[j], ga, KEYS)
+        _compare_grads(gbs[j], ga, ("viewmat", "twist"))
+        if sc.n:
+            check_images(outs[j], oracle.forward(sc))
+            check_grads(gbs[j], oracle.backward(sc, *_upstream(sc, j)))
+        else:
+            assert not any(t.any() for t in outs[j])
+
+
+def test_batch_per_job_gradient_flags():
+    """Tracking (pose-only) and mapping (all gradients) jobs in one batch."""
+    scs = _mixed_scenes()[:3]
+    devs = [to_dev(sc) for sc in scs]
+    opts = raster.RenderOptions(check=True)
+    batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)
+    batch.forward()
+    ups = [_dev(_upstream(sc, j)) for j, sc in enumerate(scs)]
+    gbs = batch.backward(ups, map_grads=[False, True, True], pose_grads=[True, False, True])
+    torch.cuda.synchronize()
+    assert set(gbs[0]) == {"viewmat", "twist"} and "twist" not in gbs[1] and set(gbs[2]) >= set(KEYS) | {"twist"}
+    for j, (m, vm) in enumerate(devs):
+        alone = raster.Job(m, vm, scs[j].intr, opts)
+        alone.forward()
+        ga = alone.backward(*ups[j])
+        _compare_grads(gbs[j], ga, [k for k in gbs[j]])
+
+
+def test_batch_config3_full_size():
+    """Four agents' room maps of 200k, 600k, 1.2M and 2M Gaussians at
+    1200x680 in one batch, against each rendered alone and the oracle on the
+    smallest."""
+    _log("config3 batch: 200k/600k/1.2M/2M at 1200x680")
+    scs = scenes.config3()
+    devs = [to_dev(sc) for sc in scs]
+    opts = raster.RenderOptions(check=True)
+    batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)
+    outs = batch.forward()
+    ups = [_dev(scenes.upstream_grads(sc.intr, scenes.rng_for(3, j, salt=2), 0.5, 0.0)) for j, sc in enumerate(scs)]
+    gbs = batch.backward(ups)
+    torch.cuda.synchronize()
+    _log(f"  batch stats {batch.stats()}")
+    for j, sc in enumerate(scs):
+        m, vm = devs[j]
+        alone = raster.Job(m, vm, sc.intr, opts)
+        for x, y in zip(outs[j], alone.forward()):
+            assert torch.equal(x, y), j
+        ga = alone.backward(*ups[j])
+        torch.cuda.synchronize()
+        _compare_grads(gbs[j], ga, KEYS + ("viewmat", "twist"))
+        del alone, ga
+    check_images(outs[0], oracle.forward(scs[0]))
