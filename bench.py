@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4-agent batched-vs-plain measurement")
+    ap.add_argument("--batch-rounds", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy three times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -119,6 +121,51 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
 
 
+def batch_bench(rounds: int):
+    """Four agents' room maps (200k, 600k, 1.2M, 2M Gaussians, 1200x680
+    each): one forward + backward of every agent per round, rendered as one
+    autotuned batch against four back-to-back plain launches with the best
+    fixed configuration. Returns the JSON object of the comparison."""
+    import numpy as np
+    import torch
+
+    from paper_2412_09723_amd import autotune, raster, scenes
+    scs = scenes.config3()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    maps = [dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity),
+                 colors=t(sc.colors)) for sc in scs]
+    vms = [t(sc.viewmat) for sc in scs]
+    intrs = [sc.intr for sc in scs]
+    ups = [[t(u) for u in scenes.upstream_grads(sc.intr, scenes.rng_for(3, j, salt=2), 0.5, 0.0)]
+           for j, sc in enumerate(scs)]
+    tuner = autotune.Autotuner()
+    plain = tuner.tune_plain(maps, vms, intrs, ups)
+    batched = tuner.tune_batch(maps, vms, intrs, ups)
+
+    def timed(step):
+        step()
+        step.unchecked()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(rounds):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / rounds
+
+    ms_plain = timed(autotune._PlainStep(maps, vms, intrs, ups, plain.options))
+    ms_batch = timed(autotune._BatchStep(maps, vms, intrs, ups, batched.options))
+    px = sum(i.pixels for i in intrs)
+    opt = lambda o: {"tile": o.tile, "wave_batch": o.wave_batch, "bin_tile": o.bin_tile, "bwd": o.bwd_records}
+    return {"workload": "4 agents, room maps of 200k/600k/1.2M/2M Gaussians, 1200x680 each, one forward+backward "
+                        "of every agent per round",
+            "rounds": rounds, "plain_ms_per_round": round(ms_plain, 4), "batched_ms_per_round": round(ms_batch, 4),
+            "plain_Mpix_s": round(px / ms_plain / 1e3, 2), "batched_Mpix_s": round(px / ms_batch / 1e3, 2),
+            "speedup": round(ms_plain / ms_batch, 3), "plain_options": opt(plain.options),
+            "batched_options": opt(batched.options), "autotune_ms": {"plain": plain.table, "batched": batched.table}}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -149,6 +196,7 @@ def main():
                                                                   check=True))
     target = obs_job.forward()
     del obs_job
+    obs_job_state = None
     vm = t(sc.viewmat)
     tracker = Tracker(m, vm, target, sc.intr, opts, lr=1e-3, w_depth=0.5, map_grads=not args.pose_only)
     job = tracker.job
@@ -233,6 +281,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
+    if not args.no_batch:
+        del tracker, job, obs_job_state
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(args.batch_rounds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)

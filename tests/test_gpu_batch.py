@@ -128,3 +128,17 @@ def test_batch_config3_full_size():
         _compare_grads(gbs[j], ga, KEYS + ("viewmat", "twist"))
         del alone, ga
     check_images(outs[0], oracle.forward(scs[0]))
+
+
+def test_autotuner_picks_a_measured_candidate():
+    from paper_2412_09723_amd import autotune
+    scs = _mixed_scenes()[:3]
+    devs = [to_dev(sc) for sc in scs]
+    ups = [_dev(_upstream(sc, j)) for j, sc in enumerate(scs)]
+    tuner = autotune.Autotuner(reps=1)
+    res = tuner.tune_batch([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], ups)
+    assert len(res.table) == 9 and res.ms == min(res.table.values()) or abs(res.ms - min(res.table.values())) < 1e-3
+    assert res.options.tile in autotune.TILES and res.options.wave_batch in autotune.WAVE_BATCHES
+    assert res.options.bin_tile >= res.options.tile
+    again = tuner.tune_batch([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], ups)
+    assert again.options == res.options         # cached

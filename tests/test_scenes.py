@@ -80,3 +80,11 @@ def test_poisson_trace_reproducible():
     assert a == b
     assert 8 * 30 * 2 * 0.7 < len(a) < 8 * 30 * 2 * 1.3
     assert all(a[i][0] <= a[i + 1][0] for i in range(len(a) - 1))
+
+
+def test_autotune_shape_key_buckets_sizes():
+    from paper_2412_09723_amd import autotune, scenes
+    i1, i2 = scenes.CONFIG1_INTR, scenes.CONFIG2_INTR
+    assert autotune.shape_key([1000, 5000], [i1, i2]) == autotune.shape_key([1023, 4097], [i1, i2])
+    assert autotune.shape_key([1000], [i1]) != autotune.shape_key([1000], [i2])
+    assert autotune.shape_key([1000, 5000], [i1, i2]).startswith("2|")
