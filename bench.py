@@ -52,6 +52,13 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-batch", action="store_true", help="skip the 4-agent batched-vs-plain measurement")
     ap.add_argument("--batch-rounds", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the 8-agent serving measurement")
+    ap.add_argument("--serve-duration", type=float, default=10.0,
+                    help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
+    ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
+    ap.add_argument("--serve-sweep-duration", type=float, default=4.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-small-gb", type=float, default=2.0, help="the forced small admission budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy three times (scale for HBM byte counters) and exit")
     return ap.parse_args()
@@ -164,6 +171,68 @@ def batch_bench(rounds: int):
             "plain_Mpix_s": round(px / ms_plain / 1e3, 2), "batched_Mpix_s": round(px / ms_batch / 1e3, 2),
             "speedup": round(ms_plain / ms_batch, 3), "plain_options": opt(plain.options),
             "batched_options": opt(batched.options), "autotune_ms": {"plain": plain.table, "batched": batched.table}}
+
+
+def serve_bench(duration: float, sweep: list, sweep_duration: float, budget_gb: float, small_gb: float):
+    """Eight agents with resident room maps of 100k-3M Gaussians (log-uniform;
+    agents 0-3 at 640x480, 4-7 at 1200x680) issue Poisson streams of jobs at
+    30 jobs/s each; a job is one forward + L1 loss gradient + backward at the
+    next pose of the agent's camera walk, half of them tracking (pose gradient
+    only) and half mapping (all gradients). Served by the continuous-batching
+    loop and by sequential FIFO plain launches; then the loop under a forced
+    small budget, and a rate sweep to saturation. Returns the JSON object."""
+    import torch
+
+    from paper_2412_09723_amd import raster, scenes, serve
+    scs = scenes.config4_agents()
+    agents = serve.make_agents(scs, steps=4096)
+    opts = raster.RenderOptions()
+    n_agents, base = len(agents), 30.0
+
+    batched_ex = serve.GpuExecutor(agents, opts, streams=2)
+    plain_ex = serve.PlainExecutor(agents, opts)
+    batched_ex.warm(8)
+    plain_ex.warm()
+
+    def run(mult, mode, dur, budget_gb_, seed=4):
+        reqs = serve.requests_from_trace(scenes.poisson_trace(n_agents, base * mult, dur, seed=seed))
+        if mode == "batched":
+            done, failed, info = serve.serve(agents, reqs, opts, budget_bytes=int(budget_gb_ * 2**30),
+                                             executor=batched_ex)
+        else:
+            done, failed, info = serve.serve_plain(agents, reqs, opts, budget_bytes=int(budget_gb_ * 2**30),
+                                                   executor=plain_ex)
+        torch.cuda.synchronize()
+        s = serve.summarize(done, info["wall_s"])
+        s.update(offered_jobs_s=round(len(reqs) / dur, 1), failed=len(failed), rounds=info["rounds"],
+                 peak_admitted_GB=round(info["peak_bytes"] / 2**30, 3))
+        print(f"serving x{mult} {mode} budget {budget_gb_} GB: {s}", file=sys.stderr, flush=True)
+        return s
+
+    run(1, "batched", 1.0, budget_gb, seed=99)       # warm-up (allocator pools, first launches)
+    run(1, "plain", 1.0, budget_gb, seed=99)
+    x1 = {"batched": run(1, "batched", duration, budget_gb), "plain": run(1, "plain", duration, budget_gb)}
+    small = run(1, "batched", duration / 2, small_gb)
+    points = []
+    live = {"batched": True, "plain": True}
+    for mult in sweep:
+        pt = {"rate_x": mult}
+        for mode in ("batched", "plain"):
+            if live[mode]:
+                r = run(mult, mode, sweep_duration, budget_gb)
+                pt[mode] = r
+                live[mode] = r["frames_s"] >= 0.9 * r["offered_jobs_s"]
+        points.append(pt)
+        if not any(live.values()):
+            break
+    sizes = [a.n for a in agents]
+    return {"workload": "8 agents, resident room maps of " + "/".join(f"{n / 1e6:.2f}M" for n in sizes)
+                        + " Gaussians, agents 0-3 at 640x480 and 4-7 at 1200x680, Poisson arrivals at 30 jobs/s "
+                        "per agent, 50% tracking (pose gradient) / 50% mapping (all gradients)",
+            "duration_s": duration, "budget_GB": budget_gb, "x1": x1,
+            "p99_plain_over_batched": round(x1["plain"]["p99_ms"] / max(x1["batched"]["p99_ms"], 1e-9), 3),
+            "forced_small_budget": dict(budget_GB=small_gb, **small),
+            "sweep_duration_s": sweep_duration, "sweep": points}
 
 
 def main():
@@ -285,6 +354,11 @@ def main():
         del tracker, job, obs_job_state
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(args.batch_rounds)
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        sweep = [float(x) for x in args.serve_sweep.split(",") if x]
+        out["serving"] = serve_bench(args.serve_duration, sweep, args.serve_sweep_duration, args.serve_budget_gb,
+                                     args.serve_small_gb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -113,3 +113,15 @@ def check_grads(g, ref, tol=1e-3, pose=True, map_grads=True):
             worst[k] = e
             assert e <= tol, (k, e, got, o)
     return worst
+
+
+def check_reordered_grads(gb, ga, keys):
+    """The same gradient terms summed by atomics in another order: compared at
+    the gradient tolerance, 1e-3 elementwise with a floor of 1e-2 of the
+    tensor maximum, and 1e-3 normwise."""
+    for k in keys:
+        a, b = ga[k].cpu().numpy().astype(np.float64), gb[k].cpu().numpy().astype(np.float64)
+        scale = max(np.abs(a).max(initial=0.0), 1e-30)
+        err = np.abs(b - a) / np.maximum(np.abs(a), 1e-2 * scale)
+        assert err.max(initial=0.0) <= 1e-3, (k, float(err.max()))
+        assert np.linalg.norm(b - a) <= 1e-3 * max(np.linalg.norm(a), 1e-30), k

@@ -1,0 +1,128 @@
+"""The serving loop on the device: a request served inside a batched round
+gives the same result as the request run alone (images and loss gradients
+bit for bit, parameter gradients up to the order of floating-point atomics),
+whatever else shares its round; admission under a forced small budget runs
+the rounds within it; invalid jobs fail alone."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2412_09723_amd import raster, scenes, serve
+from tests.gpu_util import check_images, check_reordered_grads
+
+pytestmark = pytest.mark.gpu
+KEYS = ("means", "scales", "quats", "opacity", "colors")
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def agents():
+    # four agents, two at 640x480 and two at 1200x680, maps of about 2k-60k Gaussians
+    scs = serve_scenes()
+    return scs, serve.make_agents(scs, steps=64)
+
+
+def serve_scenes():
+    return scenes.config4_agents(n_agents=4, scale=0.02)
+
+
+def _alone(agent, r, opts):
+    vm = agent.poses[r.step % agent.poses.shape[0]]
+    job = raster.Job(agent.map, vm, agent.intr, dataclasses.replace(opts, check=True))
+    imgs = job.forward()
+    ex = serve.PlainExecutor([agent], opts)
+    ups = ex._loss_grads([dataclasses.replace(r, agent=0)], [imgs], torch.cuda.current_stream())[0]
+    grads = job.backward(*ups, map_grads=r.mapping, pose_grads=True)
+    torch.cuda.synchronize()
+    return imgs, ups, grads
+
+
+def _check_same_as_alone(ags, reqs, done, opts):
+    by_id = {r.rid: r for r in reqs}
+    for d in done:
+        r = by_id[d.rid]
+        imgs, ups, grads = _alone(ags[r.agent], r, opts)
+        got = d.outputs
+        for a, b in zip(got["images"], imgs):
+            assert torch.equal(a, b), (r, "image")
+        for a, b in zip(got["upstream"], ups):
+            assert torch.equal(a, b), (r, "loss gradient")
+        keys = (KEYS if r.mapping else ()) + ("viewmat", "twist")
+        assert set(got["grads"]) == set(keys), (r, sorted(got["grads"]))
+        check_reordered_grads(got["grads"], grads, keys)
+
+
+def test_served_results_equal_alone(agents):
+    scs, ags = agents
+    reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags), 400.0, 0.2, seed=11))
+    _log(f"serving {len(reqs)} requests over {len(ags)} agents (n = {[a.n for a in ags]})")
+    opts = raster.RenderOptions()
+    done, failed, info = serve.serve(ags, reqs, opts, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert not failed and len(done) == len(reqs)
+    s = serve.summarize(done, info["wall_s"])
+    _log(f"  {s}")
+    assert s["mean_batch"] > 1.0                    # some rounds held several jobs
+    mixed = [d for d in done if d.batch > 1]
+    assert mixed
+    _check_same_as_alone(ags, reqs, done, opts)
+    # the smallest agent's first served frame also meets the oracle bar
+    a0 = int(np.argmin([a.n for a in ags]))
+    d0 = next(d for d in sorted(done, key=lambda d: d.rid) if reqs[d.rid].agent == a0)
+    sc = scs[a0]
+    vm = ags[a0].poses[reqs[d0.rid].step % ags[a0].poses.shape[0]].cpu().numpy()
+    check_images(d0.outputs["images"], oracle.forward(scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity,
+                                                                   sc.colors, vm, sc.intr)))
+
+
+def test_plain_baseline_equals_alone(agents):
+    scs, ags = agents
+    reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags), 60.0, 0.2, seed=12))
+    opts = raster.RenderOptions()
+    done, failed, info = serve.serve_plain(ags, reqs, opts, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert not failed and len(done) == len(reqs)
+    assert all(d.batch == 1 for d in done)
+    _check_same_as_alone(ags, reqs, done, opts)
+
+
+def test_forced_small_budget(agents):
+    scs, ags = agents
+    reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags), 150.0, 0.15, seed=13))
+    opts = raster.RenderOptions()
+    ex = serve.GpuExecutor(ags, opts, keep_outputs=True)
+    costs = {r.rid: ex.cost(r) for r in reqs}
+    budget = max(costs.values()) + 1               # every job fits, no two of the largest do
+    sched = serve.Scheduler(8, budget, 2, ex.cost)
+    done, failed, info = serve.Server(ex, sched).run(reqs)
+    torch.cuda.synchronize()
+    assert not failed and len(done) == len(reqs)
+    assert info["peak_bytes"] <= budget
+    rounds = {}
+    for d in done:
+        rounds.setdefault((d.launched, d.finished), []).append(d.rid)
+    for rids in rounds.values():
+        assert sum(costs[i] for i in rids) <= budget
+    _check_same_as_alone(ags, reqs, done[:12], opts)
+
+
+def test_invalid_jobs_fail_alone(agents):
+    scs, ags = agents
+    bad_intr = scenes.Intrinsics(0, 480, 500.0, 500.0, 320.0, 240.0)        # rejected by the library
+    a = ags[0]
+    bad_map = {k: v.double() for k, v in a.map.items()}                     # float64 map: refused at launch
+    ags2 = list(ags) + [serve.Agent(a.map, bad_intr, a.poses, a.target), serve.Agent(bad_map, a.intr, a.poses, a.target)]
+    reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags2), 100.0, 0.2, seed=14))
+    reqs.append(serve.Request(len(reqs), 99, 0.05, 0, False))              # no such agent
+    done, failed, info = serve.serve(ags2, reqs, raster.RenderOptions(), keep_outputs=True)
+    torch.cuda.synchronize()
+    bad = {r.rid for r in reqs if r.agent >= len(ags)}
+    assert {r.rid for r, _ in failed} == bad
+    assert {d.rid for d in done} == {r.rid for r in reqs} - bad
+    _check_same_as_alone(ags, reqs, [d for d in done][:12], raster.RenderOptions())
