@@ -105,7 +105,7 @@
 extern "C" {
 #endif
 
-#define MS_ABI_VERSION 2
+#define MS_ABI_VERSION 3
 
 typedef enum {
   MS_OK = 0,
@@ -258,23 +258,34 @@ int32_t ms_batch_read_stats(int32_t njobs, const ms_job* jobs, const ms_options*
                             size_t ws_bytes, int64_t pair_capacity, int64_t out[7], void* stream);
 
 /* Device views of the forward state inside a workspace, for inspection and
- * testing (pointers into `workspace`, valid while it is not reused). */
+ * testing (pointers into `workspace`, valid while it is not reused).
+ *
+ * Every bin list holds its Gaussians ordered by (depth key, Gaussian index).
+ * Two layouts exist, chosen by the workspace plan:
+ *  list_kind 1 (at most 1024 bins over all jobs): list entries are Gaussian
+ *    indices, `records` holds one record per Gaussian in index order, and
+ *    sorted_index, rank_of and pair_tile are NULL;
+ *  list_kind 0 (more bins): list entries are depth ranks, `records` holds one
+ *    record per visible Gaussian in depth-rank order, sorted_index and
+ *    rank_of give the permutation. */
 typedef struct {
   uint32_t* depth_key;      /* [n] binary32 depth bits, 0xFFFFFFFF when culled */
-  uint32_t* sorted_index;   /* [n] Gaussian index of depth rank r (first n_visible valid) */
-  int32_t* rank_of;         /* [n] depth rank of Gaussian i, -1 when culled */
-  uint32_t* pair_tile;      /* [pair_capacity] tile id of each sorted pair (packed: the pair word) */
-  uint32_t* pair_rank;      /* [pair_capacity] depth rank of each sorted pair (packed: the pair word) */
-  uint32_t* tile_range;     /* [bin tiles][2] start, end into the sorted pairs */
-  float* records;           /* [n][16] per-rank projected record, see ms_record_layout */
+  uint32_t* sorted_index;   /* kind 0: [n] Gaussian index of depth rank r (first n_visible valid) */
+  int32_t* rank_of;         /* kind 0: [n] depth rank of Gaussian i, -1 when culled */
+  uint32_t* pair_tile;      /* kind 0: [pair_capacity] bin id of each sorted pair (packed: the pair word) */
+  uint32_t* pair_rank;      /* [pair_capacity] list entry of each sorted pair (kind 0 packed: the pair word) */
+  uint32_t* tile_range;     /* [bins][2] start, end of each bin's list in pair_rank */
+  float* records;           /* [n][16] records, see ms_record_layout (kind 1: index order; 0: rank order) */
   float* tfinal;            /* [H][W] final transmittance */
-  uint32_t* last;           /* [H][W] last composited position (+1) in the pixel's tile list */
+  uint32_t* last;           /* [H][W] last composited position (+1) in the pixel's bin list */
   uint64_t* counters;       /* [8] visible, pairs, overflow, ... */
-  float* grad2d;            /* [n][10] per-rank screen-space gradient accumulators */
+  float* grad2d;            /* [n][10] screen-space gradient accumulators, one row per list entry value
+                               (kind 1: zero outside a backward pass) */
   int32_t pair_rank_bits;   /* 0: separate arrays; > 0: each pair is one word tile << bits | rank */
+  int32_t list_kind;
 } ms_state_view;
 
-/* Record layout (16 x 32-bit words per visible Gaussian, in depth-rank order):
+/* Record layout (16 x 32-bit words per visible Gaussian):
  * 0 floor(u), 1 floor(v) (integer-valued floats), 2 uf, 3 vf, 4 a, 5 b, 6 c, 7 qcut,
  * 8 log2(opacity), 9 z32, 10-12 colour, 13 xlo | xhi << 16, 14 ylo | yhi << 16,
  * 15 Gaussian index (uint32). */

@@ -69,7 +69,8 @@ class MsJob(ctypes.Structure):
 class MsStateView(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in (
         "depth_key", "sorted_index", "rank_of", "pair_tile", "pair_rank", "tile_range", "records",
-        "tfinal", "last", "counters", "grad2d")] + [("pair_rank_bits", ctypes.c_int32)]
+        "tfinal", "last", "counters", "grad2d")] + [("pair_rank_bits", ctypes.c_int32),
+                                                     ("list_kind", ctypes.c_int32)]
 
 
 _lib = None

@@ -173,7 +173,20 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   p.pose_blocks = (int)((nn + 255) / 256);
   p.rank_bits = 1;
   while (p.rank_bits < 31 && ((int64_t)1 << p.rank_bits) < nn) p.rank_bits++;
-  p.packed = p.rank_bits + tile_bits(p.bins) <= 32;
+  // per-bin path: units of kUnitThreads * R Gaussians, R a power of two in
+  // [8, 64] chosen so that units x bins stays within the scan's bound
+  if (p.bins <= kFastBins) {
+    for (int r = 8; r <= 64; r *= 2) {
+      const int64_t units = (nn + (int64_t)kUnitThreads * r - 1) / ((int64_t)kUnitThreads * r);
+      if (units * p.bins <= kUnitEntries) {
+        p.by_index = true;
+        p.unit_rounds = r;
+        p.units = (int)units;
+        break;
+      }
+    }
+  }
+  p.packed = !p.by_index && p.rank_bits + tile_bits(p.bins) <= 32;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -181,32 +194,38 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
     return r;
   };
   p.counters = take(kCounterBytes);
-  p.tickets = take(4 * 8);                       // 2 sorts x 4 passes
-  p.digit_hist = take(4 * 256 * 8);              // 2 sorts x 4 passes x 256 digits
-  {
+  if (!p.by_index) {
+    p.tickets = take(4 * 8);                       // 2 sorts x 4 passes
+    p.digit_hist = take(4 * 256 * 8);              // 2 sorts x 4 passes x 256 digits
     const int64_t os_tile = 2048;
     const int64_t tiles_v = (nn + os_tile - 1) / os_tile, tiles_p = (cc + os_tile - 1) / os_tile;
     p.lookback = take(8 * 256 * (size_t)(tiles_v > tiles_p ? tiles_v : tiles_p));
   }
+  p.trange = take(8 * (size_t)p.bins);
   p.ctrl_end = o;
   p.key = take(4 * nn);
-  p.vis_pos = take(4 * nn);
-  p.ntiles = take(4 * nn);
   p.rec_i = take(64 * nn);
-  p.rank_of = take(4 * nn);
-  p.ckey = take(4 * nn);
-  p.cval = take(4 * nn);
-  p.ckey2 = take(4 * nn);
-  p.cval2 = take(4 * nn);
-  p.rec = take(64 * nn);
-  p.cnt = take(4 * nn);
-  p.cnt_off = take(8 * nn);
-  p.scan_part = take(8 * (size_t)(p.scan_blocks_n + 1));
+  if (p.by_index) {
+    p.gbin = take(8 * nn);
+    p.ucnt = take(4 * (size_t)p.units * p.bins);
+    p.uvis = take(4 * (size_t)p.units);
+  } else {
+    p.vis_pos = take(4 * nn);
+    p.ntiles = take(4 * nn);
+    p.rank_of = take(4 * nn);
+    p.ckey = take(4 * nn);
+    p.cval = take(4 * nn);
+    p.ckey2 = take(4 * nn);
+    p.cval2 = take(4 * nn);
+    p.rec = take(64 * nn);
+    p.cnt = take(4 * nn);
+    p.cnt_off = take(8 * nn);
+    p.scan_part = take(8 * (size_t)(p.scan_blocks_n + 1));
+  }
   p.pkey = take(4 * cc);
   p.pval = p.packed ? p.pkey : take(4 * cc);
   p.pkey2 = take(4 * cc);
   p.pval2 = p.packed ? p.pkey2 : take(4 * cc);
-  p.trange = take(8 * (size_t)p.bins);
   p.tfinal = take(4 * (size_t)p.pixels);
   p.last = take(4 * (size_t)p.pixels);
   p.g2d = take(4 * (size_t)kGradFields * nn);
@@ -314,7 +333,9 @@ int32_t run_backward(JobTable& t, const ms_options* opts, void* workspace, size_
   if (e != hipSuccess) return hip_fail(e, "job table");
   {
     StageTimer tm(MS_STAGE_COMPOSITE_BWD, st);
-    e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * p.n, st);
+    // per-bin path: the accumulator rows of the visible Gaussians are zeroed
+    // by the projection and again by the projection adjoint after use
+    if (!p.by_index) e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * p.n, st);
     if (e == hipSuccess) e = launch_composite_bwd(p, opts->wave_batch, opts->flags, ws, st);
   }
   if (e != hipSuccess) return hip_fail(e, "composite backward");
@@ -529,12 +550,13 @@ int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_
   if (s != MS_OK) return s;
   char* ws = (char*)workspace;
   v->depth_key = at<uint32_t>(ws, p.key);
-  v->sorted_index = at<uint32_t>(ws, p.cval);
-  v->rank_of = at<int32_t>(ws, p.rank_of);
-  v->pair_tile = at<uint32_t>(ws, p.pkey);
+  v->sorted_index = p.by_index ? nullptr : at<uint32_t>(ws, p.cval);
+  v->rank_of = p.by_index ? nullptr : at<int32_t>(ws, p.rank_of);
+  v->pair_tile = p.by_index ? nullptr : at<uint32_t>(ws, p.pkey);
   v->pair_rank = at<uint32_t>(ws, p.pval);
   v->tile_range = at<uint32_t>(ws, p.trange);
-  v->records = at<float>(ws, p.rec);
+  v->records = at<float>(ws, rec_slots(p));
+  v->list_kind = p.by_index ? 1 : 0;
   v->tfinal = at<float>(ws, p.tfinal);
   v->last = at<uint32_t>(ws, p.last);
   v->counters = at<uint64_t>(ws, p.counters);

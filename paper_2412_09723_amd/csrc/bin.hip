@@ -436,6 +436,552 @@ __global__ void __launch_bounds__(kOsThreads) k_onesweep(const uint32_t* __restr
   }
 }
 
+// ------------------------------------------------------------ per-bin path
+// Used when all jobs together have at most kFastBins bins. A unit is a block
+// of kUnitThreads threads covering kUnitThreads * R consecutive virtual
+// Gaussians: wave w of the unit owns the R * 64 Gaussians starting at
+// unit_base + w * R * 64, in R rounds of 64.
+//   1. k_unit_count: pairs per (unit, bin) and visible Gaussians per unit;
+//   2. k_unit_scan (one block): exclusive offsets of every (unit, bin) in
+//      bin-major order, the bin ranges, the pair total and the capacity
+//      check;
+//   3. k_unit_emit: every pair (depth key, Gaussian index) written into its
+//      bin's segment in Gaussian-index order;
+//   4. k_bin_sort (one block per bin): stable LSD sort of the segment by
+//      depth key, which leaves it ordered by (depth key, index).
+// No step waits on another block, and every loop is bounded by the counts.
+
+__device__ inline void gbin_decode(uint32_t w, int& ntx, int& nty, int& bx) {
+  ntx = (int)(w & 1023u) + 1;
+  nty = (int)((w >> 10) & 1023u) + 1;
+  bx = (int)((w >> 20) & 1023u) + 1;
+}
+
+// Inclusive sum scan over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (VALU only).
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15 -> rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
+// The pairs of one round of 64 Gaussians, listed in (lane, bin) order --
+// Gaussian-index order -- and handed out 64 at a time so that lanes with
+// large footprints do not serialise the wave. `RoundPairs` holds the round's
+// per-lane exclusive pair offsets and footprints in LDS; pair q belongs to
+// the lane with the largest offset <= q (a 6-step binary search).
+struct RoundPairs {
+  uint32_t pre[64];    // exclusive pair offset of each lane
+  uint32_t first[64];  // first bin
+  uint32_t word[64];   // packed footprint (gbin word 1)
+};
+
+// Publishes the footprint g of this lane's Gaussian in the round and returns
+// the round's pair count (uniform).
+__device__ inline uint32_t round_setup(RoundPairs& R, uint2 g, int lane) {
+  uint32_t c = 0;
+  if (g.x != kNoBin) {
+    int ntx, nty, bx;
+    gbin_decode(g.y, ntx, nty, bx);
+    c = (uint32_t)(ntx * nty);
+  }
+  const uint32_t incl = wave_inclusive_scan(c);
+  R.pre[lane] = incl - c;
+  R.first[lane] = g.x;
+  R.word[lane] = g.y;
+  __builtin_amdgcn_wave_barrier();
+  return (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+}
+
+// Rounds are processed in groups of kRoundGroup whose footprints are loaded
+// together, so a wave waits for memory once per group.
+constexpr int kRoundGroup = 8;   // divides every unit_rounds value
+
+__device__ inline void load_group(const uint2* __restrict__ gbin, int64_t i0, int64_t n, int lane,
+                                  uint2 (&g)[kRoundGroup]) {
+#pragma unroll
+  for (int u = 0; u < kRoundGroup; u++) {
+    const int64_t i = i0 + (int64_t)u * 64 + lane;
+    g[u] = i < n ? gbin[i] : make_uint2(kNoBin, 0u);
+  }
+}
+
+// Bin of pair q (< the round's total) and its owning lane: the lane with the
+// largest exclusive offset <= q.
+__device__ inline uint32_t round_pair(const RoundPairs& R, uint32_t q, uint32_t& src) {
+  uint32_t lo = 0;   // lo + step <= 63 at every step, and pre[0] = 0 <= q
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1)
+    if (R.pre[lo + step] <= q) lo += step;
+  src = lo;
+  int ntx, nty, bx;
+  gbin_decode(R.word[lo], ntx, nty, bx);
+  const int j = (int)(q - R.pre[lo]);
+  // j / ntx in binary32: j < 2^20 and the quotient's distance to an integer
+  // is at least 0.5 / ntx, far above the rounding error; one correction step
+  // guards the boundary anyway
+  int y = (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)ntx));
+  int x = j - y * ntx;
+  if (x < 0) {
+    y--;
+    x += ntx;
+  } else if (x >= ntx) {
+    y++;
+    x -= ntx;
+  }
+  return R.first[lo] + (uint32_t)(y * bx + x);
+}
+
+__global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __restrict__ gbin, int64_t n, int rounds,
+                                                             int nbins, uint32_t* __restrict__ ucnt,
+                                                             uint32_t* __restrict__ uvis) {
+  constexpr int NW = kUnitThreads / 64;
+  __shared__ uint32_t h[kFastBins];
+  __shared__ RoundPairs RP[NW];
+  __shared__ uint32_t s_vis;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int b = t; b < nbins; b += kUnitThreads) h[b] = 0u;
+  if (t == 0) s_vis = 0u;
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * kUnitThreads * rounds + (int64_t)wave * 64 * rounds;
+  RoundPairs& R = RP[wave];
+  uint32_t nvis = 0;
+  for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
+    if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
+    uint2 g[kRoundGroup];
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+#pragma unroll
+    for (int u = 0; u < kRoundGroup; u++) {
+      nvis += g[u].x != kNoBin ? 1u : 0u;
+      const uint32_t total = round_setup(R, g[u], lane);
+      for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        if (q < total) {
+          uint32_t src;
+          atomicAdd(&h[round_pair(R, q, src)], 1u);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) nvis += __shfl_xor(nvis, off, 64);
+  if (lane == 0) atomicAdd(&s_vis, nvis);
+  __syncthreads();
+  uint32_t* row = ucnt + (int64_t)blockIdx.x * nbins;
+  for (int b = t; b < nbins; b += kUnitThreads) row[b] = h[b];
+  if (t == 0) uvis[blockIdx.x] = s_vis;
+}
+
+// One block of 1024 threads. ucnt[u][b] (unit-major) becomes the exclusive
+// offset of (unit u, bin b) in the bin-major order of all pairs. Thread
+// (chunk c, bin b) owns bin b over a contiguous chunk of units.
+constexpr int kUScanThreads = 1024;
+
+__global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restrict__ ucnt,
+                                                             const uint32_t* __restrict__ uvis, int units,
+                                                             int nbins, int64_t cap, uint64_t* __restrict__ counters,
+                                                             uint32_t* __restrict__ trange) {
+  __shared__ uint32_t part[kUScanThreads];    // [chunk][bin] chunk sums, then chunk prefixes
+  __shared__ uint32_t s_base[kFastBins];
+  __shared__ uint32_t s_wsum[kUScanThreads / 64];
+  __shared__ uint64_t s_vis[kUScanThreads / 64];
+  const int t = threadIdx.x;
+  const int chunks = kUScanThreads / nbins;           // >= 1 as nbins <= kFastBins = kUScanThreads
+  const int b = t % nbins, c = t / nbins;
+  const bool active = c < chunks;
+  const int per = (units + chunks - 1) / chunks;
+  const int u0 = active ? c * per : 0;
+  const int u1 = active ? min(units, u0 + per) : 0;
+  uint32_t sum = 0;
+  for (int ub = u0; ub < u1; ub += 16) {   // sixteen independent loads in flight
+    uint32_t x[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? ucnt[(int64_t)(ub + q) * nbins + b] : 0u;
+#pragma unroll
+    for (int q = 0; q < 16; q++) sum += x[q];
+  }
+  if (active) part[c * nbins + b] = sum;
+  // visible count
+  uint64_t v = 0;
+  for (int u = t; u < units; u += kUScanThreads) v += uvis[u];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((t & 63) == 0) s_vis[t >> 6] = v;
+  __syncthreads();
+  // per bin: exclusive prefix over chunks, and the bin total
+  uint32_t total = 0;
+  if (t < nbins) {
+    for (int k = 0; k < chunks; k++) {
+      const uint32_t x = part[k * nbins + t];
+      part[k * nbins + t] = total;
+      total += x;
+    }
+  }
+  // exclusive scan of the totals over bins (thread t holds bin t)
+  uint32_t inc = total;
+  const int lane = t & 63, wave = t >> 6;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) s_wsum[wave] = inc;
+  __syncthreads();
+  uint32_t carry = 0;
+  uint64_t grand = 0;
+  for (int w = 0; w < kUScanThreads / 64; w++) {
+    if (w < wave) carry += s_wsum[w];
+    grand += s_wsum[w];
+  }
+  if (t < nbins) {
+    const uint32_t start = carry + inc - total;
+    s_base[t] = start;
+    trange[2 * t] = start;
+    trange[2 * t + 1] = start + total;
+  }
+  if (t == 0) {
+    uint64_t nv = 0;
+    for (int w = 0; w < kUScanThreads / 64; w++) nv += s_vis[w];
+    counters[C_VISIBLE] = nv;
+    counters[C_PAIRS] = grand;
+    counters[C_OVERFLOW] = (int64_t)grand > cap ? 1ull : 0ull;
+  }
+  __syncthreads();
+  if (active) {
+    uint32_t run = s_base[b] + part[c * nbins + b];
+    for (int ub = u0; ub < u1; ub += 16) {
+      uint32_t x[16];
+#pragma unroll
+      for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? ucnt[(int64_t)(ub + q) * nbins + b] : 0u;
+#pragma unroll
+      for (int q = 0; q < 16; q++) {
+        if (ub + q < u1) ucnt[(int64_t)(ub + q) * nbins + b] = run;
+        run += x[q];
+      }
+    }
+  }
+}
+
+// Emission. Each wave first counts its pairs per bin, and the waves' starts
+// follow from the unit offsets. Then the pairs of each round, taken 64 at a
+// time in Gaussian-index order, are ranked within their bins: a lane matches
+// its pair's bin against the other lanes' with one ballot per bin bit, and
+// the lowest lane of each group advances the wave's running count of that
+// bin, as in the onesweep ranking. Each bin's pairs therefore come out in
+// index order.
+__global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restrict__ gbin,
+                                                            const uint32_t* __restrict__ key, int64_t n, int rounds,
+                                                            int nbins, int bin_bits, const uint32_t* __restrict__ uoff,
+                                                            const uint64_t* __restrict__ counters,
+                                                            uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  constexpr int NW = kUnitThreads / 64;
+  __shared__ uint32_t wc[NW][kFastBins];
+  __shared__ RoundPairs RP[NW];
+  __shared__ uint32_t lkey[NW][64];
+  if (counters[C_OVERFLOW]) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int k = t; k < NW * kFastBins; k += kUnitThreads) (&wc[0][0])[k] = 0u;
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * kUnitThreads * rounds + (int64_t)wave * 64 * rounds;
+  uint32_t* my = wc[wave];
+  RoundPairs& R = RP[wave];
+  for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
+    if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
+    uint2 g[kRoundGroup];
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+#pragma unroll
+    for (int u = 0; u < kRoundGroup; u++) {
+      const uint32_t total = round_setup(R, g[u], lane);
+      for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        if (q < total) {
+          uint32_t src;
+          atomicAdd(&my[round_pair(R, q, src)], 1u);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  const uint32_t* row = uoff + (int64_t)blockIdx.x * nbins;
+  for (int b = t; b < nbins; b += kUnitThreads) {
+    uint32_t run = row[b];
+    for (int w = 0; w < NW; w++) {
+      const uint32_t x = wc[w][b];
+      wc[w][b] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  const uint32_t lt_lo = lane >= 32 ? 0xFFFFFFFFu : ((1u << lane) - 1u);
+  const uint32_t lt_hi = lane <= 32 ? 0u : ((1u << (lane - 32)) - 1u);
+  for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
+    if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
+    uint2 g[kRoundGroup];
+    uint32_t kk[kRoundGroup];
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+#pragma unroll
+    for (int u = 0; u < kRoundGroup; u++)
+      kk[u] = g[u].x != kNoBin ? key[wbase + (int64_t)(r0 + u) * 64 + lane] : 0u;
+#pragma unroll
+    for (int u = 0; u < kRoundGroup; u++) {
+      const uint32_t total = round_setup(R, g[u], lane);
+      lkey[wave][lane] = kk[u];
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t ibase = (uint32_t)(wbase + (int64_t)(r0 + u) * 64);
+      for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        const bool ok = q < total;
+        uint32_t src = 0, B = 0;
+        if (ok) B = round_pair(R, q, src);
+        const uint64_t v = __ballot(ok);
+        uint32_t pl = (uint32_t)v, ph = (uint32_t)(v >> 32);
+        for (int bit = 0; bit < bin_bits; bit++) {
+          const uint32_t mine = (uint32_t)((int32_t)(B << (31 - bit)) >> 31);
+          const uint64_t m = __ballot(mine != 0u);
+          pl &= ~((uint32_t)m ^ mine);
+          ph &= ~((uint32_t)(m >> 32) ^ mine);
+        }
+        const uint32_t old = ok ? my[B] : 0u;
+        const uint32_t below = (uint32_t)(__popc(pl & lt_lo) + __popc(ph & lt_hi));
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == 0) my[B] = old + (uint32_t)(__popc(pl) + __popc(ph));
+        __builtin_amdgcn_wave_barrier();
+        if (ok) {
+          pkey[old + below] = lkey[wave][src];
+          pval[old + below] = ibase + src;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// Per-bin stable LSD sort by depth key of the segment trange[b] (keys in
+// pkey, Gaussian indices in pval), in place. Segments of at most kSortMax
+// pairs stay in registers and LDS: the keys are offset by the segment's
+// minimum, and the bits that remain are sorted in as few passes of at most
+// 9-bit digits as cover them (3 passes for a depth range below 2^27 key
+// units). Longer segments are sorted chunk by chunk through (tkey, tval) in
+// global memory, 4 passes of 8 bits. Item order within a chunk: wave w holds
+// positions [w*ipt*64, (w+1)*ipt*64) in rounds of 64, so (wave, round, lane)
+// is the segment order and a wave ranks its items against its own digit
+// counters (ballot matching, no block barrier), as in the onesweep pass.
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = 16;
+constexpr int kSortMax = kSortThreads * kSortItems;
+constexpr int kSortDigits = 512;
+
+struct SortShared {
+  uint32_t buf[kSortMax];
+  uint32_t wcnt[kSortWaves][kSortDigits];
+  uint32_t doff[kSortDigits];
+  uint32_t wsum[kSortDigits / 64];
+  uint32_t red[2][kSortWaves];
+};
+
+// Ranks the valid items of one chunk within each wave by the digit
+// (k >> shift) & (2^dbits - 1); afterwards S.wcnt[w][d] holds wave w's count
+// of digit d. A lane's peers (same digit) are the lanes that agree with it on
+// every digit bit: per bit, peers &= ~(ballot(bit) ^ mine), mine = 0 or ~0.
+__device__ inline void sort_rank(SortShared& S, const uint32_t (&k)[kSortItems], uint32_t (&rk)[kSortItems],
+                                 int ipt, int chunk_n, int shift, int dbits) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t lt_lo = lane >= 32 ? 0xFFFFFFFFu : ((1u << lane) - 1u);
+  const uint32_t lt_hi = lane <= 32 ? 0u : ((1u << (lane - 32)) - 1u);
+  const uint32_t dmask = (1u << dbits) - 1u;
+  uint32_t* my = S.wcnt[wave];
+  for (int d = lane; d < (1 << dbits); d += 64) my[d] = 0u;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    if (r < ipt) {   // uniform
+      const int pos = wave * ipt * 64 + r * 64 + lane;
+      const bool ok = pos < chunk_n;
+      const uint32_t dg = (k[r] >> shift) & dmask;
+      const uint64_t v = __ballot(ok);
+      uint32_t pl = (uint32_t)v, ph = (uint32_t)(v >> 32);
+      for (int bit = 0; bit < dbits; bit++) {
+        const uint32_t mine = (uint32_t)((int32_t)(dg << (31 - bit)) >> 31);
+        const uint64_t m = __ballot(mine != 0u);
+        pl &= ~((uint32_t)m ^ mine);
+        ph &= ~((uint32_t)(m >> 32) ^ mine);
+      }
+      const uint32_t old = ok ? my[dg] : 0u;
+      const uint32_t below = (uint32_t)(__popc(pl & lt_lo) + __popc(ph & lt_hi));
+      rk[r] = old + below;
+      __builtin_amdgcn_wave_barrier();
+      if (ok && below == 0) my[dg] = old + (uint32_t)(__popc(pl) + __popc(ph));
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// Thread t < 2^dbits (digit d = t): per-wave starts of digit d from `run0`;
+// returns the digit's total count.
+__device__ inline uint32_t sort_wave_starts(SortShared& S, int t, uint32_t run0) {
+  uint32_t run = run0;
+  for (int w = 0; w < kSortWaves; w++) {
+    const uint32_t x = S.wcnt[w][t];
+    S.wcnt[w][t] = run;
+    run += x;
+  }
+  return run - run0;
+}
+
+// Exclusive scan of `v` over threads 0 .. kSortDigits-1 (the digits); all
+// threads must call it (it contains a block barrier).
+__device__ inline uint32_t digit_exclusive_scan(SortShared& S, uint32_t v) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (t < kSortDigits && lane == 63) S.wsum[wave] = inc;
+  __syncthreads();
+  uint32_t carry = 0;
+  if (t < kSortDigits)
+    for (int w = 0; w < wave; w++) carry += S.wsum[w];
+  return carry + inc - v;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_bin_sort(uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
+                                                           uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                           const uint32_t* __restrict__ trange,
+                                                           const uint64_t* __restrict__ counters) {
+  __shared__ SortShared S;
+  if (counters[C_OVERFLOW]) return;
+  const uint32_t start = trange[2 * blockIdx.x], end = trange[2 * blockIdx.x + 1];
+  const int seg = (int)(end - start);
+  if (seg <= 1) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint32_t k[kSortItems], v[kSortItems], rk[kSortItems];
+  if (seg <= kSortMax) {
+    const int ipt = (seg + kSortThreads - 1) / kSortThreads;
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+      const int pos = wave * ipt * 64 + r * 64 + lane;
+      const bool ok = r < ipt && pos < seg;
+      k[r] = ok ? pkey[start + pos] : 0u;
+      v[r] = ok ? pval[start + pos] : 0u;
+      if (ok) {
+        kmin = min(kmin, k[r]);
+        kmax = max(kmax, k[r]);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+      kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+    }
+    if (lane == 0) {
+      S.red[0][wave] = kmin;
+      S.red[1][wave] = kmax;
+    }
+    __syncthreads();
+    kmin = 0xFFFFFFFFu;
+    kmax = 0u;
+    for (int w = 0; w < kSortWaves; w++) {
+      kmin = min(kmin, S.red[0][w]);
+      kmax = max(kmax, S.red[1][w]);
+    }
+    const uint32_t range = kmax - kmin;
+    const int bits = range == 0u ? 0 : 32 - __clz((int)range);
+    const int passes = bits <= 27 ? (bits + 8) / 9 : 4;
+    const int width = passes > 0 ? (bits + passes - 1) / passes : 0;
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) k[r] -= kmin;
+    for (int q = 0; q < passes; q++) {
+      const int shift = q * width;
+      const int dbits = min(width, bits - shift);
+      const int nd = 1 << dbits;
+      sort_rank(S, k, rk, ipt, seg, shift, dbits);
+      __syncthreads();
+      uint32_t total = 0;
+      if (t < nd) total = sort_wave_starts(S, t, 0u);
+      const uint32_t excl = digit_exclusive_scan(S, total);
+      if (t < nd)
+        for (int w = 0; w < kSortWaves; w++) S.wcnt[w][t] += excl;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        if (r < ipt && pos < seg) {
+          rk[r] += S.wcnt[wave][(k[r] >> shift) & (uint32_t)(nd - 1)];
+          S.buf[rk[r]] = k[r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        if (r < ipt && pos < seg) k[r] = S.buf[pos];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        if (r < ipt && pos < seg) S.buf[rk[r]] = v[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        if (r < ipt && pos < seg) v[r] = S.buf[pos];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+      const int pos = wave * ipt * 64 + r * 64 + lane;
+      if (r < ipt && pos < seg) pval[start + pos] = v[r];
+    }
+    return;
+  }
+  // long segment: four passes of 8 bits through global memory, chunk by chunk
+  uint32_t *sk = pkey, *sv = pval, *dk = tkey, *dv = tval;
+  for (int shift = 0; shift < 32; shift += 8) {
+    if (t < 256) S.doff[t] = 0u;
+    __syncthreads();
+    for (int pos = t; pos < seg; pos += kSortThreads) atomicAdd(&S.doff[(sk[start + pos] >> shift) & 255u], 1u);
+    __syncthreads();
+    const uint32_t h = t < 256 ? S.doff[t] : 0u;
+    const uint32_t excl = digit_exclusive_scan(S, h);
+    if (t < 256) S.doff[t] = excl;      // running start of every digit
+    __syncthreads();
+    for (int c0 = 0; c0 < seg; c0 += kSortMax) {
+      const int cn = min(kSortMax, seg - c0);
+      const int ipt = (cn + kSortThreads - 1) / kSortThreads;
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        k[r] = (r < ipt && pos < cn) ? sk[start + c0 + pos] : 0u;
+        v[r] = (r < ipt && pos < cn) ? sv[start + c0 + pos] : 0u;
+      }
+      sort_rank(S, k, rk, ipt, cn, shift, 8);
+      __syncthreads();
+      if (t < 256) S.doff[t] += sort_wave_starts(S, t, S.doff[t]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSortItems; r++) {
+        const int pos = wave * ipt * 64 + r * 64 + lane;
+        if (r < ipt && pos < cn) {
+          const uint32_t dst = S.wcnt[wave][(k[r] >> shift) & 255u] + rk[r];
+          dk[start + dst] = k[r];
+          dv[start + dst] = v[r];
+        }
+      }
+      __syncthreads();
+    }
+    uint32_t* tmp = sk;
+    sk = dk;
+    dk = tmp;
+    tmp = sv;
+    sv = dv;
+    dv = tmp;
+  }
+}
+
 // Stable LSD sort of (keys, vals) over bits [0, total_bits) in passes of at
 // most 8 bits, ping-ponging between buffer a and buffer b. The data start in
 // a; after an even number of passes they end in a, after an odd number in b
@@ -479,10 +1025,24 @@ hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStre
 
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
   uint64_t* counters = at<uint64_t>(ws, p.counters);
-  uint32_t* trange = at<uint32_t>(ws, p.trange);
-  hipError_t e = launch_fill_u32(trange, 0u, 2 * (int64_t)p.bins, st);
-  if (e != hipSuccess) return e;
+  uint32_t* trange = at<uint32_t>(ws, p.trange);   // zeroed with the control region
+  hipError_t e = hipSuccess;
   if (p.n == 0) return hipSuccess;
+  if (p.by_index) {
+    uint2* gbin = at<uint2>(ws, p.gbin);
+    uint32_t* ucnt = at<uint32_t>(ws, p.ucnt);
+    uint32_t *pk = at<uint32_t>(ws, p.pkey), *pv = at<uint32_t>(ws, p.pval);
+    hipLaunchKernelGGL(k_unit_count, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin, p.n, p.unit_rounds,
+                       p.bins, ucnt, at<uint32_t>(ws, p.uvis));
+    hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kUScanThreads), 0, st, ucnt, at<uint32_t>(ws, p.uvis), p.units,
+                       p.bins, p.cap, counters, trange);
+    hipLaunchKernelGGL(k_unit_emit, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin,
+                       at<uint32_t>(ws, p.key), p.n, p.unit_rounds, p.bins, tile_bits(p.bins), ucnt, counters, pk,
+                       pv);
+    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)p.bins), dim3(kSortThreads), 0, st, pk, pv,
+                       at<uint32_t>(ws, p.pkey2), at<uint32_t>(ws, p.pval2), trange, counters);
+    return hipGetLastError();
+  }
   // 1. compaction of the visible Gaussians, placed so that the depth sort
   //    ends in (ckey, cval)
   const bool dodd = sort_passes(32) & 1;

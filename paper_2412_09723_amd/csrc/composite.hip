@@ -866,7 +866,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
 template <int TILE>
 hipError_t bwd_mfma(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
-  hipLaunchKernelGGL((k_composite_bwd_m<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
+  hipLaunchKernelGGL((k_composite_bwd_m<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
@@ -876,7 +876,7 @@ hipError_t bwd_mfma(const Plan& p, char* ws, hipStream_t st) {
 template <int TILE>
 hipError_t bwd_scalar(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
-  hipLaunchKernelGGL((k_composite_bwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
+  hipLaunchKernelGGL((k_composite_bwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
@@ -886,7 +886,7 @@ hipError_t bwd_scalar(const Plan& p, char* ws, hipStream_t st) {
 template <int TILE, int WB>
 hipError_t fwd_one(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
-  hipLaunchKernelGGL((k_composite_fwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
+  hipLaunchKernelGGL((k_composite_fwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last));
@@ -896,7 +896,7 @@ hipError_t fwd_one(const Plan& p, char* ws, hipStream_t st) {
 template <int TILE, int WB>
 hipError_t bwd_one(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
-  hipLaunchKernelGGL((k_composite_bwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
+  hipLaunchKernelGGL((k_composite_bwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
@@ -906,7 +906,7 @@ hipError_t bwd_one(const Plan& p, char* ws, hipStream_t st) {
 template <int TILE>
 hipError_t fwd_scalar(const Plan& p, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
-  hipLaunchKernelGGL((k_composite_fwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, p.rec),
+  hipLaunchKernelGGL((k_composite_fwd_s<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
                      at<uint32_t>(ws, p.last));

@@ -106,25 +106,53 @@ __device__ inline int job_of_block(const JobDesc* __restrict__ jobs, int njobs, 
 }
 
 // ------------------------------------------------------------ workspace plan
+// Two binning paths produce the same per-bin lists, ordered by (depth key,
+// Gaussian index):
+//  * per-bin sort (by_index, used when all jobs together have at most
+//    kFastBins bins): pairs are counted per (unit of Gaussians, bin), placed
+//    by one scan, emitted in index order and sorted by depth key inside each
+//    bin; list entries are virtual Gaussian indices into the index-order
+//    records rec_i, and the backward accumulators are indexed the same way;
+//  * global depth sort (otherwise): the visible Gaussians are sorted by depth
+//    once, pairs are emitted in rank order and sorted by bin; list entries
+//    are depth ranks into the rank-order records rec.
+constexpr int kFastBins = 1024;
+constexpr int64_t kUnitEntries = 131072;   // bound on units x bins for the single-block scan
+constexpr int kUnitThreads = 256;          // binning unit: 4 waves, each `unit_rounds` rounds of 64 Gaussians
+
 struct Plan {
   int64_t n, cap;                   // n: virtual Gaussian slots (all jobs, padded)
   int njobs;
   int tile, tiles;                  // compositing tile edge, tiles of all jobs
   int bin, bins, bshift;            // binning tiles: bin = tile << bshift; bins of all jobs
   int64_t pixels;                   // pixels of all jobs
+  bool by_index;                    // per-bin sort path (see above)
+  int unit_rounds, units;           // per-bin path: rounds per wave of a unit, number of units
   int scan_blocks_n;     // blocks of the length-n scans
   int pose_blocks;
   int rank_bits;         // bits of a depth rank (n - 1)
   bool packed;           // pairs stored as one word: tile << rank_bits | rank
   // byte offsets
   // control region (zeroed by one fill at every forward): counters, sort
-  // tickets, digit histograms, look-back words
-  size_t counters, tickets, digit_hist, lookback, ctrl_end;
+  // tickets, digit histograms, look-back words, bin ranges
+  size_t counters, tickets, digit_hist, lookback, trange, ctrl_end;
   size_t jobs;           // device JobTable
-  size_t key, vis_pos, ntiles, rec_i, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part,
-      pkey, pval, pkey2, pval2, trange, tfinal, last, g2d, pose_part;
+  size_t key, rec_i, g2d, pose_part, tfinal, last, pkey, pval, pkey2, pval2;
+  // per-bin path
+  size_t gbin, ucnt, uvis;
+  // global depth sort path
+  size_t vis_pos, ntiles, rank_of, ckey, cval, ckey2, cval2, rec, cnt, cnt_off, scan_part;
   size_t total;
 };
+
+// Records addressed by list entries (and rows of the backward accumulators).
+inline size_t rec_slots(const Plan& p) { return p.by_index ? p.rec_i : p.rec; }
+
+// Bin footprint of a visible Gaussian on the per-bin path (uint2): x = its
+// first (lowest) global bin, y = (ntx - 1) | (nty - 1) << 10 | (bx - 1) << 20
+// with ntx x nty bins covered and bx bins per row of its job (all <= 1024 as
+// the path has at most kFastBins bins); x = 0xFFFFFFFF when culled.
+constexpr uint32_t kNoBin = 0xFFFFFFFFu;
 
 // Per-job layout (offsets of every job's slots) for options `tile`, `bin`.
 bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, int& tiles, int& bins,

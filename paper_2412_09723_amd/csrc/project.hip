@@ -53,18 +53,27 @@ __device__ inline void load_pose(const float* vm, Pose& P) {
 }
 
 // One block of 256 virtual slots belongs to one job; slots past the job's n
-// are padding and stay invisible.
+// are padding and stay invisible. Outputs per slot: the depth key and the
+// record (index order), and for the binning path in use either the bin
+// footprint `gbin` plus a zeroed accumulator row (per-bin path) or the
+// visibility flag, bin count and rank placeholder (global sort path); the
+// pointers of the other path are null.
 __global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__ jobs, int njobs, float near_z,
                                                      int tile, uint32_t* __restrict__ key,
                                                      uint32_t* __restrict__ vis, uint32_t* __restrict__ ntiles,
-                                                     int32_t* __restrict__ rank_of, uint4* __restrict__ rec_i) {
+                                                     int32_t* __restrict__ rank_of, uint4* __restrict__ rec_i,
+                                                     uint2* __restrict__ gbin, float* __restrict__ g2d) {
   const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
   const int64_t li = (int64_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x;   // index within the job
   const int64_t i = J.g0 + li;                                                     // virtual index
   key[i] = 0xFFFFFFFFu;
-  vis[i] = 0u;
-  ntiles[i] = 0u;
-  rank_of[i] = -1;
+  if (gbin) {
+    gbin[i] = make_uint2(kNoBin, 0u);
+  } else {
+    vis[i] = 0u;
+    ntiles[i] = 0u;
+    rank_of[i] = -1;
+  }
   if (li >= J.n) return;
   const int64_t n = J.n;
   const float* __restrict__ means = J.means;
@@ -153,8 +162,16 @@ __global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__
 
   uint32_t zbits = __float_as_uint(z32);
   key[i] = zbits;
-  vis[i] = 1u;
-  ntiles[i] = ntx * nty;
+  if (gbin) {
+    const uint32_t first = (uint32_t)(J.bin0 + (by0 / tile) * J.bx + bx0 / tile);
+    gbin[i] = make_uint2(first, (ntx - 1u) | ((nty - 1u) << 10) | ((uint32_t)(J.bx - 1) << 20));
+    float2* row = reinterpret_cast<float2*>(g2d + (int64_t)kGradFields * i);
+#pragma unroll
+    for (int f = 0; f < kGradFields / 2; f++) row[f] = make_float2(0.f, 0.f);
+  } else {
+    vis[i] = 1u;
+    ntiles[i] = ntx * nty;
+  }
   uint4 r0, r1, r2, r3;
   r0.x = __float_as_uint((float)ufl);   // integer-valued, |floor(u)| <= 2^22: exact
   r0.y = __float_as_uint((float)vfl);
@@ -186,7 +203,7 @@ __global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__
 __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__ jobs, int njobs,
                                                      const uint32_t* __restrict__ key,
                                                      const int32_t* __restrict__ rank_of,
-                                                     const float* __restrict__ g2d,
+                                                     float* __restrict__ g2d,
                                                      const uint64_t* __restrict__ counters,
                                                      double* __restrict__ pose_part) {
   __shared__ double red[12][256 / 64];
@@ -210,13 +227,20 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
   const bool valid = li < n;
   if (valid && key[i] != 0xFFFFFFFFu) {
-    const int r = rank_of[i];
-    const float* acc = g2d + (int64_t)r * kGradFields;
+    // accumulator row: by depth rank (global sort path) or by index (per-bin
+    // path, where the row is cleared after use for the next backward)
+    const int64_t r = rank_of ? (int64_t)rank_of[i] : i;
+    float* acc = g2d + r * kGradFields;
     const double E = acc[0], P1 = acc[1], P2 = acc[2], P1x = acc[3], P1y = acc[4], P2y = acc[5];
     const double GZ = acc[9];
     gc[0] = acc[6];
     gc[1] = acc[7];
     gc[2] = acc[8];
+    if (!rank_of) {
+      float2* row = reinterpret_cast<float2*>(acc);
+#pragma unroll
+      for (int f = 0; f < kGradFields / 2; f++) row[f] = make_float2(0.f, 0.f);
+    }
     Pose P;
     load_pose(viewmat, P);
     const double mu[3] = {means[li], means[n + li], means[2 * n + li]};
@@ -444,10 +468,12 @@ __global__ void __launch_bounds__(256) k_pose_final(const JobDesc* __restrict__ 
 
 hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
+  const bool bi = p.by_index;
   hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st,
                      at<JobTable>(ws, p.jobs)->job, p.njobs, near_z, p.bin, at<uint32_t>(ws, p.key),
-                     at<uint32_t>(ws, p.vis_pos), at<uint32_t>(ws, p.ntiles), at<int32_t>(ws, p.rank_of),
-                     at<uint4>(ws, p.rec_i));
+                     bi ? nullptr : at<uint32_t>(ws, p.vis_pos), bi ? nullptr : at<uint32_t>(ws, p.ntiles),
+                     bi ? nullptr : at<int32_t>(ws, p.rank_of), at<uint4>(ws, p.rec_i),
+                     bi ? at<uint2>(ws, p.gbin) : nullptr, bi ? at<float>(ws, p.g2d) : nullptr);
   return hipGetLastError();
 }
 
@@ -455,7 +481,8 @@ hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_
   const JobDesc* jobs = at<JobTable>(ws, p.jobs)->job;
   if (p.n > 0) {
     hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st, jobs, p.njobs,
-                       at<uint32_t>(ws, p.key), at<int32_t>(ws, p.rank_of), at<float>(ws, p.g2d),
+                       at<uint32_t>(ws, p.key), p.by_index ? nullptr : at<int32_t>(ws, p.rank_of),
+                       at<float>(ws, p.g2d),
                        at<uint64_t>(ws, p.counters), at<double>(ws, p.pose_part));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -199,17 +199,19 @@ class Job:
             nbytes = count * torch.empty((), dtype=dtype).element_size()
             return self.ws[off:off + nbytes].view(dtype)
 
-        pair_tile = view(v.pair_tile, max(self.cap, 1), torch.int32)
+        kind = int(v.list_kind)
         pair_rank = view(v.pair_rank, max(self.cap, 1), torch.int32)
+        pair_tile = view(v.pair_tile, max(self.cap, 1), torch.int32) if kind == 0 else None
         if v.pair_rank_bits > 0:       # packed pair words: tile << bits | rank
             bits = v.pair_rank_bits
             words = pair_tile.to(torch.int64) & 0xFFFFFFFF
             pair_tile = (words >> bits).to(torch.int32)
             pair_rank = (words & ((1 << bits) - 1)).to(torch.int32)
         return dict(
+            list_kind=kind,
             depth_key=view(v.depth_key, n, torch.int32),
-            sorted_index=view(v.sorted_index, n, torch.int32),
-            rank_of=view(v.rank_of, n, torch.int32),
+            sorted_index=view(v.sorted_index, n, torch.int32) if kind == 0 else None,
+            rank_of=view(v.rank_of, n, torch.int32) if kind == 0 else None,
             pair_tile=pair_tile,
             pair_rank=pair_rank,
             tile_range=view(v.tile_range, 2 * tiles, torch.int32).view(tiles, 2),

@@ -29,7 +29,10 @@ def expected_order(pr):
 
 
 def check_structure(job, sc, tile):
-    """Keys, records, depth order and tile lists: bit-exact with the oracle."""
+    """Keys, records and bin lists: bit-exact with the oracle. Lists hold
+    depth ranks into rank-order records (list kind 0) or Gaussian indices into
+    index-order records (kind 1); both must give the oracle's (depth, index)
+    order in every bin."""
     pr = oracle.project(sc)
     st = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in job.state().items()}
     nv, K = int(st["counters"][0]), int(st["counters"][1])
@@ -38,10 +41,17 @@ def check_structure(job, sc, tile):
     zk = np.where(pr["visible"] == 1, pr["zkey"], np.uint32(0xFFFFFFFF))
     assert np.array_equal(st["depth_key"].view(np.uint32)[:sc.n], zk)
     order = expected_order(pr)
-    assert np.array_equal(st["sorted_index"].view(np.uint32)[:nv], order.astype(np.uint32))
-    rec = st["records"][:nv].view(np.uint32)
-    idx = rec[:, 15].astype(np.int64)
-    assert np.array_equal(idx, order)
+    if st["list_kind"] == 0:
+        assert np.array_equal(st["sorted_index"].view(np.uint32)[:nv], order.astype(np.uint32))
+        rec = st["records"][:nv].view(np.uint32)
+        idx = rec[:, 15].astype(np.int64)
+        assert np.array_equal(idx, order)
+        rank_of = st["rank_of"][:sc.n]
+        assert np.array_equal(rank_of[order], np.arange(nv))
+    else:
+        idx = np.flatnonzero(pr["visible"])
+        rec = st["records"][idx].view(np.uint32)
+        assert np.array_equal(rec[:, 15].astype(np.int64), idx)
     assert np.array_equal(rec[:, 0].view(np.float32), pr["ctr"][0][idx].astype(np.float32))
     assert np.array_equal(rec[:, 1].view(np.float32), pr["ctr"][1][idx].astype(np.float32))
     for w, k in ((2, 0), (3, 1), (4, 2), (5, 3), (6, 4), (7, 5)):
@@ -50,9 +60,7 @@ def check_structure(job, sc, tile):
     bb = pr["bbox"][:, idx].astype(np.uint32)
     assert np.array_equal(rec[:, 13], bb[0] | (bb[1] << 16))
     assert np.array_equal(rec[:, 14], bb[2] | (bb[3] << 16))
-    rank_of = st["rank_of"][:sc.n]
-    assert np.array_equal(rank_of[order], np.arange(nv))
-    # tile lists
+    # bin lists
     W, H = sc.intr.width, sc.intr.height
     off, ids = oracle.tile_lists(pr, W, H, tile)
     assert K == len(ids)
@@ -61,10 +69,13 @@ def check_structure(job, sc, tile):
     assert np.array_equal(lens, np.diff(off))
     nonempty = lens > 0
     assert np.array_equal(tr[nonempty, 0], off[:-1][nonempty])
-    ranks = st["pair_rank"][:K].view(np.uint32).astype(np.int64)
-    assert np.array_equal(order[ranks], ids.astype(np.int64))
-    tiles_of = st["pair_tile"][:K].view(np.uint32)
-    assert np.array_equal(tiles_of, np.repeat(np.arange(len(lens)), lens).astype(np.uint32))
+    entries = st["pair_rank"][:K].view(np.uint32).astype(np.int64)
+    if st["list_kind"] == 0:
+        assert np.array_equal(order[entries], ids.astype(np.int64))
+        tiles_of = st["pair_tile"][:K].view(np.uint32)
+        assert np.array_equal(tiles_of, np.repeat(np.arange(len(lens)), lens).astype(np.uint32))
+    else:
+        assert np.array_equal(entries, ids.astype(np.int64))
     return pr, st
 
 

@@ -75,9 +75,11 @@ def test_config0_rotated_pose_and_ragged_image():
 
 @pytest.mark.parametrize("scalar,tile,bin_tile,bwd", [(False, 16, 0, None), (True, 16, 0, None),
                                                      (False, 32, 128, None), (False, 16, 128, "mfma"),
-                                                     (False, 32, 128, "mfma")])
+                                                     (False, 32, 128, "mfma"), (False, 32, 256, "mfma")])
 def test_config1_full_size(scalar, tile, bin_tile, bwd):
-    """1200x680, 1M Gaussians (the benchmark workload)."""
+    """1200x680, 1M Gaussians (the benchmark workload). Bin 0 (3225 bins)
+    takes the global depth-sort path, bins of 128 the per-bin sort, and bins
+    of 256 hold up to 30k pairs each, beyond one block's in-LDS sort."""
     _log(f"config1 full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")
     sc = scenes.config1()
     job, imgs = run_job(sc, tile=tile, wave_batch=64, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
