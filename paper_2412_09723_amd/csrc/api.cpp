@@ -174,14 +174,16 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   p.rank_bits = 1;
   while (p.rank_bits < 31 && ((int64_t)1 << p.rank_bits) < nn) p.rank_bits++;
   // per-bin path: units of kUnitThreads * R Gaussians, R a power of two in
-  // [8, 64] chosen so that units x bins stays within the scan's bound
+  // [2, 64] chosen so that unit groups x bins stays within the scan's bound
   if (p.bins <= kFastBins) {
-    for (int r = 8; r <= 64; r *= 2) {
+    for (int r = 2; r <= 64; r *= 2) {
       const int64_t units = (nn + (int64_t)kUnitThreads * r - 1) / ((int64_t)kUnitThreads * r);
-      if (units * p.bins <= kUnitEntries) {
+      const int64_t groups = (units + kGroupUnits - 1) / kGroupUnits;
+      if (groups * p.bins <= kUnitEntries) {
         p.by_index = true;
         p.unit_rounds = r;
         p.units = (int)units;
+        p.groups = (int)groups;
         break;
       }
     }
@@ -200,6 +202,8 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
     const int64_t os_tile = 2048;
     const int64_t tiles_v = (nn + os_tile - 1) / os_tile, tiles_p = (cc + os_tile - 1) / os_tile;
     p.lookback = take(8 * 256 * (size_t)(tiles_v > tiles_p ? tiles_v : tiles_p));
+  } else {
+    p.gcnt = take(4 * (size_t)p.groups * p.bins);
   }
   p.trange = take(8 * (size_t)p.bins);
   p.ctrl_end = o;

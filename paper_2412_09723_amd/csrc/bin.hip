@@ -441,10 +441,11 @@ __global__ void __launch_bounds__(kOsThreads) k_onesweep(const uint32_t* __restr
 // of kUnitThreads threads covering kUnitThreads * R consecutive virtual
 // Gaussians: wave w of the unit owns the R * 64 Gaussians starting at
 // unit_base + w * R * 64, in R rounds of 64.
-//   1. k_unit_count: pairs per (unit, bin) and visible Gaussians per unit;
-//   2. k_unit_scan (one block): exclusive offsets of every (unit, bin) in
+//   1. k_unit_count: pairs per (unit, bin), their sums over groups of
+//      kGroupUnits consecutive units, and visible Gaussians per unit;
+//   2. k_unit_scan (one block): exclusive offsets of every (group, bin) in
 //      bin-major order, the bin ranges, the pair total and the capacity
-//      check;
+//      check (a unit adds its predecessors in the group when it emits);
 //   3. k_unit_emit: every pair (depth key, Gaussian index) written into its
 //      bin's segment in Gaussian-index order;
 //   4. k_bin_sort (one block per bin): stable LSD sort of the segment by
@@ -497,16 +498,16 @@ __device__ inline uint32_t round_setup(RoundPairs& R, uint2 g, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
 }
 
-// Rounds are processed in groups of kRoundGroup whose footprints are loaded
-// together, so a wave waits for memory once per group.
-constexpr int kRoundGroup = 8;   // divides every unit_rounds value
+// Rounds are processed in groups of up to kRoundGroup whose footprints are
+// loaded together, so a wave waits for memory once per group.
+constexpr int kRoundGroup = 8;
 
-__device__ inline void load_group(const uint2* __restrict__ gbin, int64_t i0, int64_t n, int lane,
+__device__ inline void load_group(const uint2* __restrict__ gbin, int64_t i0, int64_t n, int nr, int lane,
                                   uint2 (&g)[kRoundGroup]) {
 #pragma unroll
   for (int u = 0; u < kRoundGroup; u++) {
     const int64_t i = i0 + (int64_t)u * 64 + lane;
-    g[u] = i < n ? gbin[i] : make_uint2(kNoBin, 0u);
+    g[u] = (u < nr && i < n) ? gbin[i] : make_uint2(kNoBin, 0u);
   }
 }
 
@@ -538,6 +539,7 @@ __device__ inline uint32_t round_pair(const RoundPairs& R, uint32_t q, uint32_t&
 
 __global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __restrict__ gbin, int64_t n, int rounds,
                                                              int nbins, uint32_t* __restrict__ ucnt,
+                                                             uint32_t* __restrict__ gcnt,
                                                              uint32_t* __restrict__ uvis) {
   constexpr int NW = kUnitThreads / 64;
   __shared__ uint32_t h[kFastBins];
@@ -553,9 +555,10 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __rest
   for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
     if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
     uint2 g[kRoundGroup];
-    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, rounds - r0, lane, g);
 #pragma unroll
     for (int u = 0; u < kRoundGroup; u++) {
+      if (r0 + u >= rounds) break;   // uniform
       nvis += g[u].x != kNoBin ? 1u : 0u;
       const uint32_t total = round_setup(R, g[u], lane);
       for (uint32_t q0 = 0; q0 < total; q0 += 64) {
@@ -572,17 +575,22 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __rest
   if (lane == 0) atomicAdd(&s_vis, nvis);
   __syncthreads();
   uint32_t* row = ucnt + (int64_t)blockIdx.x * nbins;
-  for (int b = t; b < nbins; b += kUnitThreads) row[b] = h[b];
+  uint32_t* grow = gcnt + (int64_t)(blockIdx.x / kGroupUnits) * nbins;
+  for (int b = t; b < nbins; b += kUnitThreads) {
+    const uint32_t c = h[b];
+    row[b] = c;
+    if (c) atomicAdd(&grow[b], c);
+  }
   if (t == 0) uvis[blockIdx.x] = s_vis;
 }
 
-// One block of 1024 threads. ucnt[u][b] (unit-major) becomes the exclusive
-// offset of (unit u, bin b) in the bin-major order of all pairs. Thread
-// (chunk c, bin b) owns bin b over a contiguous chunk of units.
+// One block of 1024 threads. gcnt[g][b] (group-major) becomes the exclusive
+// offset of (unit group g, bin b) in the bin-major order of all pairs.
+// Thread (chunk c, bin b) owns bin b over a contiguous chunk of groups.
 constexpr int kUScanThreads = 1024;
 
-__global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restrict__ ucnt,
-                                                             const uint32_t* __restrict__ uvis, int units,
+__global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restrict__ gcnt,
+                                                             const uint32_t* __restrict__ uvis, int units, int groups,
                                                              int nbins, int64_t cap, uint64_t* __restrict__ counters,
                                                              uint32_t* __restrict__ trange) {
   __shared__ uint32_t part[kUScanThreads];    // [chunk][bin] chunk sums, then chunk prefixes
@@ -593,14 +601,14 @@ __global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restric
   const int chunks = kUScanThreads / nbins;           // >= 1 as nbins <= kFastBins = kUScanThreads
   const int b = t % nbins, c = t / nbins;
   const bool active = c < chunks;
-  const int per = (units + chunks - 1) / chunks;
+  const int per = (groups + chunks - 1) / chunks;
   const int u0 = active ? c * per : 0;
-  const int u1 = active ? min(units, u0 + per) : 0;
+  const int u1 = active ? min(groups, u0 + per) : 0;
   uint32_t sum = 0;
   for (int ub = u0; ub < u1; ub += 16) {   // sixteen independent loads in flight
     uint32_t x[16];
 #pragma unroll
-    for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? ucnt[(int64_t)(ub + q) * nbins + b] : 0u;
+    for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? gcnt[(int64_t)(ub + q) * nbins + b] : 0u;
 #pragma unroll
     for (int q = 0; q < 16; q++) sum += x[q];
   }
@@ -654,10 +662,10 @@ __global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restric
     for (int ub = u0; ub < u1; ub += 16) {
       uint32_t x[16];
 #pragma unroll
-      for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? ucnt[(int64_t)(ub + q) * nbins + b] : 0u;
+      for (int q = 0; q < 16; q++) x[q] = ub + q < u1 ? gcnt[(int64_t)(ub + q) * nbins + b] : 0u;
 #pragma unroll
       for (int q = 0; q < 16; q++) {
-        if (ub + q < u1) ucnt[(int64_t)(ub + q) * nbins + b] = run;
+        if (ub + q < u1) gcnt[(int64_t)(ub + q) * nbins + b] = run;
         run += x[q];
       }
     }
@@ -673,7 +681,8 @@ __global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restric
 // index order.
 __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restrict__ gbin,
                                                             const uint32_t* __restrict__ key, int64_t n, int rounds,
-                                                            int nbins, int bin_bits, const uint32_t* __restrict__ uoff,
+                                                            int nbins, int bin_bits, const uint32_t* __restrict__ ucnt,
+                                                            const uint32_t* __restrict__ goff,
                                                             const uint64_t* __restrict__ counters,
                                                             uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
   constexpr int NW = kUnitThreads / 64;
@@ -690,9 +699,10 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restr
   for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
     if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
     uint2 g[kRoundGroup];
-    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, rounds - r0, lane, g);
 #pragma unroll
     for (int u = 0; u < kRoundGroup; u++) {
+      if (r0 + u >= rounds) break;   // uniform
       const uint32_t total = round_setup(R, g[u], lane);
       for (uint32_t q0 = 0; q0 < total; q0 += 64) {
         const uint32_t q = q0 + (uint32_t)lane;
@@ -705,9 +715,11 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restr
     }
   }
   __syncthreads();
-  const uint32_t* row = uoff + (int64_t)blockIdx.x * nbins;
+  const int grp = (int)blockIdx.x / kGroupUnits;
+  const uint32_t* grow = goff + (int64_t)grp * nbins;
   for (int b = t; b < nbins; b += kUnitThreads) {
-    uint32_t run = row[b];
+    uint32_t run = grow[b];
+    for (int u = grp * kGroupUnits; u < (int)blockIdx.x; u++) run += ucnt[(int64_t)u * nbins + b];
     for (int w = 0; w < NW; w++) {
       const uint32_t x = wc[w][b];
       wc[w][b] = run;
@@ -721,12 +733,13 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restr
     if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
     uint2 g[kRoundGroup];
     uint32_t kk[kRoundGroup];
-    load_group(gbin, wbase + (int64_t)r0 * 64, n, lane, g);
+    load_group(gbin, wbase + (int64_t)r0 * 64, n, rounds - r0, lane, g);
 #pragma unroll
     for (int u = 0; u < kRoundGroup; u++)
       kk[u] = g[u].x != kNoBin ? key[wbase + (int64_t)(r0 + u) * 64 + lane] : 0u;
 #pragma unroll
     for (int u = 0; u < kRoundGroup; u++) {
+      if (r0 + u >= rounds) break;   // uniform
       const uint32_t total = round_setup(R, g[u], lane);
       lkey[wave][lane] = kk[u];
       __builtin_amdgcn_wave_barrier();
@@ -1032,13 +1045,14 @@ hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
     uint2* gbin = at<uint2>(ws, p.gbin);
     uint32_t* ucnt = at<uint32_t>(ws, p.ucnt);
     uint32_t *pk = at<uint32_t>(ws, p.pkey), *pv = at<uint32_t>(ws, p.pval);
+    uint32_t* gcnt = at<uint32_t>(ws, p.gcnt);   // zeroed with the control region
     hipLaunchKernelGGL(k_unit_count, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin, p.n, p.unit_rounds,
-                       p.bins, ucnt, at<uint32_t>(ws, p.uvis));
-    hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kUScanThreads), 0, st, ucnt, at<uint32_t>(ws, p.uvis), p.units,
-                       p.bins, p.cap, counters, trange);
+                       p.bins, ucnt, gcnt, at<uint32_t>(ws, p.uvis));
+    hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kUScanThreads), 0, st, gcnt, at<uint32_t>(ws, p.uvis), p.units,
+                       p.groups, p.bins, p.cap, counters, trange);
     hipLaunchKernelGGL(k_unit_emit, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin,
-                       at<uint32_t>(ws, p.key), p.n, p.unit_rounds, p.bins, tile_bits(p.bins), ucnt, counters, pk,
-                       pv);
+                       at<uint32_t>(ws, p.key), p.n, p.unit_rounds, p.bins, tile_bits(p.bins), ucnt, gcnt, counters,
+                       pk, pv);
     hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)p.bins), dim3(kSortThreads), 0, st, pk, pv,
                        at<uint32_t>(ws, p.pkey2), at<uint32_t>(ws, p.pval2), trange, counters);
     return hipGetLastError();

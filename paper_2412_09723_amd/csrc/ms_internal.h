@@ -117,8 +117,9 @@ __device__ inline int job_of_block(const JobDesc* __restrict__ jobs, int njobs, 
 //    once, pairs are emitted in rank order and sorted by bin; list entries
 //    are depth ranks into the rank-order records rec.
 constexpr int kFastBins = 1024;
-constexpr int64_t kUnitEntries = 131072;   // bound on units x bins for the single-block scan
+constexpr int64_t kUnitEntries = 131072;   // bound on unit groups x bins for the single-block scan
 constexpr int kUnitThreads = 256;          // binning unit: 4 waves, each `unit_rounds` rounds of 64 Gaussians
+constexpr int kGroupUnits = 8;             // units per group (the scan works on group totals)
 
 struct Plan {
   int64_t n, cap;                   // n: virtual Gaussian slots (all jobs, padded)
@@ -127,15 +128,16 @@ struct Plan {
   int bin, bins, bshift;            // binning tiles: bin = tile << bshift; bins of all jobs
   int64_t pixels;                   // pixels of all jobs
   bool by_index;                    // per-bin sort path (see above)
-  int unit_rounds, units;           // per-bin path: rounds per wave of a unit, number of units
+  int unit_rounds, units, groups;   // per-bin path: rounds per wave of a unit, units, unit groups
   int scan_blocks_n;     // blocks of the length-n scans
   int pose_blocks;
   int rank_bits;         // bits of a depth rank (n - 1)
   bool packed;           // pairs stored as one word: tile << rank_bits | rank
   // byte offsets
   // control region (zeroed by one fill at every forward): counters, sort
-  // tickets, digit histograms, look-back words, bin ranges
-  size_t counters, tickets, digit_hist, lookback, trange, ctrl_end;
+  // tickets, digit histograms, look-back words, unit-group pair counts, bin
+  // ranges
+  size_t counters, tickets, digit_hist, lookback, gcnt, trange, ctrl_end;
   size_t jobs;           // device JobTable
   size_t key, rec_i, g2d, pose_part, tfinal, last, pkey, pval, pkey2, pval2;
   // per-bin path
