@@ -738,9 +738,15 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   float R = 0.f;
   uint32_t reduced = 0u;
   const int eaddr = (lane & 3) * 16 + (lane >> 2);
-  // Rows i < count (and 8 + i) of A hold the packed entry my[top - i]; rows
-  // whose entry index reaches `real` are padding (all zero).
-  auto flush = [&](int count, int top, int real) {
+  // Rows g < count of A (e values) and 8 + g (w values) belong to the packed
+  // entry held in lane g's `rowent`; only entries that some pixel of the wave
+  // composites get a row, so every product reduces contributing entries only.
+  // The product is formed transposed (moments x entries): lane (k, j) then
+  // holds moments 4k .. 4k+3 of row j, so lane g gathers its entry's six
+  // moments and four weighted sums from three other lanes with shuffles and
+  // issues the ten accumulations itself.
+  int rowent = 0;
+  auto flush = [&](int count) {
     wave_sync();
     float a1[16];
     const float4* e4 = reinterpret_cast<const float4*>(A + pj * kRow + pk * 16);
@@ -751,21 +757,16 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     }
     f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int st = 0; st < 16; st++) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st], Bv[st], d, 0, 0, 0);
-    wave_sync();
-    float* Dm = A;                     // the 16 x 16 product, row-major
-#pragma unroll
-    for (int r = 0; r < 4; r++) Dm[(4 * pk + r) * 16 + pj] = d[r];
-    wave_sync();
-    // one lane per Gaussian forms the ten sums; they go back to LDS so that
-    // each atomic instruction covers whole Gaussians (10 consecutive floats)
-    float* F = A + 256;                // [8][10], after the product
-    const int skip = top + 1 > real ? top + 1 - real : 0;   // leading padding rows
-    if (lane >= skip && lane < count) {
-      const Staged& sg = my[top - lane];
-      const float* m = Dm + lane * 16;
-      const float* u = Dm + (kGrp + lane) * 16 + 6;
-      const float S1 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
+    for (int st = 0; st < 16; st++) d = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[st], a1[st], d, 0, 0, 0);
+    // lane g < 8: moments 0-3 in d[0..3]; moments 4, 5 in lane 16 + g; weighted
+    // sums 6, 7 in lane 24 + g (d[2], d[3]) and 8, 9 in lane 40 + g (d[0], d[1])
+    const int l = lane & 7;
+    const float S4 = __shfl(d[0], 16 + l, 64), S5 = __shfl(d[1], 16 + l, 64);
+    const float W6 = __shfl(d[2], 24 + l, 64), W7 = __shfl(d[3], 24 + l, 64);
+    const float W8 = __shfl(d[0], 40 + l, 64), W9 = __shfl(d[1], 40 + l, 64);
+    if (lane < count) {
+      const Staged& sg = my[rowent];
+      const float S1 = d[0], Sx = d[1], Sy = d[2], Sxx = d[3], Sxy = S4, Syy = S5;
       const float U = ((-sg.geo.x) - 3.5f) + sg.geo.z;   // ui - X0 - 3.5 + uf
       const float V = ((-sg.geo.y) - 3.5f) + sg.geo.w;
       const float a = sg.conic.x, b = sg.conic.y, c = sg.conic.z;
@@ -773,32 +774,30 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       const float Edxx = Sxx - 2.f * U * Sx + U * U * S1;
       const float Edxy = Sxy - V * Sx - U * Sy + U * V * S1;
       const float Edyy = Syy - 2.f * V * Sy + V * V * S1;
-      float* f = F + lane * kGradFields;
+      float f[kGradFields];
       f[0] = S1;
       f[1] = a * Edx + b * Edy;
       f[2] = c * Edy;
       f[3] = a * Edxx + b * Edxy;
       f[4] = a * Edxy + b * Edyy;
       f[5] = c * Edyy;
-      f[6] = u[0];
-      f[7] = u[1];
-      f[8] = u[2];
-      f[9] = u[3];
-    }
-    wave_sync();
-    for (int idx = lane + skip * kGradFields; idx < count * kGradFields; idx += 64) {
-      const int g = idx / kGradFields, fi = idx - g * kGradFields;
-      const float v = F[idx];
-      if (v != 0.f) {
-        const Staged& sg = my[top - g];
-        const uint32_t pos = __float_as_uint(sg.misc.z) - 1u;   // list position
-        if (kAcc > 0 && pos < (uint32_t)kAcc)
-          atomicAdd(&acc[pos * kGradFields + fi], v);
-        else
-          unsafeAtomicAdd(g2d + (int64_t)__float_as_uint(sg.misc.y) * kGradFields + fi, v);
+      f[6] = W6;
+      f[7] = W7;
+      f[8] = W8;
+      f[9] = W9;
+      const uint32_t pos = __float_as_uint(sg.misc.z) - 1u;   // list position
+      if (kAcc > 0 && pos < (uint32_t)kAcc) {
+        float* dst = &acc[pos * kGradFields];
+#pragma unroll
+        for (int k = 0; k < kGradFields; k++)
+          if (f[k] != 0.f) atomicAdd(dst + k, f[k]);
+      } else {
+        float* dst = g2d + (int64_t)__float_as_uint(sg.misc.y) * kGradFields;
+#pragma unroll
+        for (int k = 0; k < kGradFields; k++)
+          if (f[k] != 0.f) unsafeAtomicAdd(dst + k, f[k]);
       }
     }
-    wave_sync();
   };
   for (uint32_t hi = Lmax; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
@@ -809,42 +808,48 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
                                                   packed);
     wave_sync();
     reduced += (uint32_t)packed;
-    for (int top = cnt - 1; top >= 0; top -= kGrp) {
-      const int gn = top + 1 < kGrp ? top + 1 : kGrp;   // a multiple of kBwdStep
-      for (int i = 0; i < gn; i += kBwdStep) {
-        float at[kBwdStep], alpha[kBwdStep], inv[kBwdStep], gcz[kBwdStep];
-        bool acc[kBwdStep];
+    int rows = 0;   // uniform: rows of A filled since the last product
+    for (int top = cnt - 1; top >= 0; top -= kBwdStep) {   // cnt is a multiple of kBwdStep
+      if (rows > kGrp - kBwdStep) {   // room for a whole step of entries
+        flush(rows);
+        rows = 0;
+      }
+      float at[kBwdStep], alpha[kBwdStep], inv[kBwdStep], gcz[kBwdStep];
+      bool acc[kBwdStep];
 #pragma unroll
-        for (int k = 0; k < kBwdStep; k++) {
-          const Staged& sk = my[top - i - k];
-          const float4 ge = sk.geo, cn = sk.conic, ap = sk.app;
-          const float2 mi = make_float2(sk.misc.x, sk.misc.z);
-          const float dx = (xf + ge.x) - ge.z;
-          const float dy = (yf + ge.y) - ge.w;
-          const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
-          const float t2 = cn.z * dy;
-          const float q = __builtin_fmaf(t1, t1, t2 * t2);
-          acc[k] = __float_as_uint(mi.y) <= L && q <= cn.w;   // list position < last
-          at[k] = __builtin_amdgcn_exp2f(ap.x - q);
-          alpha[k] = fminf(kAlphaMax, at[k]);
-          inv[k] = __builtin_amdgcn_rcpf(1.f - alpha[k]);
-          gcz[k] = __builtin_fmaf(G0, ap.z, __builtin_fmaf(G1, ap.w, __builtin_fmaf(G2, mi.x, GD * ap.y)));
-        }
-        // back-to-front recursion, predicated on acceptance
+      for (int k = 0; k < kBwdStep; k++) {
+        const Staged& sk = my[top - k];
+        const float4 ge = sk.geo, cn = sk.conic, ap = sk.app;
+        const float2 mi = make_float2(sk.misc.x, sk.misc.z);
+        const float dx = (xf + ge.x) - ge.z;
+        const float dy = (yf + ge.y) - ge.w;
+        const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
+        const float t2 = cn.z * dy;
+        const float q = __builtin_fmaf(t1, t1, t2 * t2);
+        acc[k] = __float_as_uint(mi.y) <= L && q <= cn.w;   // list position < last
+        at[k] = __builtin_amdgcn_exp2f(ap.x - q);
+        alpha[k] = fminf(kAlphaMax, at[k]);
+        inv[k] = __builtin_amdgcn_rcpf(1.f - alpha[k]);
+        gcz[k] = __builtin_fmaf(G0, ap.z, __builtin_fmaf(G1, ap.w, __builtin_fmaf(G2, mi.x, GD * ap.y)));
+      }
+      // back-to-front recursion, predicated on acceptance
 #pragma unroll
-        for (int k = 0; k < kBwdStep; k++) {
-          const float Tk = T * inv[k];
-          const float w = alpha[k] * Tk;
-          const float dalpha = __builtin_fmaf(Tk, gcz[k], -(R - GST) * inv[k]);
-          const float e = at[k] > kAlphaMax ? 0.f : dalpha * at[k];
-          A[(i + k) * kRow + eaddr] = acc[k] ? e : 0.f;
-          A[(kGrp + i + k) * kRow + eaddr] = acc[k] ? w : 0.f;
-          R = acc[k] ? __builtin_fmaf(gcz[k], w, R) : R;
-          T = acc[k] ? Tk : T;
+      for (int k = 0; k < kBwdStep; k++) {
+        const float Tk = T * inv[k];
+        const float w = alpha[k] * Tk;
+        const float dalpha = __builtin_fmaf(Tk, gcz[k], -(R - GST) * inv[k]);
+        const float e = at[k] > kAlphaMax ? 0.f : dalpha * at[k];
+        R = acc[k] ? __builtin_fmaf(gcz[k], w, R) : R;
+        T = acc[k] ? Tk : T;
+        if (__builtin_amdgcn_ballot_w64(acc[k]) != 0) {   // uniform
+          A[rows * kRow + eaddr] = acc[k] ? e : 0.f;
+          A[(kGrp + rows) * kRow + eaddr] = acc[k] ? w : 0.f;
+          if (lane == rows) rowent = top - k;
+          rows++;
         }
       }
-      flush(gn, top, packed);
     }
+    if (rows > 0) flush(rows);
     hi = lo;
   }
   if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
