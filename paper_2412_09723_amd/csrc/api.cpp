@@ -300,9 +300,7 @@ int32_t run_forward(JobTable& t, const ms_options* opts, void* workspace, size_t
   int32_t s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   char* ws = (char*)workspace;
-  hipError_t e = launch_set_jobs(t, p, ws, st);
-  if (e == hipSuccess)
-    e = launch_fill_u32(at<uint32_t>(ws, p.counters), 0u, (int64_t)((p.ctrl_end - p.counters) / 4), st);
+  hipError_t e = launch_setup(t, p, ws, at<uint32_t>(ws, p.counters), (int64_t)((p.ctrl_end - p.counters) / 4), st);
   if (e != hipSuccess) return hip_fail(e, "counters");
   {
     StageTimer tm(MS_STAGE_PROJECT, st);
@@ -333,14 +331,14 @@ int32_t run_backward(JobTable& t, const ms_options* opts, void* workspace, size_
   char* ws = (char*)workspace;
   bool any_pose = false;
   for (int j = 0; j < t.njobs; j++) any_pose |= !(t.job[j].flags & MS_FLAG_NO_POSE_GRAD);
-  hipError_t e = launch_set_jobs(t, p, ws, st);
+  // the global depth-sort path zeroes its accumulator rows here; on the
+  // per-bin path the rows of the visible Gaussians are zeroed by the
+  // projection and again by the projection adjoint after use
+  hipError_t e = launch_setup(t, p, ws, at<uint32_t>(ws, p.g2d), p.by_index ? 0 : (int64_t)kGradFields * p.n, st);
   if (e != hipSuccess) return hip_fail(e, "job table");
   {
     StageTimer tm(MS_STAGE_COMPOSITE_BWD, st);
-    // per-bin path: the accumulator rows of the visible Gaussians are zeroed
-    // by the projection and again by the projection adjoint after use
-    if (!p.by_index) e = launch_fill_u32(at<uint32_t>(ws, p.g2d), 0u, (int64_t)kGradFields * p.n, st);
-    if (e == hipSuccess) e = launch_composite_bwd(p, opts->wave_batch, opts->flags, ws, st);
+    e = launch_composite_bwd(p, opts->wave_batch, opts->flags, ws, st);
   }
   if (e != hipSuccess) return hip_fail(e, "composite backward");
   {
@@ -609,7 +607,9 @@ int32_t ms_profiler_create(uint32_t stage_mask, int32_t capacity, ms_profiler** 
   p->ev.resize(2 * (size_t)capacity);
   p->stage.resize(capacity);
   for (auto& e : p->ev) {
-    hipError_t r = hipEventCreate(&e);
+    // timing-only events: no system-scope fence when they complete, which
+    // would otherwise write back and invalidate caches between the stages
+    hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     if (r != hipSuccess) {
       e = nullptr;
       ms_profiler_destroy(p);

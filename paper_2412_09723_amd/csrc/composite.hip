@@ -156,7 +156,7 @@ constexpr int kFwdGroup = 4;   // entries evaluated together in the forward
 #define MS_FWD_WAVES 8
 #endif
 #ifndef MS_BWDM_WAVES
-#define MS_BWDM_WAVES 5
+#define MS_BWDM_WAVES 4
 #endif
 
 template <int TILE, int WB>
@@ -643,6 +643,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 // pixels per step -- yields both sets of sums. One lane per Gaussian then
 // forms the ten sums and the wave issues them as whole-Gaussian atomics.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kGrp = 8;                        // Gaussians per product
 constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
 constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
@@ -706,28 +707,35 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     Tf = tfinal[J.pix0 + pix];
     L = last[J.pix0 + pix];
   }
-  // B operand (constant per wave): lane holds B[k = lane / 16][j = lane % 16]
-  // of step s, i.e. column j for pixel 4 s + k.
+  // First product operand (constant per wave): the moment rows M^T. Lane
+  // (k, j) = (lane / 16, lane % 16) holds row j at the pixels 32 h + 8 k + t,
+  // t < 8, of the two 32-pixel halves h, split into bf16 high and low parts
+  // (the monomial rows are exact in bf16; the upstream rows are not).
   const int pk = lane >> 4, pj = lane & 15;
-  float Bv[16];
+  bf16x8 Mhi[2], Mlo[2];
   A[lane * 4 + 0] = G0;
   A[lane * 4 + 1] = G1;
   A[lane * 4 + 2] = G2;
   A[lane * 4 + 3] = GD;
   wave_sync();
 #pragma unroll
-  for (int st = 0; st < 16; st++) {
-    const int p = 4 * st + pk;
-    const float px = (float)(p & 7) - 3.5f, py = (float)(p >> 3) - 3.5f;
-    float m = 0.f;
-    m = pj == 0 ? 1.f : m;
-    m = pj == 1 ? px : m;
-    m = pj == 2 ? py : m;
-    m = pj == 3 ? px * px : m;
-    m = pj == 4 ? px * py : m;
-    m = pj == 5 ? py * py : m;
-    m = (pj >= 6 && pj < 10) ? A[p * 4 + (pj - 6)] : m;
-    Bv[st] = m;
+  for (int h = 0; h < 2; h++) {
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      const int p = 32 * h + 8 * pk + t;
+      const float px = (float)(p & 7) - 3.5f, py = (float)(p >> 3) - 3.5f;
+      float m = 0.f;
+      m = pj == 0 ? 1.f : m;
+      m = pj == 1 ? px : m;
+      m = pj == 2 ? py : m;
+      m = pj == 3 ? px * px : m;
+      m = pj == 4 ? px * py : m;
+      m = pj == 5 ? py * py : m;
+      m = (pj >= 6 && pj < 10) ? A[p * 4 + (pj - 6)] : m;
+      const __bf16 mh = (__bf16)m;
+      Mhi[h][t] = mh;
+      Mlo[h][t] = (__bf16)(m - (float)mh);
+    }
   }
   wave_sync();
   const uint32_t Lmax = __builtin_amdgcn_readfirstlane(wave_max_u32(L));
@@ -737,7 +745,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   float T = Tf;
   float R = 0.f;
   uint32_t reduced = 0u;
-  const int eaddr = (lane & 3) * 16 + (lane >> 2);
+  const int eaddr = lane;   // pixel-contiguous rows of A
   // Rows g < count of A (e values) and 8 + g (w values) belong to the packed
   // entry held in lane g's `rowent`; only entries that some pixel of the wave
   // composites get a row, so every product reduces contributing entries only.
@@ -748,16 +756,26 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   int rowent = 0;
   auto flush = [&](int count) {
     wave_sync();
-    float a1[16];
-    const float4* e4 = reinterpret_cast<const float4*>(A + pj * kRow + pk * 16);
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const float4 ev = e4[q];
-      a1[4 * q] = ev.x; a1[4 * q + 1] = ev.y; a1[4 * q + 2] = ev.z; a1[4 * q + 3] = ev.w;
-    }
+    // second operand: lane (k, j) holds row j of A at the pixels 32 h + 8 k + t;
+    // three bf16 products (hi.hi + hi.lo + lo.hi) per half keep about 16
+    // significant bits of every term
     f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int st = 0; st < 16; st++) d = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[st], a1[st], d, 0, 0, 0);
+    for (int h = 0; h < 2; h++) {
+      const float4* r4 = reinterpret_cast<const float4*>(A + pj * kRow + 32 * h + 8 * pk);
+      const float4 x0 = r4[0], x1 = r4[1];
+      const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      bf16x8 rh, rl;
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        const __bf16 vh = (__bf16)v[t];
+        rh[t] = vh;
+        rl[t] = (__bf16)(v[t] - (float)vh);
+      }
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mhi[h], rh, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mhi[h], rl, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mlo[h], rh, d, 0, 0, 0);
+    }
     // lane g < 8: moments 0-3 in d[0..3]; moments 4, 5 in lane 16 + g; weighted
     // sums 6, 7 in lane 24 + g (d[2], d[3]) and 8, 9 in lane 40 + g (d[0], d[1])
     const int l = lane & 7;

@@ -178,8 +178,9 @@ inline int tile_bits(int tiles) {
 
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns the launch status. The job
-// table lives in the workspace (written by launch_set_jobs).
-hipError_t launch_set_jobs(const JobTable& t, const Plan& p, char* ws, hipStream_t st);
+// table lives in the workspace (written by launch_setup).
+// Writes the job table into the workspace and zeroes `count` words at `zero`.
+hipError_t launch_setup(const JobTable& t, const Plan& p, char* ws, uint32_t* zero, int64_t count, hipStream_t st);
 hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st);
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st);
 hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);

@@ -37,10 +37,17 @@ __global__ void k_zero_f32(float* p) { *p = 0.f; }
 
 // Copies a job table (passed by value in the kernel arguments) into the
 // workspace, so that it is stream-ordered with the launches that read it.
-__global__ void __launch_bounds__(256) k_set_jobs(JobTable t, JobTable* __restrict__ dst) {
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(&t);
-  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-  for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += blockDim.x) d[i] = src[i];
+// Writes the job table (passed by value) into the workspace and zeroes
+// `count` words at `zero` (the first launch of a pass: one launch for both).
+__global__ void __launch_bounds__(256) k_setup(JobTable t, JobTable* __restrict__ dst, uint32_t* __restrict__ zero,
+                                               int64_t count) {
+  if (blockIdx.x == 0) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&t);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += blockDim.x) d[i] = src[i];
+  }
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x)
+    zero[j] = 0u;
 }
 
 // Adam on the twist xi = (rho, phi), then V <- exp(-step^) V in binary64.
@@ -105,9 +112,12 @@ hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, i
   return hipGetLastError();
 }
 
-hipError_t launch_set_jobs(const JobTable& t, const Plan& p, char* ws, hipStream_t st) {
+hipError_t launch_setup(const JobTable& t, const Plan& p, char* ws, uint32_t* zero, int64_t count, hipStream_t st) {
   static_assert(sizeof(JobTable) % 4 == 0, "job table is copied in 32-bit words");
-  hipLaunchKernelGGL(k_set_jobs, dim3(1), dim3(256), 0, st, t, at<JobTable>(ws, p.jobs));
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(256), 0, st, t, at<JobTable>(ws, p.jobs), zero, count);
   return hipGetLastError();
 }
 
