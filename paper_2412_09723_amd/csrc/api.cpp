@@ -581,10 +581,13 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
   const int64_t P = (int64_t)intr->width * intr->height;
   hipError_t e = hipSuccess;
   if (loss) e = launch_zero_scalar(loss, st);
-  if (e == hipSuccess) e = launch_l1_grad(pred->rgb, target->rgb, grad->rgb, 3 * P, w_rgb / (3.0f * (float)P), loss, st);
-  if (e == hipSuccess) e = launch_l1_grad(pred->depth, target->depth, grad->depth, P, w_depth / (float)P, loss, st);
-  if (e == hipSuccess)
-    e = launch_l1_grad(pred->silhouette, target->silhouette, grad->silhouette, P, w_sil / (float)P, loss, st);
+  if (e == hipSuccess) {
+    const float* pr[3] = {pred->rgb, pred->depth, pred->silhouette};
+    const float* tg[3] = {target->rgb, target->depth, target->silhouette};
+    float* gr[3] = {grad->rgb, grad->depth, grad->silhouette};
+    const float sc[3] = {w_rgb / (3.0f * (float)P), w_depth / (float)P, w_sil / (float)P};
+    e = launch_l1_grad(pr, tg, gr, P, sc, loss, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "l1 loss");
   return MS_OK;
 }

@@ -187,8 +187,10 @@ hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, c
 hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);
 hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStream_t st);
-hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, int64_t count, float scale,
-                          float* loss, hipStream_t st);
+// The L1 loss gradient of the rgb (3P), depth (P) and silhouette (P) planes
+// in one launch.
+hipError_t launch_l1_grad(const float* const pred[3], const float* const target[3], float* const grad[3], int64_t P,
+                          const float scale[3], float* loss, hipStream_t st);
 hipError_t launch_zero_scalar(float* p, hipStream_t st);
 hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,
                             hipStream_t st);

@@ -207,10 +207,33 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
                                                      const uint64_t* __restrict__ counters,
                                                      double* __restrict__ pose_part) {
   __shared__ double red[12][256 / 64];
+  __shared__ int s_list[256];
+  __shared__ int s_wcnt[256 / 64];
   const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
-  const int64_t li = (int64_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x;   // index within the job
-  const int64_t i = J.g0 + li;                                                     // virtual index
   const int64_t n = J.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // The block's visible Gaussians are packed onto its first threads, so the
+  // long binary64 path runs on as few waves as the block has visible
+  // Gaussians; invisible ones only get zero gradients from their own thread.
+  const int64_t li0 = (int64_t)((int)blockIdx.x - J.block0) * 256;   // block's first index within the job
+  const int64_t li_own = li0 + threadIdx.x;
+  const bool own_valid = li_own < n;
+  const bool own_vis = own_valid && key[J.g0 + li_own] != 0xFFFFFFFFu;
+  const uint64_t vm = __ballot(own_vis);
+  if (lane == 0) s_wcnt[wave] = __popcll(vm);
+  __syncthreads();
+  int vbase = 0, nvis = 0;
+  for (int w = 0; w < 256 / 64; w++) {
+    if (w < wave) vbase += s_wcnt[w];
+    nvis += s_wcnt[w];
+  }
+  if (own_vis)
+    s_list[vbase + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u))] =
+        (int)threadIdx.x;
+  __syncthreads();
+  const bool heavy = (int)threadIdx.x < nvis;
+  const int64_t li = heavy ? li0 + s_list[threadIdx.x] : li_own;   // index within the job (heavy path)
+  const int64_t i = J.g0 + li;                                       // virtual index
   const float* __restrict__ means = J.means;
   const float* __restrict__ scales = J.scales;
   const float* __restrict__ quats = J.quats;
@@ -225,8 +248,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const bool overflow = counters[C_OVERFLOW] != 0;
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
   float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
-  const bool valid = li < n;
-  if (valid && key[i] != 0xFFFFFFFFu) {
+  if (heavy) {
     // accumulator row: by depth rank (global sort path) or by index (per-bin
     // path, where the row is cleared after use for the next backward)
     const int64_t r = rank_of ? (int64_t)rank_of[i] : i;
@@ -367,7 +389,18 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       go = nanv;
     }
   }
-  if (valid && map_grads) {
+  // heavy threads write their visible Gaussian's gradients and the owners of
+  // invisible ones write zeros (a thread can do both): every index once
+  if (map_grads && own_valid && !own_vis) {
+    for (int k = 0; k < 3; k++) {
+      J.gm[k * n + li_own] = 0.f;
+      J.gs[k * n + li_own] = 0.f;
+      J.gc[k * n + li_own] = 0.f;
+    }
+    for (int k = 0; k < 4; k++) J.gq[k * n + li_own] = 0.f;
+    J.go[li_own] = 0.f;
+  }
+  if (map_grads && heavy) {
     for (int k = 0; k < 3; k++) {
       J.gm[k * n + li] = gm[k];
       J.gs[k * n + li] = gs[k];
@@ -377,17 +410,21 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     J.go[li] = go;
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
-  // block reduction of the 12 pose partials: wave shuffle, then LDS
-  double v[12];
-  for (int a = 0; a < 3; a++) {
-    for (int b = 0; b < 3; b++) v[3 * a + b] = GR[a][b];
-    v[9 + a] = Gt[a];
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < 12; k++) {
-    double x = v[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) red[k][wave] = x;
+  // block reduction of the 12 pose partials: wave shuffle, then LDS (waves
+  // past the visible count hold zeros)
+  if (wave * 64 < nvis) {
+    double v[12];
+    for (int a = 0; a < 3; a++) {
+      for (int b = 0; b < 3; b++) v[3 * a + b] = GR[a][b];
+      v[9 + a] = Gt[a];
+    }
+    for (int k = 0; k < 12; k++) {
+      double x = v[k];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) red[k][wave] = x;
+    }
+  } else if (lane < 12) {
+    red[lane][wave] = 0.0;
   }
   __syncthreads();
   if (threadIdx.x < 12) {
@@ -399,10 +436,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
 
 // One block per job: folds the job's per-block pose partials in a fixed
 // order and writes dL/d[R|t] and the left-twist gradient.
-__global__ void __launch_bounds__(256) k_pose_final(const JobDesc* __restrict__ jobs,
-                                                    const double* __restrict__ part,
-                                                    const uint64_t* __restrict__ counters) {
-  __shared__ double red[12][256 / 64];
+constexpr int kPoseThreads = 1024;
+
+__global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __restrict__ jobs,
+                                                             const double* __restrict__ part,
+                                                             const uint64_t* __restrict__ counters) {
+  __shared__ double red[12][kPoseThreads / 64];
   __shared__ double tot[12];
   const JobDesc& J = jobs[blockIdx.x];
   if (J.flags & MS_FLAG_NO_POSE_GRAD) return;   // uniform over the block
@@ -488,7 +527,7 @@ hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_
     if (e != hipSuccess) return e;
   }
   if (any_pose) {
-    hipLaunchKernelGGL(k_pose_final, dim3((unsigned)p.njobs), dim3(256), 0, st, jobs, at<double>(ws, p.pose_part),
+    hipLaunchKernelGGL(k_pose_final, dim3((unsigned)p.njobs), dim3(kPoseThreads), 0, st, jobs, at<double>(ws, p.pose_part),
                        at<uint64_t>(ws, p.counters));
     return hipGetLastError();
   }

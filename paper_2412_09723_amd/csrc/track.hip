@@ -10,17 +10,29 @@ namespace {
 
 constexpr int kLossThreads = 256;
 
-// grad = w * sign(pred - target) / count for each plane; optional loss sum
-// (sum of w |pred - target| / count) accumulated with one atomic per block.
-__global__ void __launch_bounds__(kLossThreads) k_l1_grad(const float* __restrict__ pred,
-                                                          const float* __restrict__ target, float* __restrict__ grad,
-                                                          int64_t count, float scale, float* __restrict__ loss) {
+// The three planes of one L1 loss gradient in one launch: for the flat
+// index j over rgb (3P entries), depth (P) and silhouette (P),
+// grad = scale * sign(pred - target) with the plane's scale; optional loss
+// sum (sum of scale |pred - target|) accumulated with one atomic per block.
+struct L1Planes {
+  const float* pred[3];
+  const float* target[3];
+  float* grad[3];
+  float scale[3];
+  int64_t end[3];   // cumulative flat end of each plane
+};
+
+__global__ void __launch_bounds__(kLossThreads) k_l1_grad(L1Planes L, float* __restrict__ loss) {
   __shared__ float red[kLossThreads / 64];
   float acc = 0.f;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
-    const float d = pred[j] - target[j];
-    grad[j] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-    acc += fabsf(d) * scale;
+  const int64_t total = L.end[2];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+    const int pl = j < L.end[0] ? 0 : (j < L.end[1] ? 1 : 2);
+    const int64_t o = pl == 0 ? j : j - L.end[pl - 1];
+    const float d = L.pred[pl][o] - L.target[pl][o];
+    const float sc = L.scale[pl];
+    L.grad[pl][o] = d > 0.f ? sc : (d < 0.f ? -sc : 0.f);
+    acc += fabsf(d) * sc;
   }
   if (!loss) return;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -35,8 +47,6 @@ __global__ void __launch_bounds__(kLossThreads) k_l1_grad(const float* __restric
 
 __global__ void k_zero_f32(float* p) { *p = 0.f; }
 
-// Copies a job table (passed by value in the kernel arguments) into the
-// workspace, so that it is stream-ordered with the launches that read it.
 // Writes the job table (passed by value) into the workspace and zeroes
 // `count` words at `zero` (the first launch of a pass: one launch for both).
 __global__ void __launch_bounds__(256) k_setup(JobTable t, JobTable* __restrict__ dst, uint32_t* __restrict__ zero,
@@ -101,14 +111,24 @@ __global__ void k_pose_adam(float* __restrict__ viewmat, const float* __restrict
 
 }  // namespace
 
-hipError_t launch_l1_grad(const float* pred, const float* target, float* grad, int64_t count, float scale,
-                          float* loss, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  int64_t blocks = (count + kLossThreads - 1) / kLossThreads;
-  const int64_t max_blocks = loss ? 128 : 2048;   // one atomic per block on the loss
+hipError_t launch_l1_grad(const float* const pred[3], const float* const target[3], float* const grad[3], int64_t P,
+                          const float scale[3], float* loss, hipStream_t st) {
+  if (P <= 0) return hipSuccess;
+  L1Planes L;
+  const int64_t counts[3] = {3 * P, P, P};
+  int64_t run = 0;
+  for (int k = 0; k < 3; k++) {
+    L.pred[k] = pred[k];
+    L.target[k] = target[k];
+    L.grad[k] = grad[k];
+    L.scale[k] = scale[k];
+    run += counts[k];
+    L.end[k] = run;
+  }
+  int64_t blocks = (run + kLossThreads - 1) / kLossThreads;
+  const int64_t max_blocks = loss ? 256 : 4096;   // one atomic per block on the loss
   if (blocks > max_blocks) blocks = max_blocks;
-  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, pred, target, grad, count, scale,
-                     loss);
+  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, L, loss);
   return hipGetLastError();
 }
 
