@@ -273,7 +273,8 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     for (int a = 0; a < 3; a++) p[a] = P.R[a][0] * mu[0] + P.R[a][1] * mu[1] + P.R[a][2] * mu[2] + P.t[a];
     const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const double qnorm = sqrt(qn2);
-    const double w = q[0] / qnorm, x = q[1] / qnorm, y = q[2] / qnorm, z = q[3] / qnorm;
+    const double iq = 1.0 / qnorm;   // reciprocals: the adjoint needs no correctly rounded quotients
+    const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
     const double Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
                              {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
                              {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
@@ -299,21 +300,23 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     const double s1 = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
     const double s2 = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + kDilation;
     const double d = s0 * s2 - s1 * s1;
-    const double l11 = sqrt(s2 / d), l22 = 1.0 / sqrt(s2);
-    const double l12 = -s1 / sqrt(d * s2);
+    const double sqd = sqrt(d), sqs2 = sqrt(s2);
+    const double r_d = 1.0 / d, r_s2 = 1.0 / s2, r_sqd = 1.0 / sqd, r_sqs2 = 1.0 / sqs2;
+    const double l11 = sqs2 * r_sqd, l22 = r_sqs2;
+    const double l12 = -s1 * (r_sqd * r_sqs2);
     const double a_ = kKappa * l11, b_ = kKappa * l12, c_ = kKappa * l22;
     // record-level gradients; g_t = -2 ln2 t e collected as P-sums
     const double c2 = -2.0 * kLn2;
     const double gu = -a_ * c2 * P1;
     const double gv = -(b_ * c2 * P1 + c_ * c2 * P2);
     const double gl11 = kKappa * c2 * P1x, gl12 = kKappa * c2 * P1y, gl22 = kKappa * c2 * P2y;
-    go = (float)(E / o);
+    go = (float)(E * (1.0 / o));
     // Cholesky factors -> (S00, S01, S11)
-    const double dsq = d * sqrt(d * s2);
-    const double gS0 = gl11 * (-0.5 * l11 * s2 / d) + gl12 * (-0.5 * l12 * s2 / d);
-    const double gS1 = gl11 * (l11 * s1 / d) + gl12 * (-(s0 * s2) / dsq);
-    const double gS2 = gl11 * (0.5 * l11 * (1.0 / s2 - s0 / d)) + gl12 * (-0.5 * l12 * (s0 / d + 1.0 / s2)) +
-                       gl22 * (-0.5 * l22 / s2);
+    const double r_dsq = r_d * r_sqd * r_sqs2;   // 1 / (d sqrt(d s2))
+    const double gS0 = gl11 * (-0.5 * l11 * s2 * r_d) + gl12 * (-0.5 * l12 * s2 * r_d);
+    const double gS1 = gl11 * (l11 * s1 * r_d) + gl12 * (-(s0 * s2) * r_dsq);
+    const double gS2 = gl11 * (0.5 * l11 * (r_s2 - s0 * r_d)) + gl12 * (-0.5 * l12 * (s0 * r_d + r_s2)) +
+                       gl22 * (-0.5 * l22 * r_s2);
     // S = V V^T + 0.3 I
     double gV0[3], gV1[3];
     for (int k = 0; k < 3; k++) {
@@ -353,10 +356,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     double gz = 2 * (-2 * z * gRq[0][0] - w * gRq[0][1] + x * gRq[0][2] + w * gRq[1][0] - 2 * z * gRq[1][1] +
                      y * gRq[1][2] + x * gRq[2][0] + y * gRq[2][1]);
     const double dot = gw * w + gx * x + gy * y + gz * z;
-    gq[0] = (float)((gw - w * dot) / qnorm);
-    gq[1] = (float)((gx - x * dot) / qnorm);
-    gq[2] = (float)((gy - y * dot) / qnorm);
-    gq[3] = (float)((gz - z * dot) / qnorm);
+    gq[0] = (float)((gw - w * dot) * iq);
+    gq[1] = (float)((gx - x * dot) * iq);
+    gq[2] = (float)((gy - y * dot) * iq);
+    gq[3] = (float)((gz - z * dot) * iq);
     // J(p), (u, v)(p), direct depth
     double gp[3] = {0, 0, GZ};
     gp[2] += gj00 * (-fx * rz * rz) + gj11 * (-fy * rz * rz);
