@@ -206,7 +206,6 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
                                                      float* __restrict__ g2d,
                                                      const uint64_t* __restrict__ counters,
                                                      double* __restrict__ pose_part) {
-  __shared__ double red[12][256 / 64];
   __shared__ int s_list[256];
   __shared__ int s_wcnt[256 / 64];
   const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
@@ -413,26 +412,27 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     J.go[li] = go;
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
-  // block reduction of the 12 pose partials: wave shuffle, then LDS (waves
-  // past the visible count hold zeros)
-  if (wave * 64 < nvis) {
-    double v[12];
+  // block reduction of the 12 pose partials of the visible threads: through
+  // LDS, in a fixed order (16 partial sums of 16 threads each, then their sum)
+  __shared__ double pr[12][256];
+  __shared__ double ps[12][16];
+  if (heavy) {
     for (int a = 0; a < 3; a++) {
-      for (int b = 0; b < 3; b++) v[3 * a + b] = GR[a][b];
-      v[9 + a] = Gt[a];
+      for (int b = 0; b < 3; b++) pr[3 * a + b][threadIdx.x] = GR[a][b];
+      pr[9 + a][threadIdx.x] = Gt[a];
     }
-    for (int k = 0; k < 12; k++) {
-      double x = v[k];
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-      if (lane == 0) red[k][wave] = x;
-    }
-  } else if (lane < 12) {
-    red[lane][wave] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12 * 16) {
+    const int k = threadIdx.x >> 4, seg = threadIdx.x & 15;
+    double acc = 0.0;
+    for (int j = seg * 16; j < seg * 16 + 16 && j < nvis; j++) acc += pr[k][j];
+    ps[k][seg] = acc;
   }
   __syncthreads();
   if (threadIdx.x < 12) {
     double acc = 0.0;
-    for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) acc += red[threadIdx.x][wv];
+    for (int q = 0; q < 16; q++) acc += ps[threadIdx.x][q];
     pose_part[(int64_t)blockIdx.x * 12 + threadIdx.x] = acc;
   }
 }
