@@ -910,11 +910,23 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_sort(uint32_t* __restrict_
       const int nd = 1 << dbits;
       sort_rank(S, k, rk, ipt, seg, shift, dbits);
       __syncthreads();
+      // digit t: the waves' counts stay in registers between the scan and
+      // the write of the waves' starts
+      uint32_t wc[kSortWaves];
       uint32_t total = 0;
-      if (t < nd) total = sort_wave_starts(S, t, 0u);
-      const uint32_t excl = digit_exclusive_scan(S, total);
-      if (t < nd)
-        for (int w = 0; w < kSortWaves; w++) S.wcnt[w][t] += excl;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; w++) {
+        wc[w] = t < nd ? S.wcnt[w][t] : 0u;
+        total += wc[w];
+      }
+      uint32_t run = digit_exclusive_scan(S, total);
+      if (t < nd) {
+#pragma unroll
+        for (int w = 0; w < kSortWaves; w++) {
+          S.wcnt[w][t] = run;
+          run += wc[w];
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < kSortItems; r++) {

@@ -439,12 +439,13 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
 
 // One block per job: folds the job's per-block pose partials in a fixed
 // order and writes dL/d[R|t] and the left-twist gradient.
-constexpr int kPoseThreads = 1024;
+constexpr int kPoseThreads = 256;
 
 __global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __restrict__ jobs,
                                                              const double* __restrict__ part,
                                                              const uint64_t* __restrict__ counters) {
-  __shared__ double red[12][kPoseThreads / 64];
+  __shared__ double pr[12][kPoseThreads];
+  __shared__ double ps[12][16];
   __shared__ double tot[12];
   const JobDesc& J = jobs[blockIdx.x];
   if (J.flags & MS_FLAG_NO_POSE_GRAD) return;   // uniform over the block
@@ -453,20 +454,24 @@ __global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __re
   float* gtwist = J.gtwist;
   const int nblocks = J.n > 0 ? J.blocks : 0;
   part += (int64_t)J.block0 * 12;
+  // thread t folds partials t, t + 256, ...; then 16 sums of 16 threads and
+  // their sum, all in a fixed order
   double acc[12];
   for (int k = 0; k < 12; k++) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+  for (int b = threadIdx.x; b < nblocks; b += kPoseThreads)
     for (int k = 0; k < 12; k++) acc[k] += part[(int64_t)b * 12 + k];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < 12; k++) {
-    double x = acc[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) red[k][wave] = x;
+  for (int k = 0; k < 12; k++) pr[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 12 * 16) {
+    const int k = threadIdx.x >> 4, seg = threadIdx.x & 15;
+    double a = 0.0;
+    for (int j = seg * 16; j < seg * 16 + 16; j++) a += pr[k][j];
+    ps[k][seg] = a;
   }
   __syncthreads();
   if (threadIdx.x < 12) {
     double a = 0.0;
-    for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) a += red[threadIdx.x][wv];
+    for (int q = 0; q < 16; q++) a += ps[threadIdx.x][q];
     tot[threadIdx.x] = a;
   }
   __syncthreads();
