@@ -63,19 +63,53 @@ __global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__
                                                      uint32_t* __restrict__ vis, uint32_t* __restrict__ ntiles,
                                                      int32_t* __restrict__ rank_of, uint4* __restrict__ rec_i,
                                                      uint2* __restrict__ gbin, float* __restrict__ g2d) {
+  __shared__ int s_list[256];
+  __shared__ int s_wcnt[256 / 64];
   const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
-  const int64_t li = (int64_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x;   // index within the job
-  const int64_t i = J.g0 + li;                                                     // virtual index
-  key[i] = 0xFFFFFFFFu;
-  if (gbin) {
-    gbin[i] = make_uint2(kNoBin, 0u);
-  } else {
-    vis[i] = 0u;
-    ntiles[i] = 0u;
-    rank_of[i] = -1;
-  }
-  if (li >= J.n) return;
   const int64_t n = J.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto set_culled = [&](int64_t iv) {
+    key[iv] = 0xFFFFFFFFu;
+    if (gbin) {
+      gbin[iv] = make_uint2(kNoBin, 0u);
+    } else {
+      vis[iv] = 0u;
+      ntiles[iv] = 0u;
+      rank_of[iv] = -1;
+    }
+  };
+  // The Gaussians in front of the near plane are packed onto the block's
+  // first threads, so the binary64 projection runs on as few waves as there
+  // are such Gaussians. The owner of any other slot marks it culled.
+  const int64_t li0 = (int64_t)((int)blockIdx.x - J.block0) * 256;   // block's first index within the job
+  const int64_t li_own = li0 + threadIdx.x;
+  bool front = false;
+  if (li_own < n) {
+    Pose P0;
+    load_pose(J.viewmat, P0);
+    const double m0 = J.means[li_own], m1 = J.means[n + li_own], m2 = J.means[2 * n + li_own];
+    double pz[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) pz[r] = ((P0.R[r][0] * m0 + P0.R[r][1] * m1) + P0.R[r][2] * m2) + P0.t[r];
+    front = pz[2] > (double)near_z && isfinite(pz[0]) && isfinite(pz[1]) && isfinite(pz[2]);
+  }
+  if (!front) set_culled(J.g0 + li_own);
+  const uint64_t fm = __ballot(front);
+  if (lane == 0) s_wcnt[wave] = __popcll(fm);
+  __syncthreads();
+  int fbase = 0, nfront = 0;
+  for (int w = 0; w < 256 / 64; w++) {
+    if (w < wave) fbase += s_wcnt[w];
+    nfront += s_wcnt[w];
+  }
+  if (front)
+    s_list[fbase + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u))] =
+        (int)threadIdx.x;
+  __syncthreads();
+  if ((int)threadIdx.x >= nfront) return;
+  const int64_t li = li0 + s_list[threadIdx.x];   // index within the job
+  const int64_t i = J.g0 + li;                     // virtual index
+  set_culled(i);   // until the projection below accepts it
   const float* __restrict__ means = J.means;
   const float* __restrict__ scales = J.scales;
   const float* __restrict__ quats = J.quats;
