@@ -22,6 +22,11 @@ struct L1Planes {
   int64_t end[3];   // cumulative flat end of each plane
 };
 
+__device__ inline float l1_sign(float d, float sc) { return d > 0.f ? sc : (d < 0.f ? -sc : 0.f); }
+
+// VEC: every plane length is a multiple of 4 and every plane 16-byte
+// aligned, so j counts groups of four floats (L.end in groups).
+template <bool VEC>
 __global__ void __launch_bounds__(kLossThreads) k_l1_grad(L1Planes L, float* __restrict__ loss) {
   __shared__ float red[kLossThreads / 64];
   float acc = 0.f;
@@ -29,10 +34,19 @@ __global__ void __launch_bounds__(kLossThreads) k_l1_grad(L1Planes L, float* __r
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
     const int pl = j < L.end[0] ? 0 : (j < L.end[1] ? 1 : 2);
     const int64_t o = pl == 0 ? j : j - L.end[pl - 1];
-    const float d = L.pred[pl][o] - L.target[pl][o];
     const float sc = L.scale[pl];
-    L.grad[pl][o] = d > 0.f ? sc : (d < 0.f ? -sc : 0.f);
-    acc += fabsf(d) * sc;
+    if (VEC) {
+      const float4 a = reinterpret_cast<const float4*>(L.pred[pl])[o];
+      const float4 b = reinterpret_cast<const float4*>(L.target[pl])[o];
+      const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+      reinterpret_cast<float4*>(L.grad[pl])[o] =
+          make_float4(l1_sign(d.x, sc), l1_sign(d.y, sc), l1_sign(d.z, sc), l1_sign(d.w, sc));
+      acc += (fabsf(d.x) + fabsf(d.y) + fabsf(d.z) + fabsf(d.w)) * sc;
+    } else {
+      const float d = L.pred[pl][o] - L.target[pl][o];
+      L.grad[pl][o] = l1_sign(d, sc);
+      acc += fabsf(d) * sc;
+    }
   }
   if (!loss) return;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -115,7 +129,11 @@ hipError_t launch_l1_grad(const float* const pred[3], const float* const target[
                           const float scale[3], float* loss, hipStream_t st) {
   if (P <= 0) return hipSuccess;
   L1Planes L;
-  const int64_t counts[3] = {3 * P, P, P};
+  bool vec = P % 4 == 0;
+  for (int k = 0; k < 3; k++)
+    vec = vec && ((uintptr_t)pred[k] % 16 == 0) && ((uintptr_t)target[k] % 16 == 0) && ((uintptr_t)grad[k] % 16 == 0);
+  const int64_t unit = vec ? 4 : 1;
+  const int64_t counts[3] = {3 * P / unit, P / unit, P / unit};
   int64_t run = 0;
   for (int k = 0; k < 3; k++) {
     L.pred[k] = pred[k];
@@ -128,7 +146,10 @@ hipError_t launch_l1_grad(const float* const pred[3], const float* const target[
   int64_t blocks = (run + kLossThreads - 1) / kLossThreads;
   const int64_t max_blocks = loss ? 256 : 4096;   // one atomic per block on the loss
   if (blocks > max_blocks) blocks = max_blocks;
-  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, L, loss);
+  if (vec)
+    hipLaunchKernelGGL(k_l1_grad<true>, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, L, loss);
+  else
+    hipLaunchKernelGGL(k_l1_grad<false>, dim3((unsigned)blocks), dim3(kLossThreads), 0, st, L, loss);
   return hipGetLastError();
 }
 

@@ -19,13 +19,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def test_l1_loss_grad_matches_numpy():
-    print("l1 grad", flush=True)
-    intr = scenes.Intrinsics(37, 29, 30.0, 30.0, 18.0, 14.0)
+@pytest.mark.parametrize("W,H", [(37, 29), (40, 30)])   # odd pixel count (scalar path), multiple of 4 (vector path)
+def test_l1_loss_grad_matches_numpy(W, H):
+    print(f"l1 grad {W}x{H}", flush=True)
+    intr = scenes.Intrinsics(W, H, 30.0, 30.0, W / 2.0, H / 2.0)
     rng = np.random.default_rng(0)
     P = intr.pixels
-    pred = [rng.standard_normal(s).astype(np.float32) for s in ((3, 29, 37), (29, 37), (29, 37))]
-    tgt = [rng.standard_normal(s).astype(np.float32) for s in ((3, 29, 37), (29, 37), (29, 37))]
+    pred = [rng.standard_normal(s).astype(np.float32) for s in ((3, H, W), (H, W), (H, W))]
+    tgt = [rng.standard_normal(s).astype(np.float32) for s in ((3, H, W), (H, W), (H, W))]
     tgt[1][0, :5] = pred[1][0, :5]           # sign(0) = 0
     dp = [torch.from_numpy(a).cuda() for a in pred]
     dt = [torch.from_numpy(a).cuda() for a in tgt]
