@@ -754,7 +754,10 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   // moments and four weighted sums from three other lanes with shuffles and
   // issues the ten accumulations itself.
   int rowent = 0;
+  float* Fg = A;                                                  // [kGrp][10] sums bound for HBM
+  uint32_t* Fslot = reinterpret_cast<uint32_t*>(A + kGrp * kGradFields);   // [kGrp] their accumulator rows
   auto flush = [&](int count) {
+    bool to_global = false;
     wave_sync();
     // second operand: lane (k, j) holds row j of A at the pixels 32 h + 8 k + t;
     // three bf16 products (hi.hi + hi.lo + lo.hi) per half keep about 16
@@ -804,18 +807,33 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       f[8] = W8;
       f[9] = W9;
       const uint32_t pos = __float_as_uint(sg.misc.z) - 1u;   // list position
-      if (kAcc > 0 && pos < (uint32_t)kAcc) {
+      to_global = !(kAcc > 0 && pos < (uint32_t)kAcc);
+      if (!to_global) {
         float* dst = &acc[pos * kGradFields];
 #pragma unroll
         for (int k = 0; k < kGradFields; k++)
           if (f[k] != 0.f) atomicAdd(dst + k, f[k]);
       } else {
-        float* dst = g2d + (int64_t)__float_as_uint(sg.misc.y) * kGradFields;
+        // global sums go through LDS so that each atomic instruction covers
+        // whole Gaussians (ten consecutive floats), which the memory side
+        // serves far better than ten instructions of scattered lanes
 #pragma unroll
-        for (int k = 0; k < kGradFields; k++)
-          if (f[k] != 0.f) unsafeAtomicAdd(dst + k, f[k]);
+        for (int k = 0; k < kGradFields; k++) Fg[lane * kGradFields + k] = f[k];
+        Fslot[lane] = __float_as_uint(sg.misc.y);
       }
     }
+    const uint64_t gmask = __builtin_amdgcn_ballot_w64(lane < count && to_global);
+    if (gmask != 0) {   // uniform
+      wave_sync();
+      for (int idx = lane; idx < count * kGradFields; idx += 64) {
+        const int g = idx / kGradFields, fi = idx - g * kGradFields;
+        if ((gmask >> g) & 1u) {
+          const float v = Fg[idx];
+          if (v != 0.f) unsafeAtomicAdd(g2d + (int64_t)Fslot[g] * kGradFields + fi, v);
+        }
+      }
+    }
+    wave_sync();   // the next rows of A overwrite Fg
   };
   for (uint32_t hi = Lmax; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
