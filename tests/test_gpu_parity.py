@@ -156,3 +156,25 @@ def test_pose_only_and_map_only_flags():
     assert "twist" not in mapg
     assert torch.allclose(pose["twist"], full["twist"], rtol=1e-5, atol=1e-9)
     assert torch.allclose(mapg["means"], full["means"], rtol=1e-4, atol=1e-9)
+
+
+@pytest.mark.parametrize("W,H,tile", [(160, 120, 16), (160, 120, 8), (400, 300, 8)])
+def test_exact_depth_ties_keep_index_order(W, H, tile):
+    """Many Gaussians at exactly the same depth (identity pose, three depth
+    values): every bin list must hold them in index order, on the per-bin
+    sort path (the first two cases) and on the global sort path (1900 bins)."""
+    _log(f"depth ties {W}x{H} tile {tile}")
+    intr = scenes.Intrinsics(W, H, 150.0, 150.0, W / 2.0, H / 2.0)
+    sc = scenes.frustum_scene(3000, intr, scenes.rng_for(9, 123))
+    z = np.array([2.0, 2.5, 3.0], np.float32)[np.arange(sc.n) % 3]
+    sc.means[0] *= z / sc.means[2]
+    sc.means[1] *= z / sc.means[2]
+    sc.means[2] = z
+    job, imgs = run_job(sc, tile=tile, wave_batch=64, bwd="mfma")
+    _, st = check_structure(job, sc, tile)
+    assert st["list_kind"] == (1 if (W // tile) * (H // tile) <= 1024 else 0)
+    check_images(imgs, oracle.forward(sc))
+    up = _up(sc)
+    g = job.backward(*_dev_grads(up))
+    torch.cuda.synchronize()
+    check_grads(g, oracle.backward(sc, *up))
