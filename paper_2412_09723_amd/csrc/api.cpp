@@ -211,7 +211,7 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   p.rec_i = take(64 * nn);
   if (p.by_index) {
     p.gbin = take(8 * nn);
-    p.ucnt = take(4 * (size_t)p.units * p.bins);
+    p.ucnt = take(4 * (size_t)p.units * (kUnitThreads / 64) * p.bins);   // per wave
     p.uvis = take(4 * (size_t)p.units);
   } else {
     p.vis_pos = take(4 * nn);

@@ -542,11 +542,12 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __rest
                                                              uint32_t* __restrict__ gcnt,
                                                              uint32_t* __restrict__ uvis) {
   constexpr int NW = kUnitThreads / 64;
-  __shared__ uint32_t h[kFastBins];
+  __shared__ uint32_t hw[NW][kFastBins];
   __shared__ RoundPairs RP[NW];
   __shared__ uint32_t s_vis;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int b = t; b < nbins; b += kUnitThreads) h[b] = 0u;
+  for (int k = t; k < NW * kFastBins; k += kUnitThreads) (&hw[0][0])[k] = 0u;
+  uint32_t* h = hw[wave];
   if (t == 0) s_vis = 0u;
   __syncthreads();
   const int64_t wbase = (int64_t)blockIdx.x * kUnitThreads * rounds + (int64_t)wave * 64 * rounds;
@@ -574,11 +575,17 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_count(const uint2* __rest
   for (int off = 32; off > 0; off >>= 1) nvis += __shfl_xor(nvis, off, 64);
   if (lane == 0) atomicAdd(&s_vis, nvis);
   __syncthreads();
-  uint32_t* row = ucnt + (int64_t)blockIdx.x * nbins;
+  // per-wave counts (the emission places each wave's pairs from them) and
+  // the unit's total into its group
+  uint32_t* rows = ucnt + (int64_t)blockIdx.x * NW * nbins;
   uint32_t* grow = gcnt + (int64_t)(blockIdx.x / kGroupUnits) * nbins;
   for (int b = t; b < nbins; b += kUnitThreads) {
-    const uint32_t c = h[b];
-    row[b] = c;
+    uint32_t c = 0;
+    for (int w = 0; w < NW; w++) {
+      const uint32_t x = hw[w][b];
+      rows[(int64_t)w * nbins + b] = x;
+      c += x;
+    }
     if (c) atomicAdd(&grow[b], c);
   }
   if (t == 0) uvis[blockIdx.x] = s_vis;
@@ -672,8 +679,8 @@ __global__ void __launch_bounds__(kUScanThreads) k_unit_scan(uint32_t* __restric
   }
 }
 
-// Emission. Each wave first counts its pairs per bin, and the waves' starts
-// follow from the unit offsets. Then the pairs of each round, taken 64 at a
+// Emission. Each wave's start in every bin follows from the group offsets
+// and the per-wave counts of k_unit_count. Then the pairs of each round, taken 64 at a
 // time in Gaussian-index order, are ranked within their bins: a lane matches
 // its pair's bin against the other lanes' with one ballot per bin bit, and
 // the lowest lane of each group advances the wave's running count of that
@@ -691,39 +698,20 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restr
   __shared__ uint32_t lkey[NW][64];
   if (counters[C_OVERFLOW]) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int k = t; k < NW * kFastBins; k += kUnitThreads) (&wc[0][0])[k] = 0u;
-  __syncthreads();
   const int64_t wbase = (int64_t)blockIdx.x * kUnitThreads * rounds + (int64_t)wave * 64 * rounds;
   uint32_t* my = wc[wave];
   RoundPairs& R = RP[wave];
-  for (int r0 = 0; r0 < rounds; r0 += kRoundGroup) {
-    if (wbase + (int64_t)r0 * 64 >= n) break;   // uniform
-    uint2 g[kRoundGroup];
-    load_group(gbin, wbase + (int64_t)r0 * 64, n, rounds - r0, lane, g);
-#pragma unroll
-    for (int u = 0; u < kRoundGroup; u++) {
-      if (r0 + u >= rounds) break;   // uniform
-      const uint32_t total = round_setup(R, g[u], lane);
-      for (uint32_t q0 = 0; q0 < total; q0 += 64) {
-        const uint32_t q = q0 + (uint32_t)lane;
-        if (q < total) {
-          uint32_t src;
-          atomicAdd(&my[round_pair(R, q, src)], 1u);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
+  // each wave's start in every bin: the group's offset, the earlier units of
+  // the group and the earlier waves of this unit (counts from k_unit_count)
   const int grp = (int)blockIdx.x / kGroupUnits;
   const uint32_t* grow = goff + (int64_t)grp * nbins;
   for (int b = t; b < nbins; b += kUnitThreads) {
     uint32_t run = grow[b];
-    for (int u = grp * kGroupUnits; u < (int)blockIdx.x; u++) run += ucnt[(int64_t)u * nbins + b];
+    for (int u = grp * kGroupUnits; u < (int)blockIdx.x; u++)
+      for (int w = 0; w < NW; w++) run += ucnt[((int64_t)u * NW + w) * nbins + b];
     for (int w = 0; w < NW; w++) {
-      const uint32_t x = wc[w][b];
       wc[w][b] = run;
-      run += x;
+      run += ucnt[((int64_t)blockIdx.x * NW + w) * nbins + b];
     }
   }
   __syncthreads();
