@@ -644,6 +644,10 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 // forms the ten sums and the wave issues them as whole-Gaussian atomics.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// v_writelane_b32 (the compiler intrinsic; HIP exposes no builtin for it):
+// returns `old` with lane `lane` replaced by the wave-uniform `value`
+__device__ int writelane_u(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 constexpr int kGrp = 8;                        // Gaussians per product
 constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
 constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
@@ -741,9 +745,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   const uint32_t Lmax = __builtin_amdgcn_readfirstlane(wave_max_u32(L));
   const uint32_t start = trange[2 * bin_id];
   const float xf = (float)xl, yf = (float)yl;
-  const float GST = GS * Tf;
   float T = Tf;
-  float R = 0.f;
+  float Rs = -(GS * Tf);   // suffix sum of (G_rgb . c + G_depth z) alpha T, minus G_sil T_final
   uint32_t reduced = 0u;
   const int eaddr = lane;   // pixel-contiguous rows of A
   // Rows g < count of A (e values) and 8 + g (w values) belong to the packed
@@ -768,13 +771,18 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       const float4* r4 = reinterpret_cast<const float4*>(A + pj * kRow + 32 * h + 8 * pk);
       const float4 x0 = r4[0], x1 = r4[1];
       const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      // high parts by truncation (a byte permute packs two of them), low
+      // parts rounded from the exact remainders
       bf16x8 rh, rl;
+      u32x4 hw;
 #pragma unroll
-      for (int t = 0; t < 8; t++) {
-        const __bf16 vh = (__bf16)v[t];
-        rh[t] = vh;
-        rl[t] = (__bf16)(v[t] - (float)vh);
+      for (int t = 0; t < 8; t += 2) {
+        const uint32_t u0 = __float_as_uint(v[t]), u1 = __float_as_uint(v[t + 1]);
+        hw[t / 2] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);   // high halves, truncated
+        rl[t] = (__bf16)(v[t] - __uint_as_float(u0 & 0xFFFF0000u));
+        rl[t + 1] = (__bf16)(v[t + 1] - __uint_as_float(u1 & 0xFFFF0000u));
       }
+      rh = __builtin_bit_cast(bf16x8, hw);
       d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mhi[h], rh, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mhi[h], rl, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Mlo[h], rh, d, 0, 0, 0);
@@ -811,8 +819,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       if (!to_global) {
         float* dst = &acc[pos * kGradFields];
 #pragma unroll
-        for (int k = 0; k < kGradFields; k++)
-          if (f[k] != 0.f) atomicAdd(dst + k, f[k]);
+        for (int k = 0; k < kGradFields; k++) atomicAdd(dst + k, f[k]);
       } else {
         // global sums go through LDS so that each atomic instruction covers
         // whole Gaussians (ten consecutive floats), which the memory side
@@ -852,9 +859,14 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       }
       float at[kBwdStep], alpha[kBwdStep], inv[kBwdStep], gcz[kBwdStep];
       bool acc[kBwdStep];
+      // the step's entries from one base address in a VGPR, so that the four
+      // reads use immediate offsets
+      int lo_slot = top - (kBwdStep - 1);
+      __asm__ volatile("" : "+v"(lo_slot));
+      const Staged* sp = my + lo_slot;
 #pragma unroll
       for (int k = 0; k < kBwdStep; k++) {
-        const Staged& sk = my[top - k];
+        const Staged& sk = sp[kBwdStep - 1 - k];
         const float4 ge = sk.geo, cn = sk.conic, ap = sk.app;
         const float2 mi = make_float2(sk.misc.x, sk.misc.z);
         const float dx = (xf + ge.x) - ge.z;
@@ -863,24 +875,26 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
         const float t2 = cn.z * dy;
         const float q = __builtin_fmaf(t1, t1, t2 * t2);
         acc[k] = __float_as_uint(mi.y) <= L && q <= cn.w;   // list position < last
-        at[k] = __builtin_amdgcn_exp2f(ap.x - q);
+        // a pixel that does not composite the entry takes alpha~ = 0: its
+        // weight, its e and its share of the suffix sum are then exactly zero
+        at[k] = acc[k] ? __builtin_amdgcn_exp2f(ap.x - q) : 0.f;
         alpha[k] = fminf(kAlphaMax, at[k]);
         inv[k] = __builtin_amdgcn_rcpf(1.f - alpha[k]);
         gcz[k] = __builtin_fmaf(G0, ap.z, __builtin_fmaf(G1, ap.w, __builtin_fmaf(G2, mi.x, GD * ap.y)));
       }
-      // back-to-front recursion, predicated on acceptance
+      // back-to-front recursion; only the transmittance needs the predicate
 #pragma unroll
       for (int k = 0; k < kBwdStep; k++) {
         const float Tk = T * inv[k];
         const float w = alpha[k] * Tk;
-        const float dalpha = __builtin_fmaf(Tk, gcz[k], -(R - GST) * inv[k]);
+        const float dalpha = __builtin_fmaf(Tk, gcz[k], -Rs * inv[k]);
         const float e = at[k] > kAlphaMax ? 0.f : dalpha * at[k];
-        R = acc[k] ? __builtin_fmaf(gcz[k], w, R) : R;
+        Rs = __builtin_fmaf(gcz[k], w, Rs);
         T = acc[k] ? Tk : T;
         if (__builtin_amdgcn_ballot_w64(acc[k]) != 0) {   // uniform
-          A[rows * kRow + eaddr] = acc[k] ? e : 0.f;
-          A[(kGrp + rows) * kRow + eaddr] = acc[k] ? w : 0.f;
-          if (lane == rows) rowent = top - k;
+          A[rows * kRow + eaddr] = e;
+          A[(kGrp + rows) * kRow + eaddr] = w;
+          rowent = writelane_u(top - k, rows, rowent);
           rows++;
         }
       }
