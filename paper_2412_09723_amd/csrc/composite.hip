@@ -29,6 +29,10 @@
 
 #pragma clang fp contract(off)
 
+// v_writelane_b32 (the compiler intrinsic; HIP exposes no builtin for it):
+// returns `old` with lane `lane` replaced by the wave-uniform `value`
+__device__ int writelane_u(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace ms {
 namespace {
 
@@ -54,14 +58,47 @@ __device__ inline Staged inert_entry() {
 #define MS_STAGE_CPOL -1
 #endif
 
-// Packs the bin-list entries at list positions [lo, lo + n) (n <= 64) whose
-// pixel box meets the 8x8 sub-block at (X0, Y0) into dst[0 ..), in list
+// Conservative test that a record's acceptance ellipse can reach a pixel of
+// the 8x8 sub-block at (X0, Y0), evaluated on the quad lane that holds the
+// conic (a, b, c, qcut); the centre (ui, vi, uf, vf) comes from the quad's
+// first lane. The offsets the pixels use, dx = (x - ui) - uf rounded, lie in
+// [x0, x1] (rounding is monotonic), likewise dy in [y0, y1]. Over that
+// rectangle |a dx + b dy| >= m1 and |c dy| >= m2 (interval bounds). A pixel
+// with q <= qcut has |t1|, |t2| within a few units in the last place of
+// those exact forms, so reducing m1, m2 by 2^-20 (|a| |dx|max + |b| |dy|max + 3)
+// and 2^-20 |c| |dy|max, and allowing qcut (1 + 2^-20), leaves no accepted
+// pixel out: a record that fails composites nowhere in the sub-block.
+__device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0) {
+  constexpr float kEps = 0x1p-20f;
+  const float ui = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.x, 0x00, 0xF, 0xF, false));
+  const float vi = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.y, 0x00, 0xF, 0xF, false));
+  const float uf = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.z, 0x00, 0xF, 0xF, false));
+  const float vf = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.w, 0x00, 0xF, 0xF, false));
+  const float a = __uint_as_float(v.x), b = __uint_as_float(v.y), c = __uint_as_float(v.z), qc = __uint_as_float(v.w);
+  const float gx = (float)X0 - ui, gy = (float)Y0 - vi;   // exact
+  const float x0 = gx - uf, x1 = (7.f + gx) - uf;
+  const float y0 = gy - vf, y1 = (7.f + gy) - vf;
+  const float ax0 = a * x0, ax1 = a * x1, by0 = b * y0, by1 = b * y1;
+  const float lo1 = fminf(ax0, ax1) + fminf(by0, by1);
+  const float hi1 = fmaxf(ax0, ax1) + fmaxf(by0, by1);
+  const float ym = fmaxf(fabsf(y0), fabsf(y1));
+  const float m1 = fmaxf(fmaxf(lo1, -hi1), 0.f);
+  const float m2 = fabsf(c) * fmaxf(fmaxf(y0, -y1), 0.f);
+  const float e1 = kEps * ((fabsf(a) * fmaxf(fabsf(x0), fabsf(x1)) + fabsf(b) * ym) + 3.f);
+  const float e2 = kEps * (fabsf(c) * ym);
+  const float r1 = fmaxf(m1 - e1, 0.f), r2 = fmaxf(m2 - e2, 0.f);
+  return __builtin_fmaf(r1, r1, r2 * r2) <= qc * (1.f + kEps);
+}
+
+// Packs the bin-list entries at list positions [lo, lo + n) (n <= 64) that
+// can composite in the 8x8 sub-block at (X0, Y0) into dst[0 ..), in list
 // order, and returns how many there are (wave-uniform). Lane j reads pair
 // word j (coalesced); the records are then read four lanes per 64-byte
 // record, so each load instruction covers 16 whole records rather than 64
 // scattered 16-byte pieces. The quad's last lane holds the record's pixel
-// box; its decision selects the quad, and a ballot plus a masked bit count
-// gives each packed record its slot.
+// box and its second lane the conic; a record is packed when the box meets
+// the sub-block and ellipse_reaches holds, and a ballot plus a masked bit
+// count gives each packed record its slot.
 __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                   uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
                                   Staged* __restrict__ dst) {
@@ -90,6 +127,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
   int base = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
+    if (16 * k < n) {   // uniform
     const int e = 16 * k + sub;
     bool touch = false;
     if (part == 3 && e < n) {
@@ -97,7 +135,10 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
       const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
       touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
     }
-    const uint64_t m = __builtin_amdgcn_ballot_w64(touch);
+    const bool reach = ellipse_reaches(v[k], X0, Y0);   // meaningful on the conic lane (part 1)
+    // a record is packed when its box meets the sub-block and its ellipse can
+    // reach a pixel centre of it
+    const uint64_t m = __builtin_amdgcn_ballot_w64(touch) & (__builtin_amdgcn_ballot_w64(reach) << 2);
     if ((m >> (4 * sub + 3)) & 1u) {
       // packed records before this one: their box lanes lie below this quad
       const int slot =
@@ -113,6 +154,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
       reinterpret_cast<float4*>(dst + slot)[part] = o;
     }
     base += __builtin_popcountll(m);
+    }
   }
   return base;
 }
@@ -645,9 +687,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-// v_writelane_b32 (the compiler intrinsic; HIP exposes no builtin for it):
-// returns `old` with lane `lane` replaced by the wave-uniform `value`
-__device__ int writelane_u(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 constexpr int kGrp = 8;                        // Gaussians per product
 constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
 constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
