@@ -919,18 +919,22 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_sort(uint32_t* __restrict_
 #pragma unroll
       for (int r = 0; r < kSortItems; r++) {
         const int pos = wave * ipt * 64 + r * 64 + lane;
-        if (r < ipt && pos < seg) {
-          rk[r] += S.wcnt[wave][(k[r] >> shift) & (uint32_t)(nd - 1)];
-          S.buf[rk[r]] = k[r];
-        }
+        if (r < ipt && pos < seg) rk[r] += S.wcnt[wave][(k[r] >> shift) & (uint32_t)(nd - 1)];
       }
-      __syncthreads();
+      if (q + 1 < passes) {   // the last pass moves only the values
 #pragma unroll
-      for (int r = 0; r < kSortItems; r++) {
-        const int pos = wave * ipt * 64 + r * 64 + lane;
-        if (r < ipt && pos < seg) k[r] = S.buf[pos];
+        for (int r = 0; r < kSortItems; r++) {
+          const int pos = wave * ipt * 64 + r * 64 + lane;
+          if (r < ipt && pos < seg) S.buf[rk[r]] = k[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortItems; r++) {
+          const int pos = wave * ipt * 64 + r * 64 + lane;
+          if (r < ipt && pos < seg) k[r] = S.buf[pos];
+        }
+        __syncthreads();
       }
-      __syncthreads();
 #pragma unroll
       for (int r = 0; r < kSortItems; r++) {
         const int pos = wave * ipt * 64 + r * 64 + lane;
