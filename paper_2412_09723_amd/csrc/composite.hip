@@ -40,7 +40,7 @@ struct Staged {
   float4 geo;    // gx = X0 - ui, gy = Y0 - vi (exact), uf, vf
   float4 conic;  // a, b, c, qcut
   float4 app;    // log2 o, z, r, g
-  float4 misc;   // b(lue), rank bits, list position + 1 (bits), 0
+  float4 misc;   // b(lue), rank bits, list position + 1 (bits), moment flag (backward) or 0
 };
 
 // An entry that accepts no pixel, with finite fields (pads a packed chunk to
@@ -58,6 +58,15 @@ __device__ inline Staged inert_entry() {
 #define MS_STAGE_CPOL -1
 #endif
 
+#ifndef MS_MOMENT_SPREAD
+#define MS_MOMENT_SPREAD 16.f
+#endif
+// Where (|a U| + (|b| + |c|) |V|)^2 exceeds this multiple of qcut, with (U, V)
+// the Gaussian's centre relative to the sub-block centre (a spread of 4
+// acceptance radii), the backward takes the record's conic sums from
+// per-pixel products rather than from block-centred moments.
+constexpr float kMomentSpread = MS_MOMENT_SPREAD;
+
 // Conservative test that a record's acceptance ellipse can reach a pixel of
 // the 8x8 sub-block at (X0, Y0), evaluated on the quad lane that holds the
 // conic (a, b, c, qcut); the centre (ui, vi, uf, vf) comes from the quad's
@@ -68,7 +77,10 @@ __device__ inline Staged inert_entry() {
 // those exact forms, so reducing m1, m2 by 2^-20 (|a| |dx|max + |b| |dy|max + 3)
 // and 2^-20 |c| |dy|max, and allowing qcut (1 + 2^-20), leaves no accepted
 // pixel out: a record that fails composites nowhere in the sub-block.
-__device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0) {
+// With kSpread, `wide` tells whether the record's moments about the sub-block
+// centre are badly conditioned (kMomentSpread).
+template <bool kSpread>
+__device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0, bool& wide) {
   constexpr float kEps = 0x1p-20f;
   const float ui = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.x, 0x00, 0xF, 0xF, false));
   const float vi = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.y, 0x00, 0xF, 0xF, false));
@@ -87,6 +99,11 @@ __device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0) {
   const float e1 = kEps * ((fabsf(a) * fmaxf(fabsf(x0), fabsf(x1)) + fabsf(b) * ym) + 3.f);
   const float e2 = kEps * (fabsf(c) * ym);
   const float r1 = fmaxf(m1 - e1, 0.f), r2 = fmaxf(m2 - e2, 0.f);
+  if (kSpread) {
+    const float U = ((-gx) - 3.5f) + uf, V = ((-gy) - 3.5f) + vf;
+    const float spread = fabsf(a) * fabsf(U) + (fabsf(b) + fabsf(c)) * fabsf(V);
+    wide = spread * spread > kMomentSpread * qc;
+  }
   return __builtin_fmaf(r1, r1, r2 * r2) <= qc * (1.f + kEps);
 }
 
@@ -98,7 +115,9 @@ __device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0) {
 // scattered 16-byte pieces. The quad's last lane holds the record's pixel
 // box and its second lane the conic; a record is packed when the box meets
 // the sub-block and ellipse_reaches holds, and a ballot plus a masked bit
-// count gives each packed record its slot.
+// count gives each packed record its slot. With kSpread, misc.w of a packed
+// record is 1 where its block-centred moments are badly conditioned.
+template <bool kSpread>
 __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                   uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
                                   Staged* __restrict__ dst) {
@@ -135,7 +154,9 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
       const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
       touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
     }
-    const bool reach = ellipse_reaches(v[k], X0, Y0);   // meaningful on the conic lane (part 1)
+    bool wide = false;
+    const bool reach = ellipse_reaches<kSpread>(v[k], X0, Y0, wide);   // meaningful on the conic lane (part 1)
+    const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
     // a record is packed when its box meets the sub-block and its ellipse can
     // reach a pixel centre of it
     const uint64_t m = __builtin_amdgcn_ballot_w64(touch) & (__builtin_amdgcn_ballot_w64(reach) << 2);
@@ -149,7 +170,8 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
         o.x = (float)X0 - o.x;   // exact: both are integers below 2^24
         o.y = (float)Y0 - o.y;
       } else if (part == 3) {
-        o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u), 0.f);
+        o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u),
+                        ((wm >> (4 * sub + 1)) & 1u) ? 1.f : 0.f);
       }
       reinterpret_cast<float4*>(dst + slot)[part] = o;
     }
@@ -162,7 +184,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
 // Packs a chunk of up to WB entries (WB / 64 rounds of stage_chunk) and pads
 // the packed count to a multiple of `group` with inert entries; returns the
 // padded count.
-template <int WB>
+template <int WB, bool kSpread = false>
 __device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                          uint32_t rank_mask, uint32_t start, uint32_t lo, int nb, int X0, int Y0,
                                          int lane, Staged* __restrict__ dst, int group, int& packed) {
@@ -170,7 +192,9 @@ __device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const ui
 #pragma unroll
   for (int h = 0; h < WB; h += 64) {
     const int n = nb - h;
-    if (n > 0) cnt += stage_chunk(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane, dst + cnt);
+    if (n > 0)
+      cnt += stage_chunk<kSpread>(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane,
+                                  dst + cnt);
   }
   const int padded = (cnt + group - 1) / group * group;
   if (lane < padded - cnt) dst[cnt + lane] = inert_entry();
@@ -679,11 +703,16 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 // of e = dL/dalpha * alpha~ and w = alpha T over the pixels p (x, y pixel
 // coordinates about the sub-block centre). For a group of 8 Gaussians, each
 // pixel lane writes its e values to rows 0-7 and its w values to rows 8-15 of
-// a 16 x 64 LDS matrix A; B (64 x 16) holds the six moment monomials in
-// columns 0-5 and the four upstream values in columns 6-9, so the
-// (16 x 64) x (64 x 16) product -- sixteen v_mfma_f32_16x16x4_f32 steps, K = 4
-// pixels per step -- yields both sets of sums. One lane per Gaussian then
-// forms the ten sums and the wave issues them as whole-Gaussian atomics.
+// a 16 x 64 LDS matrix A; the moment matrix M (16 x 64) holds the six
+// monomials in rows 0-5 and the four upstream values in rows 6-9, so the
+// product M A^T yields both sets of sums: per 32-pixel half, three
+// v_mfma_f32_16x16x32_bf16 on high and low bf16 parts (about 16 significant
+// bits per term). One lane per Gaussian then shifts the moments to the
+// Gaussian's centre and forms the ten sums; rows where that shift is badly
+// conditioned (needle-like Gaussians far from their centre) take their conic
+// sums from per-pixel products instead. The sums leave as whole-Gaussian
+// atomics, through the workgroup's LDS accumulator where the list position
+// allows.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -699,6 +728,7 @@ constexpr int kBwdStep = 4;                    // entries whose alphas are evalu
 #define MS_ACC_ROWS 256
 #endif
 constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
+
 
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
@@ -832,6 +862,34 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     const float S4 = __shfl(d[0], 16 + l, 64), S5 = __shfl(d[1], 16 + l, 64);
     const float W6 = __shfl(d[2], 24 + l, 64), W7 = __shfl(d[3], 24 + l, 64);
     const float W8 = __shfl(d[0], 40 + l, 64), W9 = __shfl(d[1], 40 + l, 64);
+    // The moment form multiplies the sums by the centre offset (U, V) of the
+    // Gaussian from the sub-block centre, which loses precision where the
+    // conic terms a U, b V, c V are large next to the acceptance radius (a
+    // needle-like Gaussian crossing the sub-block far from its centre). Such
+    // rows get their five conic sums from the pixels' own offsets instead:
+    // per pixel e t1, e t2, e t1 dx, e t1 dy, e t2 dy, summed over the wave.
+    const bool bad = lane < count && my[rowent].misc.w != 0.f;   // flagged when staged
+    uint64_t badm = __builtin_amdgcn_ballot_w64(bad);
+    float X1 = 0.f, X2 = 0.f, X3 = 0.f, X4 = 0.f, X5 = 0.f;
+    while (badm != 0) {   // uniform
+      const int g = __builtin_ctzll(badm);
+      badm &= badm - 1;
+      const Staged& sg = my[__builtin_amdgcn_readlane(rowent, g)];
+      const float e = A[g * kRow + eaddr];
+      const float dx = (xf + sg.geo.x) - sg.geo.z;
+      const float dy = (yf + sg.geo.y) - sg.geo.w;
+      const float t1 = __builtin_fmaf(sg.conic.x, dx, sg.conic.y * dy);
+      const float et1 = e * t1, et2 = e * (sg.conic.z * dy);
+      const float s1 = wave_sum_dpp(et1), s2 = wave_sum_dpp(et2);
+      const float s3 = wave_sum_dpp(et1 * dx), s4 = wave_sum_dpp(et1 * dy), s5 = wave_sum_dpp(et2 * dy);
+      if (lane == g) {
+        X1 = s1;
+        X2 = s2;
+        X3 = s3;
+        X4 = s4;
+        X5 = s5;
+      }
+    }
     if (lane < count) {
       const Staged& sg = my[rowent];
       const float S1 = d[0], Sx = d[1], Sy = d[2], Sxx = d[3], Sxy = S4, Syy = S5;
@@ -849,6 +907,13 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       f[3] = a * Edxx + b * Edxy;
       f[4] = a * Edxy + b * Edyy;
       f[5] = c * Edyy;
+      if (bad) {
+        f[1] = X1;
+        f[2] = X2;
+        f[3] = X3;
+        f[4] = X4;
+        f[5] = X5;
+      }
       f[6] = W6;
       f[7] = W7;
       f[8] = W8;
@@ -886,7 +951,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, kBwdStep,
+    const int cnt = stage_chunk_padded<kBwdChunk, true>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, kBwdStep,
                                                   packed);
     wave_sync();
     reduced += (uint32_t)packed;

@@ -178,3 +178,28 @@ def test_exact_depth_ties_keep_index_order(W, H, tile):
     g = job.backward(*_dev_grads(up))
     torch.cuda.synchronize()
     check_grads(g, oracle.backward(sc, *up))
+
+
+@pytest.mark.parametrize("tile,wb", [(16, 64), (8, 32), (32, 128)])
+def test_needle_gaussians_grazing_sub_blocks(tile, wb):
+    """Thin, strongly anisotropic Gaussians at random orientations, with
+    opacities down to the 1/255 cut-off: their acceptance ellipses cover a
+    small part of their pixel boxes and graze many 8x8 sub-blocks, which is
+    where the compositing kernels' record skipping must stay conservative."""
+    _log(f"needles tile {tile} wb {wb}")
+    intr = scenes.Intrinsics(160, 120, 150.0, 150.0, 80.0, 60.0)
+    rng = scenes.rng_for(9, 321)
+    sc = scenes.frustum_scene(2500, intr, rng, zmin=1.0, zmax=4.0)
+    n = sc.n
+    long_axis = rng.integers(0, 3, size=n)
+    sc.scales[:] = np.float32(0.0015)
+    sc.scales[long_axis, np.arange(n)] = rng.uniform(0.05, 0.4, size=n).astype(np.float32)
+    sc.opacity[:] = np.exp(rng.uniform(np.log(1.0 / 255.0), 0.0, size=n)).astype(np.float32)
+    job, imgs = run_job(sc, tile=tile, wave_batch=wb, bwd="mfma")
+    check_structure(job, sc, tile)
+    errs, flagged = check_images(imgs, oracle.forward(sc))
+    _log(f"  image max rel err {errs}, flagged {flagged}")
+    up = _up(sc, 1.0, 1.0, salt=7)
+    g = job.backward(*_dev_grads(up))
+    torch.cuda.synchronize()
+    _log(f"  grad worst {check_grads(g, oracle.backward(sc, *up))}")
