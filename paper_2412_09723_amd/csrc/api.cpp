@@ -300,11 +300,18 @@ int32_t run_forward(JobTable& t, const ms_options* opts, void* workspace, size_t
   int32_t s = check_ws(workspace, ws_bytes, p);
   if (s != MS_OK) return s;
   char* ws = (char*)workspace;
-  hipError_t e = launch_setup(t, p, ws, at<uint32_t>(ws, p.counters), (int64_t)((p.ctrl_end - p.counters) / 4), st);
-  if (e != hipSuccess) return hip_fail(e, "counters");
+  // the projection writes the job table and zeroes the control region; with
+  // no Gaussians a separate launch does both
+  uint32_t* ctrl = at<uint32_t>(ws, p.counters);
+  const int64_t ctrl_words = (int64_t)((p.ctrl_end - p.counters) / 4);
+  hipError_t e = hipSuccess;
+  if (p.n == 0) {
+    e = launch_setup(t, p, ws, ctrl, ctrl_words, st);
+    if (e != hipSuccess) return hip_fail(e, "counters");
+  }
   {
     StageTimer tm(MS_STAGE_PROJECT, st);
-    e = launch_project_fwd(p, opts->near_z, ws, st);
+    e = launch_project_fwd(p, opts->near_z, t, ctrl, ctrl_words, ws, st);
   }
   if (e != hipSuccess) return hip_fail(e, "project");
   {
@@ -333,12 +340,16 @@ int32_t run_backward(JobTable& t, const ms_options* opts, void* workspace, size_
   for (int j = 0; j < t.njobs; j++) any_pose |= !(t.job[j].flags & MS_FLAG_NO_POSE_GRAD);
   // the global depth-sort path zeroes its accumulator rows here; on the
   // per-bin path the rows of the visible Gaussians are zeroed by the
-  // projection and again by the projection adjoint after use
-  hipError_t e = launch_setup(t, p, ws, at<uint32_t>(ws, p.g2d), p.by_index ? 0 : (int64_t)kGradFields * p.n, st);
-  if (e != hipSuccess) return hip_fail(e, "job table");
+  // projection and again by the projection adjoint after use, and the MFMA
+  // backward writes the job table itself
+  hipError_t e = hipSuccess;
+  if (!(p.by_index && (opts->flags & MS_FLAG_MFMA_BWD) && p.tiles > 0)) {
+    e = launch_setup(t, p, ws, at<uint32_t>(ws, p.g2d), p.by_index ? 0 : (int64_t)kGradFields * p.n, st);
+    if (e != hipSuccess) return hip_fail(e, "job table");
+  }
   {
     StageTimer tm(MS_STAGE_COMPOSITE_BWD, st);
-    e = launch_composite_bwd(p, opts->wave_batch, opts->flags, ws, st);
+    e = launch_composite_bwd(p, opts->wave_batch, opts->flags, t, ws, st);
   }
   if (e != hipSuccess) return hip_fail(e, "composite backward");
   {

@@ -733,10 +733,20 @@ constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in L
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     k_composite_bwd_m(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift, const float* __restrict__ tfinal,
+                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobTable tbl,
+                      JobTable* __restrict__ tbl_dst, int bshift, const float* __restrict__ tfinal,
                       const uint32_t* __restrict__ last, float* __restrict__ g2d) {
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
+  // the job table arrives by value; the first workgroup leaves a copy in the
+  // workspace for the projection adjoint
+  const JobDesc* jobs = tbl.job;
+  const int njobs = tbl.njobs;
+  if (blockIdx.x == 0) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&tbl);
+    uint32_t* d = reinterpret_cast<uint32_t*>(tbl_dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
+  }
   __shared__ __attribute__((aligned(16))) float lds[NW * kWaveLds];
   __shared__ Staged stage[NW][kBwdChunk];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1023,12 +1033,12 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
 }
 
 template <int TILE>
-hipError_t bwd_mfma(const Plan& p, char* ws, hipStream_t st) {
+hipError_t bwd_mfma(const Plan& p, const JobTable& t, char* ws, hipStream_t st) {
   constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
   hipLaunchKernelGGL((k_composite_bwd_m<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
-                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
-                     at<uint32_t>(ws, p.last), at<float>(ws, p.g2d));
+                     t, at<JobTable>(ws, p.jobs), p.bshift, at<float>(ws, p.tfinal), at<uint32_t>(ws, p.last),
+                     at<float>(ws, p.g2d));
   return hipGetLastError();
 }
 
@@ -1101,13 +1111,14 @@ hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, c
   MS_DISPATCH(fwd_one, p, ws, st)
 }
 
-hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st) {
+hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, const JobTable& t, char* ws,
+                                hipStream_t st) {
   if (p.tiles == 0) return hipSuccess;
   if (flags & MS_FLAG_MFMA_BWD) {
     switch (p.tile) {
-      case 8: return bwd_mfma<8>(p, ws, st);
-      case 16: return bwd_mfma<16>(p, ws, st);
-      case 32: return bwd_mfma<32>(p, ws, st);
+      case 8: return bwd_mfma<8>(p, t, ws, st);
+      case 16: return bwd_mfma<16>(p, t, ws, st);
+      case 32: return bwd_mfma<32>(p, t, ws, st);
       default: return hipErrorInvalidValue;
     }
   }

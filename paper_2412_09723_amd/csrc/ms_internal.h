@@ -181,10 +181,15 @@ inline int tile_bits(int tiles) {
 // table lives in the workspace (written by launch_setup).
 // Writes the job table into the workspace and zeroes `count` words at `zero`.
 hipError_t launch_setup(const JobTable& t, const Plan& p, char* ws, uint32_t* zero, int64_t count, hipStream_t st);
-hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st);
+// The projection also writes the job table and zeroes `zcount` words at `zero`.
+hipError_t launch_project_fwd(const Plan& p, float near_z, const JobTable& t, uint32_t* zero, int64_t zcount,
+                              char* ws, hipStream_t st);
 hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st);
 hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);
-hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, char* ws, hipStream_t st);
+// The MFMA backward (MS_FLAG_MFMA_BWD) also writes the job table `t` into the
+// workspace; the other backward kernels read it from there.
+hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, const JobTable& t, char* ws,
+                                hipStream_t st);
 hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStream_t st);
 // The L1 loss gradient of the rgb (3P), depth (P) and silhouette (P) planes

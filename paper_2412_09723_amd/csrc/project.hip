@@ -58,13 +58,25 @@ __device__ inline void load_pose(const float* vm, Pose& P) {
 // footprint `gbin` plus a zeroed accumulator row (per-bin path) or the
 // visibility flag, bin count and rank placeholder (global sort path); the
 // pointers of the other path are null.
-__global__ void __launch_bounds__(256) k_project_fwd(const JobDesc* __restrict__ jobs, int njobs, float near_z,
+// The first kernel of a forward pass: it also writes the job table (passed
+// by value) into the workspace for the kernels after it, and zeroes `zcount`
+// words at `zero` (the control region), which no projection block reads.
+__global__ void __launch_bounds__(256) k_project_fwd(const JobTable tbl, JobTable* __restrict__ tbl_dst,
+                                                     uint32_t* __restrict__ zero, int64_t zcount, float near_z,
                                                      int tile, uint32_t* __restrict__ key,
                                                      uint32_t* __restrict__ vis, uint32_t* __restrict__ ntiles,
                                                      int32_t* __restrict__ rank_of, uint4* __restrict__ rec_i,
                                                      uint2* __restrict__ gbin, float* __restrict__ g2d) {
   __shared__ int s_list[256];
   __shared__ int s_wcnt[256 / 64];
+  const JobDesc* jobs = tbl.job;
+  const int njobs = tbl.njobs;
+  if (blockIdx.x == 0) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&tbl);
+    uint32_t* d = reinterpret_cast<uint32_t*>(tbl_dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += 256) d[i] = src[i];
+  }
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < zcount; j += (int64_t)gridDim.x * 256) zero[j] = 0u;
   const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
   const int64_t n = J.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -547,11 +559,12 @@ __global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __re
 
 }  // namespace
 
-hipError_t launch_project_fwd(const Plan& p, float near_z, char* ws, hipStream_t st) {
+hipError_t launch_project_fwd(const Plan& p, float near_z, const JobTable& t, uint32_t* zero, int64_t zcount,
+                              char* ws, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
   const bool bi = p.by_index;
-  hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st,
-                     at<JobTable>(ws, p.jobs)->job, p.njobs, near_z, p.bin, at<uint32_t>(ws, p.key),
+  hipLaunchKernelGGL(k_project_fwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st, t, at<JobTable>(ws, p.jobs), zero,
+                     zcount, near_z, p.bin, at<uint32_t>(ws, p.key),
                      bi ? nullptr : at<uint32_t>(ws, p.vis_pos), bi ? nullptr : at<uint32_t>(ws, p.ntiles),
                      bi ? nullptr : at<int32_t>(ws, p.rank_of), at<uint4>(ws, p.rec_i),
                      bi ? at<uint2>(ws, p.gbin) : nullptr, bi ? at<float>(ws, p.g2d) : nullptr);
