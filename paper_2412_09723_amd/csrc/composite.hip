@@ -54,9 +54,6 @@ __device__ inline Staged inert_entry() {
   return s;
 }
 
-#ifndef MS_STAGE_CPOL
-#define MS_STAGE_CPOL -1
-#endif
 
 #ifndef MS_MOMENT_SPREAD
 #define MS_MOMENT_SPREAD 16.f
@@ -125,23 +122,12 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
   const int part = lane & 3, sub = lane >> 2;
   uint4 v[4];
   uint32_t rk[4];
-#if MS_STAGE_CPOL >= 0
-  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)rec, (short)0, 0x7FFFFFFF, 0x00020000);
-#endif
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int e = 16 * k + sub;
     rk[k] = (uint32_t)__shfl((int)rank, e, 64);
     v[k] = make_uint4(0u, 0u, 0u, 0u);
-#if MS_STAGE_CPOL >= 0
-    if (e < n) {
-      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-      const v4u t = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(rk[k] * 64u + (uint32_t)part * 16u), 0, MS_STAGE_CPOL);
-      v[k] = make_uint4(t.x, t.y, t.z, t.w);
-    }
-#else
     if (e < n) v[k] = rec[4 * (int64_t)rk[k] + part];
-#endif
   }
   int base = 0;
 #pragma unroll
