@@ -203,3 +203,23 @@ def test_needle_gaussians_grazing_sub_blocks(tile, wb):
     g = job.backward(*_dev_grads(up))
     torch.cuda.synchronize()
     _log(f"  grad worst {check_grads(g, oracle.backward(sc, *up))}")
+
+
+@pytest.mark.parametrize("W,H,tile,bin_tile", [(16384, 8, 16, 128), (8, 16384, 8, 0), (1, 1, 16, 0), (1, 700, 8, 0),
+                                               (16384, 24, 32, 0)])
+def test_extreme_image_shapes(W, H, tile, bin_tile):
+    """The largest image edge the ABI accepts, one-pixel images and strips,
+    where almost every bin, tile and sub-block is ragged: (16384, 8) has 128
+    bins of 128 px in one row; (16384, 24) at tile 32 has 512 bins of one
+    tile each; (8, 16384) at tile 8 has 2048 bins (the global sort path)."""
+    _log(f"shape {W}x{H} tile {tile} bin {bin_tile}")
+    f = 200.0
+    intr = scenes.Intrinsics(W, H, f, f, W / 2.0, H / 2.0)
+    sc = scenes.frustum_scene(1500, intr, scenes.rng_for(9, 400 + W % 97 + H % 89), zmin=1.0, zmax=3.0)
+    job, imgs = run_job(sc, tile=tile, wave_batch=32, bin_tile=bin_tile, bwd="mfma")
+    check_structure(job, sc, bin_tile or tile)
+    check_images(imgs, oracle.forward(sc))
+    up = _up(sc, 1.0, 1.0, salt=9)
+    g = job.backward(*_dev_grads(up))
+    torch.cuda.synchronize()
+    check_grads(g, oracle.backward(sc, *up))
