@@ -54,7 +54,6 @@ __device__ inline Staged inert_entry() {
   return s;
 }
 
-
 #ifndef MS_MOMENT_SPREAD
 #define MS_MOMENT_SPREAD 16.f
 #endif
@@ -133,35 +132,35 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     if (16 * k < n) {   // uniform
-    const int e = 16 * k + sub;
-    bool touch = false;
-    if (part == 3 && e < n) {
-      const int bx0 = (int)(v[k].y & 0xFFFFu), bx1 = (int)(v[k].y >> 16);
-      const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
-      touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
-    }
-    bool wide = false;
-    const bool reach = ellipse_reaches<kSpread>(v[k], X0, Y0, wide);   // meaningful on the conic lane (part 1)
-    const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
-    // a record is packed when its box meets the sub-block and its ellipse can
-    // reach a pixel centre of it
-    const uint64_t m = __builtin_amdgcn_ballot_w64(touch) & (__builtin_amdgcn_ballot_w64(reach) << 2);
-    if ((m >> (4 * sub + 3)) & 1u) {
-      // packed records before this one: their box lanes lie below this quad
-      const int slot =
-          base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      float4 o = make_float4(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z),
-                             __uint_as_float(v[k].w));
-      if (part == 0) {
-        o.x = (float)X0 - o.x;   // exact: both are integers below 2^24
-        o.y = (float)Y0 - o.y;
-      } else if (part == 3) {
-        o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u),
-                        ((wm >> (4 * sub + 1)) & 1u) ? 1.f : 0.f);
+      const int e = 16 * k + sub;
+      bool touch = false;
+      if (part == 3 && e < n) {
+        const int bx0 = (int)(v[k].y & 0xFFFFu), bx1 = (int)(v[k].y >> 16);
+        const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
+        touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
       }
-      reinterpret_cast<float4*>(dst + slot)[part] = o;
-    }
-    base += __builtin_popcountll(m);
+      bool wide = false;
+      const bool reach = ellipse_reaches<kSpread>(v[k], X0, Y0, wide);   // meaningful on the conic lane (part 1)
+      const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
+      // a record is packed when its box meets the sub-block and its ellipse can
+      // reach a pixel centre of it
+      const uint64_t m = __builtin_amdgcn_ballot_w64(touch) & (__builtin_amdgcn_ballot_w64(reach) << 2);
+      if ((m >> (4 * sub + 3)) & 1u) {
+        // packed records before this one: their box lanes lie below this quad
+        const int slot =
+            base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        float4 o = make_float4(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z),
+                               __uint_as_float(v[k].w));
+        if (part == 0) {
+          o.x = (float)X0 - o.x;   // exact: both are integers below 2^24
+          o.y = (float)Y0 - o.y;
+        } else if (part == 3) {
+          o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u),
+                          ((wm >> (4 * sub + 1)) & 1u) ? 1.f : 0.f);
+        }
+        reinterpret_cast<float4*>(dst + slot)[part] = o;
+      }
+      base += __builtin_popcountll(m);
     }
   }
   return base;
@@ -715,7 +714,6 @@ constexpr int kBwdStep = 4;                    // entries whose alphas are evalu
 #endif
 constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
 
-
 template <int TILE>
 __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     k_composite_bwd_m(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
@@ -947,8 +945,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<kBwdChunk, true>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, kBwdStep,
-                                                  packed);
+    const int cnt = stage_chunk_padded<kBwdChunk, true>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
+                                                        kBwdStep, packed);
     wave_sync();
     reduced += (uint32_t)packed;
     int rows = 0;   // uniform: rows of A filled since the last product
