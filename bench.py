@@ -242,8 +242,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the per-agent shard design is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the rasterizer has no multi-GPU path (agents would be placed "
+              "whole on GPUs, each running this single-GPU path). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -22,7 +22,8 @@ ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    # packed FP32 instructions stay off ("compiler settings")
+    # packed FP32 instructions (v_pk_*_f32) stay off: some of their forms have
+    # given wrong results on this hardware without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
 ]
