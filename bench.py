@@ -137,7 +137,7 @@ def batch_bench(rounds: int):
     import torch
 
     from paper_2412_09723_amd import autotune, raster, scenes
-    scs = scenes.config3()
+    scs = scenes.four_agent_rooms()
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     maps = [dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity),
                  colors=t(sc.colors)) for sc in scs]
@@ -184,7 +184,7 @@ def serve_bench(duration: float, sweep: list, sweep_duration: float, budget_gb: 
     import torch
 
     from paper_2412_09723_amd import raster, scenes, serve
-    scs = scenes.config4_agents()
+    scs = scenes.serving_agents()
     agents = serve.make_agents(scs, steps=4096)
     opts = raster.RenderOptions()
     n_agents, base = len(agents), 30.0
@@ -254,7 +254,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    sc = scenes.config1(n=args.n)
+    sc = scenes.room_view(n=args.n)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     m = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), colors=t(sc.colors))
     opts = raster.RenderOptions(tile=args.tile, wave_batch=args.wave_batch, fwd_records=args.fwd_records,

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "Intrinsics", "Scene", "rng_for", "frustum_scene", "room_scene",
     "room_center_pose", "look_outward_pose", "perturb_pose", "upstream_grads",
-    "config0", "config1", "config2", "config3", "config4_agents",
+    "small_frustum", "room_view", "keyframe_ring", "four_agent_rooms", "serving_agents",
     "poisson_trace",
 ]
 
@@ -76,9 +76,10 @@ class Scene:
                      self.viewmat.copy(), self.intr)
 
 
-def rng_for(config: int, agent: int = 0, salt: int = 0) -> np.random.Generator:
-    """PCG64 stream with seed = 1000*config + agent (+ salt for auxiliary draws)."""
-    return np.random.Generator(np.random.PCG64(1000 * config + agent + 7919 * salt))
+def rng_for(stream: int, agent: int = 0, salt: int = 0) -> np.random.Generator:
+    """PCG64 stream with seed = 1000*stream + agent (+ salt for auxiliary draws);
+    each workload below draws from its own stream number."""
+    return np.random.Generator(np.random.PCG64(1000 * stream + agent + 7919 * salt))
 
 
 def _attributes(rng: np.random.Generator, n: int):
@@ -194,16 +195,16 @@ def upstream_grads(intr: Intrinsics, rng: np.random.Generator, w_depth: float = 
     return gc.astype(np.float32), gd.astype(np.float32), gs.astype(np.float32)
 
 
-# ---------------------------------------------------------------- configurations
+# ---------------------------------------------------------------- workloads
 
-CONFIG0_INTR = Intrinsics(160, 120, 150.0, 150.0, 80.0, 60.0)
-CONFIG1_INTR = Intrinsics(1200, 680, 600.0, 600.0, 600.0, 340.0)
-CONFIG2_INTR = Intrinsics(640, 480, 500.0, 500.0, 320.0, 240.0)
+SMALL_INTR = Intrinsics(160, 120, 150.0, 150.0, 80.0, 60.0)
+ROOM_INTR = Intrinsics(1200, 680, 600.0, 600.0, 600.0, 340.0)
+VGA_INTR = Intrinsics(640, 480, 500.0, 500.0, 320.0, 240.0)
 
 
-def config0(seed_agent: int = 0, n: int = 4096) -> Scene:
+def small_frustum(seed_agent: int = 0, n: int = 4096) -> Scene:
     """160x120, fx=fy=150, identity pose, 4,096 Gaussians in the frustum at 1-5 m."""
-    return frustum_scene(n, CONFIG0_INTR, rng_for(0, seed_agent))
+    return frustum_scene(n, SMALL_INTR, rng_for(0, seed_agent))
 
 
 def _room_map(n: int, rng: np.random.Generator, room) -> tuple:
@@ -212,16 +213,16 @@ def _room_map(n: int, rng: np.random.Generator, room) -> tuple:
     return means.astype(np.float32), scales, quats, opacity, colors
 
 
-def config1(n: int = 1_000_000, agent: int = 0, intr: Intrinsics = CONFIG1_INTR,
-            room=(6.0, 4.0, 3.0), config_id: int = 1) -> Scene:
+def room_view(n: int = 1_000_000, agent: int = 0, intr: Intrinsics = ROOM_INTR,
+            room=(6.0, 4.0, 3.0), stream: int = 1) -> Scene:
     """1200x680, fx=fy=600, 1M Gaussians in a 6x4x3 m room (70% planar with
     2 cm noise, 30% volumetric), camera at the room centre."""
-    rng = rng_for(config_id, agent)
+    rng = rng_for(stream, agent)
     m = _room_map(n, rng, room)
     return Scene(*m, room_center_pose(room), intr)
 
 
-def config2(n: int = 500_000, views: int = 8, intr: Intrinsics = CONFIG2_INTR):
+def keyframe_ring(n: int = 500_000, views: int = 8, intr: Intrinsics = VGA_INTR):
     """Mapping step: `views` keyframes on a horizontal 1 m circle (45 degree
     spacing), each facing radially outward; n/views Gaussians drawn in each
     keyframe's frustum at 1-5 m. Returns (map Scene for view 0, [viewmats])."""
@@ -242,21 +243,21 @@ def config2(n: int = 500_000, views: int = 8, intr: Intrinsics = CONFIG2_INTR):
     return scene, poses
 
 
-CONFIG3_SIZES = (200_000, 600_000, 1_200_000, 2_000_000)
-CONFIG3_ROOM_SCALE = (1.0, 1.2, 1.4, 1.6)
+FOUR_AGENT_SIZES = (200_000, 600_000, 1_200_000, 2_000_000)
+FOUR_AGENT_ROOM_SCALE = (1.0, 1.2, 1.4, 1.6)
 
 
-def config3(sizes=CONFIG3_SIZES, intr: Intrinsics = CONFIG1_INTR):
+def four_agent_rooms(sizes=FOUR_AGENT_SIZES, intr: Intrinsics = ROOM_INTR):
     """Batching: one room map per agent with its own seed and room size scaled
     by (1, 1.2, 1.4, 1.6), each rendered at 1200x680 from its room centre."""
     scenes = []
     for a, n in enumerate(sizes):
-        s = CONFIG3_ROOM_SCALE[a % len(CONFIG3_ROOM_SCALE)]
-        scenes.append(config1(n=n, agent=a, intr=intr, room=(6.0 * s, 4.0 * s, 3.0 * s), config_id=3))
+        s = FOUR_AGENT_ROOM_SCALE[a % len(FOUR_AGENT_ROOM_SCALE)]
+        scenes.append(room_view(n=n, agent=a, intr=intr, room=(6.0 * s, 4.0 * s, 3.0 * s), stream=3))
     return scenes
 
 
-def config4_agents(n_agents: int = 8, nmin: float = 1e5, nmax: float = 3e6, scale: float = 1.0):
+def serving_agents(n_agents: int = 8, nmin: float = 1e5, nmax: float = 3e6, scale: float = 1.0):
     """Serving: agent k keeps a resident room map of exp(U(ln nmin, ln nmax))
     Gaussians (times `scale`); agents 0-3 render 640x480, 4-7 1200x680."""
     rng = rng_for(4, 0, salt=1)
@@ -264,8 +265,8 @@ def config4_agents(n_agents: int = 8, nmin: float = 1e5, nmax: float = 3e6, scal
     out = []
     for a in range(n_agents):
         n = max(1, int(sizes[a] * scale))
-        intr = CONFIG2_INTR if a < n_agents // 2 else CONFIG1_INTR
-        out.append(config1(n=n, agent=a, intr=intr, config_id=4))
+        intr = VGA_INTR if a < n_agents // 2 else ROOM_INTR
+        out.append(room_view(n=n, agent=a, intr=intr, stream=4))
     return out
 
 

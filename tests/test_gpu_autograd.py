@@ -30,8 +30,8 @@ def _view(sc, vm):
 
 
 def test_mapping_step_through_autograd_matches_oracle_and_fd():
-    _log("config2 autograd: 8 views 640x480, 500k Gaussians")
-    sc, vms = scenes.config2()
+    _log("keyframe_ring autograd: 8 views 640x480, 500k Gaussians")
+    sc, vms = scenes.keyframe_ring()
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     m = {k: t(getattr(sc, k)).requires_grad_(True) for k, _ in KINDS}
@@ -101,7 +101,7 @@ def test_mapping_step_through_autograd_matches_oracle_and_fd():
 def test_autograd_requested_inputs_only():
     """Only the inputs that require grad get gradients; the pose-only and
     map-only paths agree with the full backward."""
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     up = [t(u) for u in scenes.upstream_grads(sc.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.5)]

@@ -21,7 +21,7 @@ def _log(msg):
 
 
 def _mixed_scenes():
-    out = [scenes.config0()]
+    out = [scenes.small_frustum()]
     intr = scenes.Intrinsics(37, 23, 30.0, 31.0, 18.3, 11.1)
     R0 = Rotation.from_euler("xyz", [6, -4, 9], degrees=True).as_matrix()
     vm = np.concatenate([R0, np.array([[0.04], [-0.03], [0.1]])], axis=1).reshape(12).astype(np.float32)
@@ -96,8 +96,8 @@ def test_batch_config3_full_size():
     """Four agents' room maps of 200k, 600k, 1.2M and 2M Gaussians at
     1200x680 in one batch, against each rendered alone and the oracle on the
     smallest."""
-    _log("config3 batch: 200k/600k/1.2M/2M at 1200x680")
-    scs = scenes.config3()
+    _log("four_agent_rooms batch: 200k/600k/1.2M/2M at 1200x680")
+    scs = scenes.four_agent_rooms()
     devs = [to_dev(sc) for sc in scs]
     opts = raster.RenderOptions(check=True)
     batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)

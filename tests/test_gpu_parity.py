@@ -36,9 +36,9 @@ def _dev_grads(g):
     (32, 64, True, 0, None), (16, 64, False, 64, None), (16, 64, True, 128, None), (32, 64, False, 128, None),
     (8, 32, True, 32, None), (16, 64, False, 128, "mfma"), (8, 64, False, 0, "mfma"), (16, 64, True, 0, "mfma"),
     (32, 64, False, 128, "mfma"), (32, 128, False, 0, "mfma")])
-def test_config0_forward_backward(tile, wb, scalar, bin_tile, bwd):
-    _log(f"config0 tile={tile} wb={wb} scalar={scalar} bin={bin_tile} bwd={bwd}")
-    sc = scenes.config0()
+def test_small_frustum_forward_backward(tile, wb, scalar, bin_tile, bwd):
+    _log(f"small_frustum tile={tile} wb={wb} scalar={scalar} bin={bin_tile} bwd={bwd}")
+    sc = scenes.small_frustum()
     job, imgs = run_job(sc, tile=tile, wave_batch=wb, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
     check_structure(job, sc, bin_tile or tile)
     ref = oracle.forward(sc)
@@ -52,7 +52,7 @@ def test_config0_forward_backward(tile, wb, scalar, bin_tile, bwd):
     _log(f"  grad worst {worst}")
 
 
-def test_config0_rotated_pose_and_ragged_image():
+def test_rotated_pose_and_ragged_image():
     _log("ragged 37x23 rotated pose")
     from scipy.spatial.transform import Rotation
     intr = scenes.Intrinsics(37, 23, 30.0, 31.0, 18.3, 11.1)
@@ -76,12 +76,12 @@ def test_config0_rotated_pose_and_ragged_image():
 @pytest.mark.parametrize("scalar,tile,bin_tile,bwd", [(False, 16, 0, None), (True, 16, 0, None),
                                                      (False, 32, 128, None), (False, 16, 128, "mfma"),
                                                      (False, 32, 128, "mfma"), (False, 32, 256, "mfma")])
-def test_config1_full_size(scalar, tile, bin_tile, bwd):
+def test_room_1m_full_size(scalar, tile, bin_tile, bwd):
     """1200x680, 1M Gaussians (the benchmark workload). Bin 0 (3225 bins)
     takes the global depth-sort path, bins of 128 the per-bin sort, and bins
     of 256 hold up to 30k pairs each, beyond one block's in-LDS sort."""
-    _log(f"config1 full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")
-    sc = scenes.config1()
+    _log(f"room_view full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")
+    sc = scenes.room_view()
     job, imgs = run_job(sc, tile=tile, wave_batch=64, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
     check_structure(job, sc, bin_tile or tile)
     ref = oracle.forward(sc)
@@ -113,7 +113,7 @@ def test_empty_map_and_all_culled():
 
 def test_capacity_overflow_is_reported_not_truncated():
     _log("overflow")
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     m, vm = to_dev(sc)
     from paper_2412_09723_amd import raster, _lib
     job = raster.Job(m, vm, sc.intr, raster.RenderOptions(pair_capacity=1000))
@@ -134,7 +134,7 @@ def test_repeat_determinism_of_forward():
     """Forward images and discrete state are bitwise identical across runs
     (no atomics in the forward)."""
     _log("determinism")
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     job, imgs = run_job(sc, tile=16, wave_batch=64)
     a = [t.clone() for t in imgs]
     s1 = job.state()["pair_rank"].clone()
@@ -146,7 +146,7 @@ def test_repeat_determinism_of_forward():
 
 def test_pose_only_and_map_only_flags():
     _log("flags")
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     job, _ = run_job(sc)
     up = _dev_grads(_up(sc))
     full = job.backward(*up)

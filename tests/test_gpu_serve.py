@@ -29,7 +29,7 @@ def agents():
 
 
 def serve_scenes():
-    return scenes.config4_agents(n_agents=4, scale=0.02)
+    return scenes.serving_agents(n_agents=4, scale=0.02)
 
 
 def _alone(agent, r, opts):

@@ -74,7 +74,7 @@ def test_pose_adam_step_matches_closed_form():
 
 def test_tracking_reduces_pose_error():
     print("tracking", flush=True)
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     m, _ = to_dev(sc)
     vm_true = scenes.perturb_pose(sc.viewmat, scenes.rng_for(0, 0, salt=3), trans=0.02, rot_deg=1.0)
     obs = raster.Job(m, torch.from_numpy(vm_true).cuda(), sc.intr, raster.RenderOptions(check=True)).forward()

@@ -68,7 +68,7 @@ def test_anisotropic_screen_covariance_matches_ewa():
     """Sigma' = J W Sigma W^T J^T + 0.3 I with Sigma from scipy's quaternion
     rotation; compared with the pinned conic factors (binary32 rounding)."""
     rng = np.random.default_rng(3)
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     R0 = Rotation.from_euler("xyz", [10, -20, 5], degrees=True).as_matrix()
     vm = np.concatenate([R0, np.array([[0.1], [-0.2], [0.3]])], axis=1).reshape(12)
     sc = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity, sc.colors, vm.astype(np.float32), sc.intr)
@@ -153,8 +153,8 @@ def test_alpha_clamp_and_floor():
 
 # --------------------------------------------------------------- invariants
 
-def test_invariants_config0():
-    sc = scenes.config0()
+def test_invariants_small_frustum():
+    sc = scenes.small_frustum()
     out = oracle.forward(sc)
     T = out["tfinal"]
     assert T.min() >= 1e-4 and T.max() <= 1.0
@@ -173,7 +173,7 @@ def test_invariants_config0():
 
 
 def test_colour_linearity():
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     rng = np.random.default_rng(5)
     c2 = rng.uniform(0, 1, sc.colors.shape).astype(np.float32)
     c3 = (0.25 * sc.colors.astype(np.float64) + 0.75 * c2.astype(np.float64)).astype(np.float32)
@@ -186,7 +186,7 @@ def test_colour_linearity():
 
 
 def test_permutation_invariance():
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     perm = np.random.default_rng(1).permutation(sc.n)
     pr = oracle.project(sc)
     assert len(np.unique(pr["zkey"][pr["visible"] == 1])) == int(pr["visible"].sum())
@@ -202,7 +202,7 @@ def test_rigid_motion_equivariance(shift):
     a 180 degree turn about z (exact in binary32), optionally with a
     translation (then the binary32 rounding of the moved means limits the
     agreement to ~1e-7)."""
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     Rg = np.diag([-1.0, -1.0, 1.0])
     d = shift * np.array([0.5, 0.25, -0.125])
     means = (Rg @ sc.means.astype(np.float64) + d[:, None]).astype(np.float32)
@@ -257,7 +257,7 @@ def test_pixel_box_contains_every_accepted_pixel():
     box (the box has a 2^-8 margin over 3 sigma), so skipping pixels outside
     the box never changes a result. Checked by brute force, including very
     elongated splats."""
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     rng = np.random.default_rng(11)
     sc.scales[:, :200] = np.stack([np.full(200, 0.3), np.full(200, 0.002), np.full(200, 0.002)])
     sc.opacity[:200] = 0.999
@@ -276,7 +276,7 @@ def test_pixel_box_contains_every_accepted_pixel():
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_tile_lists_brute_force(tile):
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     pr = oracle.project(sc)
     offsets, ids = oracle.tile_lists(pr, 160, 120, tile)
     TX, TY = (160 + tile - 1) // tile, (120 + tile - 1) // tile
@@ -293,7 +293,7 @@ def test_tile_lists_brute_force(tile):
 def test_tile_size_invariance_of_image():
     """The definition has no tiles: the oracle's image is identical for any
     candidate bucketing, checked against a scene shifted by whole buckets."""
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     a = oracle.forward(sc)
     assert np.isfinite(a["rgb"]).all()
     # the brute force (no buckets at all) on a crop-sized scene gives the same pixels
@@ -419,7 +419,7 @@ def test_frozen_fd_matches_pose_gradients():
 
 
 def test_upstream_linearity():
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     g1 = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 1, salt=1), 1.0, 0.5)
     g2 = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 2, salt=1), 0.3, 1.0)
     a, b = 0.5, -1.25
@@ -435,7 +435,7 @@ def test_margin_flags_cover_every_gaussian_at_a_flagged_pixel():
     """A decision inside its margin can change T for the whole pixel, so every
     Gaussian composited at a flagged pixel is excluded from the elementwise
     gradient comparison."""
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     f = oracle.forward(sc)
     rec = oracle.record(sc)
     g = oracle.backward(sc, *scenes.upstream_grads(sc.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.5))
@@ -449,7 +449,7 @@ def test_margin_flags_cover_every_gaussian_at_a_flagged_pixel():
 
 
 def test_culled_gaussians_get_zero_gradient():
-    sc = scenes.config0()
+    sc = scenes.small_frustum()
     sc.means[2, :10] = -1.0            # behind the camera
     g = scenes.upstream_grads(sc.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.5)
     out = oracle.backward(sc, *g)

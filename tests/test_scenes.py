@@ -7,7 +7,7 @@ from paper_2412_09723_amd import scenes
 
 
 def test_config0_deterministic_and_shaped():
-    a, b = scenes.config0(), scenes.config0()
+    a, b = scenes.small_frustum(), scenes.small_frustum()
     for k in ("means", "scales", "quats", "opacity", "colors", "viewmat"):
         assert np.array_equal(getattr(a, k), getattr(b, k))
     assert a.means.shape == (3, 4096) and a.means.dtype == np.float32
@@ -16,7 +16,7 @@ def test_config0_deterministic_and_shaped():
 
 
 def test_config0_distributions():
-    s = scenes.config0()
+    s = scenes.small_frustum()
     z = s.means[2]
     assert z.min() >= 1.0 and z.max() <= 5.0
     u = s.intr.fx * s.means[0] / z + s.intr.cx
@@ -66,7 +66,7 @@ def test_perturb_pose_magnitudes():
 
 
 def test_upstream_grads_shape_and_scale():
-    intr = scenes.CONFIG0_INTR
+    intr = scenes.SMALL_INTR
     gc, gd, gs = scenes.upstream_grads(intr, scenes.rng_for(0, 0, salt=2), 0.5, 0.0)
     assert gc.shape == (3, 120, 160) and gd.shape == (120, 160)
     assert np.allclose(np.abs(gc), 1.0 / (3 * 120 * 160))
@@ -84,7 +84,7 @@ def test_poisson_trace_reproducible():
 
 def test_autotune_shape_key_buckets_sizes():
     from paper_2412_09723_amd import autotune, scenes
-    i1, i2 = scenes.CONFIG1_INTR, scenes.CONFIG2_INTR
+    i1, i2 = scenes.ROOM_INTR, scenes.VGA_INTR
     assert autotune.shape_key([1000, 5000], [i1, i2]) == autotune.shape_key([1023, 4097], [i1, i2])
     assert autotune.shape_key([1000], [i1]) != autotune.shape_key([1000], [i2])
     assert autotune.shape_key([1000, 5000], [i1, i2]).startswith("2|")
