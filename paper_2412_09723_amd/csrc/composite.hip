@@ -64,9 +64,8 @@ __device__ inline Staged inert_entry() {
 constexpr float kMomentSpread = MS_MOMENT_SPREAD;
 
 // Conservative test that a record's acceptance ellipse can reach a pixel of
-// the 8x8 sub-block at (X0, Y0), evaluated on the quad lane that holds the
-// conic (a, b, c, qcut); the centre (ui, vi, uf, vf) comes from the quad's
-// first lane. The offsets the pixels use, dx = (x - ui) - uf rounded, lie in
+// the 8x8 sub-block at (X0, Y0), from the record's centre words ctr = (ui,
+// vi, uf, vf) and conic words con = (a, b, c, qcut). The offsets the pixels use, dx = (x - ui) - uf rounded, lie in
 // [x0, x1] (rounding is monotonic), likewise dy in [y0, y1]. Over that
 // rectangle |a dx + b dy| >= m1 and |c dy| >= m2 (interval bounds). A pixel
 // with q <= qcut has |t1|, |t2| within a few units in the last place of
@@ -76,13 +75,12 @@ constexpr float kMomentSpread = MS_MOMENT_SPREAD;
 // With kSpread, `wide` tells whether the record's moments about the sub-block
 // centre are badly conditioned (kMomentSpread).
 template <bool kSpread>
-__device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0, bool& wide) {
+__device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X0, int Y0, bool& wide) {
   constexpr float kEps = 0x1p-20f;
-  const float ui = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.x, 0x00, 0xF, 0xF, false));
-  const float vi = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.y, 0x00, 0xF, 0xF, false));
-  const float uf = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.z, 0x00, 0xF, 0xF, false));
-  const float vf = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)v.w, 0x00, 0xF, 0xF, false));
-  const float a = __uint_as_float(v.x), b = __uint_as_float(v.y), c = __uint_as_float(v.z), qc = __uint_as_float(v.w);
+  const float ui = __uint_as_float(ctr.x), vi = __uint_as_float(ctr.y);
+  const float uf = __uint_as_float(ctr.z), vf = __uint_as_float(ctr.w);
+  const float a = __uint_as_float(con.x), b = __uint_as_float(con.y), c = __uint_as_float(con.z),
+              qc = __uint_as_float(con.w);
   const float gx = (float)X0 - ui, gy = (float)Y0 - vi;   // exact
   const float x0 = gx - uf, x1 = (7.f + gx) - uf;
   const float y0 = gy - vf, y1 = (7.f + gy) - vf;
@@ -108,16 +106,22 @@ __device__ inline bool ellipse_reaches(const uint4& v, int X0, int Y0, bool& wid
 // order, and returns how many there are (wave-uniform). Lane j reads pair
 // word j (coalesced); the records are then read four lanes per 64-byte
 // record, so each load instruction covers 16 whole records rather than 64
-// scattered 16-byte pieces. The quad's last lane holds the record's pixel
-// box and its second lane the conic; a record is packed when the box meets
-// the sub-block and ellipse_reaches holds, and a ballot plus a masked bit
-// count gives each packed record its slot. With kSpread, misc.w of a packed
-// record is 1 where its block-centred moments are badly conditioned.
+// scattered 16-byte pieces. Lane j first tests record j's acceptance ellipse
+// against the sub-block (ellipse_reaches, one record per lane); the quad's
+// last lane then holds the record's pixel box, a record is packed when the
+// box meets the sub-block and the ellipse test held, and a ballot plus a
+// masked bit count gives each packed record its slot. With kSpread, misc.w
+// of a packed record is 1 where its block-centred moments are badly
+// conditioned.
 template <bool kSpread>
 __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                   uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
                                   Staged* __restrict__ dst) {
   const uint32_t rank = lane < n ? (pval[start + lo + (uint32_t)lane] & rank_mask) : 0u;
+  bool reach = false, wide = false;
+  if (lane < n) reach = ellipse_reaches<kSpread>(rec[4 * (int64_t)rank], rec[4 * (int64_t)rank + 1], X0, Y0, wide);
+  const uint64_t rm = __builtin_amdgcn_ballot_w64(reach);
+  const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
   const int part = lane & 3, sub = lane >> 2;
   uint4 v[4];
   uint32_t rk[4];
@@ -134,17 +138,14 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
     if (16 * k < n) {   // uniform
       const int e = 16 * k + sub;
       bool touch = false;
-      if (part == 3 && e < n) {
+      // a record is packed when its box meets the sub-block and its ellipse can
+      // reach a pixel centre of it
+      if (part == 3 && e < n && ((rm >> e) & 1u)) {
         const int bx0 = (int)(v[k].y & 0xFFFFu), bx1 = (int)(v[k].y >> 16);
         const int by0 = (int)(v[k].z & 0xFFFFu), by1 = (int)(v[k].z >> 16);
         touch = bx0 <= X0 + 7 && bx1 >= X0 && by0 <= Y0 + 7 && by1 >= Y0;
       }
-      bool wide = false;
-      const bool reach = ellipse_reaches<kSpread>(v[k], X0, Y0, wide);   // meaningful on the conic lane (part 1)
-      const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
-      // a record is packed when its box meets the sub-block and its ellipse can
-      // reach a pixel centre of it
-      const uint64_t m = __builtin_amdgcn_ballot_w64(touch) & (__builtin_amdgcn_ballot_w64(reach) << 2);
+      const uint64_t m = __builtin_amdgcn_ballot_w64(touch);
       if ((m >> (4 * sub + 3)) & 1u) {
         // packed records before this one: their box lanes lie below this quad
         const int slot =
@@ -156,7 +157,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
           o.y = (float)Y0 - o.y;
         } else if (part == 3) {
           o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u),
-                          ((wm >> (4 * sub + 1)) & 1u) ? 1.f : 0.f);
+                          ((wm >> e) & 1u) ? 1.f : 0.f);
         }
         reinterpret_cast<float4*>(dst + slot)[part] = o;
       }
