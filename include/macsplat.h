@@ -78,7 +78,7 @@
  * 3x4 world-to-camera matrix [R|t]. Arrays are structure-of-arrays float32:
  * means [3][n], scales [3][n] (standard deviations in metres), quats [4][n]
  * (w, x, y, z; any non-zero norm, normalised inside), opacity [n] (already in
- * (0,1)), colors [3][n] (RGB). Images are planar: rgb [3][H][W], depth and
+ * (0,1); 0 is accepted and composites nowhere), colors [3][n] (RGB). Images are planar: rgb [3][H][W], depth and
  * silhouette [H][W].
  *
  * Memory and streams. Every array pointer is a DEVICE pointer unless stated

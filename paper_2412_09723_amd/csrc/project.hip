@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     const double gu = -a_ * c2 * P1;
     const double gv = -(b_ * c2 * P1 + c_ * c2 * P2);
     const double gl11 = kKappa * c2 * P1x, gl12 = kKappa * c2 * P1y, gl22 = kKappa * c2 * P2y;
-    go = (float)(E * (1.0 / o));
+    go = (float)(o > 0.0 ? E * (1.0 / o) : 0.0);   // opacity 0 composites nowhere (E = 0)
     // Cholesky factors -> (S00, S01, S11)
     const double r_dsq = r_d * r_sqd * r_sqs2;   // 1 / (d sqrt(d s2))
     const double gS0 = gl11 * (-0.5 * l11 * s2 * r_d) + gl12 * (-0.5 * l12 * s2 * r_d);

@@ -223,3 +223,37 @@ def test_extreme_image_shapes(W, H, tile, bin_tile):
     g = job.backward(*_dev_grads(up))
     torch.cuda.synchronize()
     check_grads(g, oracle.backward(sc, *up))
+
+
+def test_degenerate_gaussians_mixed_into_a_scene():
+    """A scene with degenerate Gaussians sprinkled in: zero-norm rotation,
+    zero, tiny, NaN and huge scales, non-finite colour and opacity, opacity 0
+    and 1, a centre far outside the guard band, one on the near plane. The
+    structure, images and gradients must match the oracle, which culls the
+    same ones; culled Gaussians get exactly zero gradients."""
+    _log("degenerate mix")
+    intr = scenes.Intrinsics(96, 72, 90.0, 90.0, 48.0, 36.0)
+    sc = scenes.frustum_scene(600, intr, scenes.rng_for(9, 555))
+    sc.quats[:, 0] = 0.0                       # zero-norm rotation
+    sc.scales[:, 1] = 0.0                      # zero scale: dilation only
+    sc.scales[:, 2] = 1e-7                     # tiny
+    sc.scales[0, 3] = np.nan                   # non-finite scale
+    sc.scales[:, 4] = 5e3                      # far beyond the 2D variance limit
+    sc.colors[1, 5] = np.inf                   # non-finite colour
+    sc.opacity[6] = np.nan                     # non-finite opacity
+    sc.opacity[7] = 0.0                        # never accepted
+    sc.opacity[8] = 1.0                        # clamped alpha
+    sc.means[0, 9] = sc.means[2, 9] * 1e5      # centre far outside the guard band
+    sc.means[2, 10] = 0.2                      # on the near plane
+    job, imgs = run_job(sc, tile=16, wave_batch=64, bwd="mfma")
+    pr, _ = check_structure(job, sc, 16)
+    check_images(imgs, oracle.forward(sc))
+    up = _up(sc, 1.0, 1.0, salt=11)
+    g = job.backward(*_dev_grads(up))
+    torch.cuda.synchronize()
+    check_grads(g, oracle.backward(sc, *up))
+    culled = np.flatnonzero(pr["visible"] == 0)
+    assert len(culled) >= 5
+    for k in ("means", "scales", "quats", "opacity", "colors"):
+        a = g[k].detach().cpu().numpy().reshape(-1, sc.n)
+        assert not a[:, culled].any(), k
