@@ -257,3 +257,26 @@ def test_degenerate_gaussians_mixed_into_a_scene():
     for k in ("means", "scales", "quats", "opacity", "colors"):
         a = g[k].detach().cpu().numpy().reshape(-1, sc.n)
         assert not a[:, culled].any(), k
+
+
+def test_long_bin_segment_with_depth_ties():
+    """One bin holding 20000 pairs (more than a workgroup sorts in LDS), with
+    exact depth ties: the chunked global-memory sort must keep (depth, index)
+    order too."""
+    _log("long segment with ties")
+    intr = scenes.Intrinsics(48, 40, 60.0, 60.0, 24.0, 20.0)
+    sc = scenes.frustum_scene(20000, intr, scenes.rng_for(9, 777))
+    z = np.array([2.0, 2.5, 3.0, 3.5], np.float32)[np.arange(sc.n) % 4]
+    sc.means[0] *= z / sc.means[2]
+    sc.means[1] *= z / sc.means[2]
+    sc.means[2] = z
+    job, imgs = run_job(sc, tile=16, wave_batch=64, bin_tile=128, bwd="mfma")
+    _, st = check_structure(job, sc, 128)
+    assert st["list_kind"] == 1
+    lens = st["tile_range"].view(np.uint32).astype(np.int64)
+    assert (lens[:, 1] - lens[:, 0]).max() > 16384
+    check_images(imgs, oracle.forward(sc))
+    up = _up(sc)
+    g = job.backward(*_dev_grads(up))
+    torch.cuda.synchronize()
+    check_grads(g, oracle.backward(sc, *up))
