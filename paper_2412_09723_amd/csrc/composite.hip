@@ -706,7 +706,7 @@ constexpr int kGrp = 8;                        // Gaussians per product
 constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
 constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
 #ifndef MS_BWD_CHUNK
-#define MS_BWD_CHUNK 32
+#define MS_BWD_CHUNK 48
 #endif
 constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per staging round
 constexpr int kBwdStep = 4;                    // entries whose alphas are evaluated together
