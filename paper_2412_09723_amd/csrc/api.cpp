@@ -120,14 +120,13 @@ bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, 
                  int64_t& pixels) {
   t.njobs = njobs;
   int64_t g = 0, pix = 0;
-  int tl = 0, bn = 0, blk = 0;
+  int tl = 0, bn = 0;
   for (int j = 0; j < njobs; j++) {
     JobDesc& J = t.job[j];
     J.g0 = g;
-    J.block0 = blk;
+    J.block0 = (int)(g / 256);
     J.blocks = (int)((J.n + 255) / 256);
-    blk += J.blocks;
-    g += (int64_t)J.blocks * 256;
+    g += (J.n + kAdjSlots - 1) / kAdjSlots * kAdjSlots;
     J.tx = (J.W + tile - 1) / tile;
     J.tile0 = tl;
     J.tiles = J.tx * ((J.H + tile - 1) / tile);
@@ -170,7 +169,7 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   const int64_t nn = n > 0 ? n : 1;
   const int64_t cc = cap > 0 ? cap : 1;
   p.scan_blocks_n = (int)((nn + 2047) / 2048);
-  p.pose_blocks = (int)((nn + 255) / 256);
+  p.pose_blocks = (int)((nn + kAdjSlots - 1) / kAdjSlots);
   p.rank_bits = 1;
   while (p.rank_bits < 31 && ((int64_t)1 << p.rank_bits) < nn) p.rank_bits++;
   // per-bin path: units of kUnitThreads * R Gaussians, R a power of two in
@@ -417,7 +416,7 @@ int32_t batch_table(int32_t njobs, const ms_job* jobs, const ms_options* opts, i
     }
   }
   int64_t total = 0;
-  for (int j = 0; j < njobs; j++) total += (jobs[j].map.n + 255) / 256 * 256;
+  for (int j = 0; j < njobs; j++) total += (jobs[j].map.n + kAdjSlots - 1) / kAdjSlots * kAdjSlots;
   if (total > (int64_t)0x7FFFFFFF) return fail(MS_ERR_INVALID_ARG, "batch of %lld Gaussian slots", (long long)total);
   return MS_OK;
 }

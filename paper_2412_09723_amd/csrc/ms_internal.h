@@ -63,13 +63,15 @@ __device__ inline void work_add(uint64_t* counters, int slot, int which, uint64_
 // ------------------------------------------------------------------ batches
 // A batch renders several jobs (a map, a camera, its images) through one
 // launch sequence. Job j's Gaussians take the virtual indices [g0, g0 + n)
-// (g0 a multiple of 256, so each projection block belongs to one job), its
+// (g0 a multiple of kAdjSlots, so each projection block and each adjoint
+// block belongs to one job), its
 // compositing tiles the global tile ids [tile0, tile0 + tiles), its bins
 // [bin0, bin0 + bins) and its pixels [pix0, pix0 + W*H) of the per-pixel
 // arrays. The depth sort and the pair sort run once over all jobs: restricted
 // to one job's Gaussians, the global (depth, index) order is that job's own
 // order, and every bin belongs to one job. A single render is a batch of one.
 constexpr int kMaxJobs = 12;
+constexpr int kAdjSlots = 1024;   // Gaussian slots per projection-adjoint block (four per thread)
 struct JobDesc {
   const float *means, *scales, *quats, *opacity, *colors;   // map, SoA [k][n]
   const float* viewmat;                                      // [12]
@@ -81,7 +83,7 @@ struct JobDesc {
   float fx, fy, cx, cy;
   int tile0, tiles, tx;      // compositing tiles
   int bin0, bins, bx;        // bins
-  int block0, blocks;        // projection blocks of 256 Gaussians
+  int block0, blocks;        // projection blocks of 256 Gaussians (block0 a multiple of kAdjSlots / 256)
   uint32_t flags;            // MS_FLAG_POSE_GRAD_ONLY / MS_FLAG_NO_POSE_GRAD for this job
 };
 struct JobTable {

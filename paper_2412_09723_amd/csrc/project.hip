@@ -252,33 +252,42 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
                                                      float* __restrict__ g2d,
                                                      const uint64_t* __restrict__ counters,
                                                      double* __restrict__ pose_part) {
-  __shared__ int s_list[256];
-  __shared__ int s_wcnt[256 / 64];
-  const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x)];
+  constexpr int kSub = kAdjSlots / 256;   // slots per thread
+  __shared__ int s_list[kAdjSlots];
+  __shared__ int s_wcnt[kSub][256 / 64];
+  const JobDesc& J = jobs[job_of_block(jobs, njobs, (int)blockIdx.x * kSub)];
   const int64_t n = J.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // The block's visible Gaussians are packed onto its first threads, so the
-  // long binary64 path runs on as few waves as the block has visible
-  // Gaussians; invisible ones only get zero gradients from their own thread.
-  const int64_t li0 = (int64_t)((int)blockIdx.x - J.block0) * 256;   // block's first index within the job
-  const int64_t li_own = li0 + threadIdx.x;
-  const bool own_valid = li_own < n;
-  const bool own_vis = own_valid && key[J.g0 + li_own] != 0xFFFFFFFFu;
-  const uint64_t vm = __ballot(own_vis);
-  if (lane == 0) s_wcnt[wave] = __popcll(vm);
-  __syncthreads();
-  int vbase = 0, nvis = 0;
-  for (int w = 0; w < 256 / 64; w++) {
-    if (w < wave) vbase += s_wcnt[w];
-    nvis += s_wcnt[w];
+  // The block's kAdjSlots slots (slot s * 256 + t belongs to thread t) are
+  // checked for visibility, and the visible Gaussians are packed in index
+  // order onto the block's threads, so every wave runs the long binary64
+  // path with nearly all lanes busy (a quarter of the slots are visible in a
+  // typical frame); the owners of invisible slots write zero gradients.
+  const int64_t li0 = ((int64_t)blockIdx.x * kSub - J.block0) * 256;   // block's first index within the job
+  bool own_vis[kSub];
+  uint64_t vm[kSub];
+#pragma unroll
+  for (int u = 0; u < kSub; u++) {
+    const int64_t li = li0 + u * 256 + threadIdx.x;
+    own_vis[u] = li < n && key[J.g0 + li] != 0xFFFFFFFFu;
+    vm[u] = __ballot(own_vis[u]);
+    if (lane == 0) s_wcnt[u][wave] = __popcll(vm[u]);
   }
-  if (own_vis)
-    s_list[vbase + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u))] =
-        (int)threadIdx.x;
   __syncthreads();
-  const bool heavy = (int)threadIdx.x < nvis;
-  const int64_t li = heavy ? li0 + s_list[threadIdx.x] : li_own;   // index within the job (heavy path)
-  const int64_t i = J.g0 + li;                                       // virtual index
+  int vbase[kSub], nvis = 0;
+#pragma unroll
+  for (int u = 0; u < kSub; u++)
+    for (int w = 0; w < 256 / 64; w++) {
+      if (w == wave) vbase[u] = nvis;
+      nvis += s_wcnt[u][w];
+    }
+#pragma unroll
+  for (int u = 0; u < kSub; u++)
+    if (own_vis[u])
+      s_list[vbase[u] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vm[u] >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)vm[u], 0u))] =
+          u * 256 + (int)threadIdx.x;
+  __syncthreads();
   const float* __restrict__ means = J.means;
   const float* __restrict__ scales = J.scales;
   const float* __restrict__ quats = J.quats;
@@ -291,9 +300,26 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const bool map_grads = !(J.flags & MS_FLAG_POSE_GRAD_ONLY);
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool overflow = counters[C_OVERFLOW] != 0;
+  if (map_grads) {
+#pragma unroll
+    for (int u = 0; u < kSub; u++) {
+      const int64_t li = li0 + u * 256 + threadIdx.x;
+      if (li < n && !own_vis[u]) {
+        for (int k = 0; k < 3; k++) {
+          J.gm[k * n + li] = 0.f;
+          J.gs[k * n + li] = 0.f;
+          J.gc[k * n + li] = 0.f;
+        }
+        for (int k = 0; k < 4; k++) J.gq[k * n + li] = 0.f;
+        J.go[li] = 0.f;
+      }
+    }
+  }
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
-  float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
-  if (heavy) {
+  for (int h = threadIdx.x; h < nvis; h += 256) {
+    const int64_t li = li0 + s_list[h];   // index within the job
+    const int64_t i = J.g0 + li;          // virtual index
+    float gm[3], gs[3], gq[4], go, gc[3];
     // accumulator row: by depth rank (global sort path) or by index (per-bin
     // path, where the row is cleared after use for the next backward)
     const int64_t r = rank_of ? (int64_t)rank_of[i] : i;
@@ -436,43 +462,30 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       for (int k = 0; k < 4; k++) gq[k] = nanv;
       go = nanv;
     }
-  }
-  // heavy threads write their visible Gaussian's gradients and the owners of
-  // invisible ones write zeros (a thread can do both): every index once
-  if (map_grads && own_valid && !own_vis) {
-    for (int k = 0; k < 3; k++) {
-      J.gm[k * n + li_own] = 0.f;
-      J.gs[k * n + li_own] = 0.f;
-      J.gc[k * n + li_own] = 0.f;
+    if (map_grads) {
+      for (int k = 0; k < 3; k++) {
+        J.gm[k * n + li] = gm[k];
+        J.gs[k * n + li] = gs[k];
+        J.gc[k * n + li] = gc[k];
+      }
+      for (int k = 0; k < 4; k++) J.gq[k * n + li] = gq[k];
+      J.go[li] = go;
     }
-    for (int k = 0; k < 4; k++) J.gq[k * n + li_own] = 0.f;
-    J.go[li_own] = 0.f;
-  }
-  if (map_grads && heavy) {
-    for (int k = 0; k < 3; k++) {
-      J.gm[k * n + li] = gm[k];
-      J.gs[k * n + li] = gs[k];
-      J.gc[k * n + li] = gc[k];
-    }
-    for (int k = 0; k < 4; k++) J.gq[k * n + li] = gq[k];
-    J.go[li] = go;
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
-  // block reduction of the 12 pose partials of the visible threads: through
-  // LDS, in a fixed order (16 partial sums of 16 threads each, then their sum)
+  // block reduction of the 12 pose partials of the threads: through LDS, in a
+  // fixed order (16 partial sums of 16 threads each, then their sum)
   __shared__ double pr[12][256];
   __shared__ double ps[12][16];
-  if (heavy) {
-    for (int a = 0; a < 3; a++) {
-      for (int b = 0; b < 3; b++) pr[3 * a + b][threadIdx.x] = GR[a][b];
-      pr[9 + a][threadIdx.x] = Gt[a];
-    }
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 3; b++) pr[3 * a + b][threadIdx.x] = GR[a][b];
+    pr[9 + a][threadIdx.x] = Gt[a];
   }
   __syncthreads();
   if (threadIdx.x < 12 * 16) {
     const int k = threadIdx.x >> 4, seg = threadIdx.x & 15;
     double acc = 0.0;
-    for (int j = seg * 16; j < seg * 16 + 16 && j < nvis; j++) acc += pr[k][j];
+    for (int j = seg * 16; j < seg * 16 + 16; j++) acc += pr[k][j];
     ps[k][seg] = acc;
   }
   __syncthreads();
@@ -498,8 +511,8 @@ __global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __re
   const float* viewmat = J.viewmat;
   float* gview = J.gview;
   float* gtwist = J.gtwist;
-  const int nblocks = J.n > 0 ? J.blocks : 0;
-  part += (int64_t)J.block0 * 12;
+  const int nblocks = (int)((J.n + kAdjSlots - 1) / kAdjSlots);   // adjoint blocks of this job
+  part += (int64_t)(J.block0 / (kAdjSlots / 256)) * 12;
   // thread t folds partials t, t + 256, ...; then 16 sums of 16 threads and
   // their sum, all in a fixed order
   double acc[12];
@@ -574,7 +587,7 @@ hipError_t launch_project_fwd(const Plan& p, float near_z, const JobTable& t, ui
 hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_t st) {
   const JobDesc* jobs = at<JobTable>(ws, p.jobs)->job;
   if (p.n > 0) {
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)(p.n / 256)), dim3(256), 0, st, jobs, p.njobs,
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)(p.n / kAdjSlots)), dim3(256), 0, st, jobs, p.njobs,
                        at<uint32_t>(ws, p.key), p.by_index ? nullptr : at<int32_t>(ws, p.rank_of),
                        at<float>(ws, p.g2d),
                        at<uint64_t>(ws, p.counters), at<double>(ws, p.pose_part));
