@@ -776,8 +776,8 @@ constexpr int kSortItems = 16;
 constexpr int kSortMax = kSortThreads * kSortItems;
 constexpr int kSortDigits = 512;
 
-struct SortShared {
-  uint32_t buf[kSortMax];
+struct alignas(16) SortShared {
+  uint32_t buf[kSortMax];   // scatter/gather buffer; while ranking, the waves' peer masks
   uint32_t wcnt[kSortWaves][kSortDigits];
   uint32_t doff[kSortDigits];
   uint32_t wsum[kSortDigits / 64];
@@ -786,16 +786,25 @@ struct SortShared {
 
 // Ranks the valid items of one chunk within each wave by the digit
 // (k >> shift) & (2^dbits - 1); afterwards S.wcnt[w][d] holds wave w's count
-// of digit d. A lane's peers (same digit) are the lanes that agree with it on
-// every digit bit: per bit, peers &= ~(ballot(bit) ^ mine), mine = 0 or ~0.
+// of digit d. A lane's peers (the lanes of its round with the same digit)
+// come from a 64-bit mask per digit in LDS: every lane ORs its own bit into
+// its digit's mask, reads the mask back, and the lowest peer clears it. The
+// OR is order-independent, and a wave's LDS operations complete in program
+// order, so the masks are exact. They live in S.buf, which is free while
+// the waves rank.
+static_assert(sizeof(uint32_t) * kSortMax >= sizeof(uint64_t) * kSortWaves * kSortDigits,
+              "peer masks must fit the scatter buffer");
 __device__ inline void sort_rank(SortShared& S, const uint32_t (&k)[kSortItems], uint32_t (&rk)[kSortItems],
                                  int ipt, int chunk_n, int shift, int dbits) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const uint32_t lt_lo = lane >= 32 ? 0xFFFFFFFFu : ((1u << lane) - 1u);
-  const uint32_t lt_hi = lane <= 32 ? 0u : ((1u << (lane - 32)) - 1u);
+  const uint64_t bit = 1ull << lane, below_me = bit - 1ull;
   const uint32_t dmask = (1u << dbits) - 1u;
   uint32_t* my = S.wcnt[wave];
-  for (int d = lane; d < (1 << dbits); d += 64) my[d] = 0u;
+  uint64_t* peers = reinterpret_cast<uint64_t*>(S.buf) + wave * kSortDigits;
+  for (int d = lane; d < (1 << dbits); d += 64) {
+    my[d] = 0u;
+    peers[d] = 0ull;
+  }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int r = 0; r < kSortItems; r++) {
@@ -803,19 +812,17 @@ __device__ inline void sort_rank(SortShared& S, const uint32_t (&k)[kSortItems],
       const int pos = wave * ipt * 64 + r * 64 + lane;
       const bool ok = pos < chunk_n;
       const uint32_t dg = (k[r] >> shift) & dmask;
-      const uint64_t v = __ballot(ok);
-      uint32_t pl = (uint32_t)v, ph = (uint32_t)(v >> 32);
-      for (int bit = 0; bit < dbits; bit++) {
-        const uint32_t mine = (uint32_t)((int32_t)(dg << (31 - bit)) >> 31);
-        const uint64_t m = __ballot(mine != 0u);
-        pl &= ~((uint32_t)m ^ mine);
-        ph &= ~((uint32_t)(m >> 32) ^ mine);
-      }
+      if (ok) atomicOr(&peers[dg], bit);
+      __builtin_amdgcn_wave_barrier();
+      const uint64_t pm = ok ? peers[dg] : 0ull;
       const uint32_t old = ok ? my[dg] : 0u;
-      const uint32_t below = (uint32_t)(__popc(pl & lt_lo) + __popc(ph & lt_hi));
+      const uint32_t below = (uint32_t)__popcll(pm & below_me);
       rk[r] = old + below;
       __builtin_amdgcn_wave_barrier();
-      if (ok && below == 0) my[dg] = old + (uint32_t)(__popc(pl) + __popc(ph));
+      if (ok && below == 0) {
+        my[dg] = old + (uint32_t)__popcll(pm);
+        peers[dg] = 0ull;
+      }
       __builtin_amdgcn_wave_barrier();
     }
   }
