@@ -74,6 +74,35 @@ def test_batch_equals_alone_and_oracle(tile, bin_tile, bwd):
             assert not any(t.any() for t in outs[j])
 
 
+def test_batch_empty_maps_first_and_between():
+    """Empty maps ahead of and between non-empty ones: an empty job owns no
+    Gaussian slots, so its slot range coincides with the next job's start;
+    every projection and adjoint block must still find the non-empty job."""
+    mixed = _mixed_scenes()
+    empty, tiny, small, mid = mixed[3], mixed[1], mixed[0], mixed[2]
+    scs = [empty, tiny, empty, small, mid, empty]
+    _log(f"batch with empty maps at 0, 2, 5: n = {[sc.n for sc in scs]}")
+    opts = raster.RenderOptions(check=True)
+    devs = [to_dev(sc) for sc in scs]
+    batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)
+    outs = batch.forward()
+    ups = [_dev(_upstream(sc, j)) for j, sc in enumerate(scs)]
+    gbs = batch.backward(ups)
+    torch.cuda.synchronize()
+    for j, sc in enumerate(scs):
+        m, vm = devs[j]
+        alone = raster.Job(m, vm, sc.intr, opts)
+        for x, y in zip(outs[j], alone.forward()):
+            assert torch.equal(x, y), j
+        ga = alone.backward(*ups[j])
+        torch.cuda.synchronize()
+        check_reordered_grads(gbs[j], ga, (KEYS if sc.n else ()) + ("viewmat", "twist"))
+        if not sc.n:
+            assert not any(t.any() for t in outs[j])
+            assert not gbs[j]["twist"].any() and not gbs[j]["viewmat"].any()
+    check_grads(gbs[1], oracle.backward(tiny, *_upstream(tiny, 1)))
+
+
 def test_batch_per_job_gradient_flags():
     """Tracking (pose-only) and mapping (all gradients) jobs in one batch."""
     scs = _mixed_scenes()[:3]
