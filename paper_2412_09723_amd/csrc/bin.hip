@@ -769,7 +769,7 @@ __global__ void __launch_bounds__(kUnitThreads) k_unit_emit(const uint2* __restr
 // global memory, 4 passes of 8 bits. Item order within a chunk: wave w holds
 // positions [w*ipt*64, (w+1)*ipt*64) in rounds of 64, so (wave, round, lane)
 // is the segment order and a wave ranks its items against its own digit
-// counters (ballot matching, no block barrier), as in the onesweep pass.
+// counters (peer masks, no block barrier).
 constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItems = 16;
