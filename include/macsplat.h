@@ -302,6 +302,20 @@ int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_
 int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms_intrinsics* intr, float w_rgb,
                         float w_depth, float w_sil, const ms_images* grad, float* loss, void* stream);
 
+/* SSIM term of the mapping objective (Eq. 7), with the SSIM formula of the
+ * evaluation-metrics appendix computed from local statistics under an 11x11
+ * Gaussian window (standard deviation 1.5 px, weights summing to 1; zero
+ * outside the image), C1 = 0.01^2, C2 = 0.03^2 for intensities on [0, 1]:
+ *   loss = weight * (1 - mean SSIM(pred, target)) over all channels and pixels,
+ * and its gradient with respect to pred (target is fixed).
+ * pred, target, grad: device float [channels][height][width], planar, caller-
+ * owned; grad must not overlap pred or target. accumulate = 0 overwrites
+ * grad and *loss, 1 adds to them (so the term can join an L1 gradient).
+ * loss: device float, or NULL. channels in [1, 16], sizes in [1, 16384];
+ * otherwise MS_ERR_INVALID_ARG and nothing is enqueued. Enqueued on `stream`. */
+int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channels, int32_t width, int32_t height,
+                          float weight, float* grad, int32_t accumulate, float* loss, void* stream);
+
 /* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
  * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
  * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]

@@ -602,6 +602,41 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
   return MS_OK;
 }
 
+int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channels, int32_t width, int32_t height,
+                          float weight, float* grad, int32_t accumulate, float* loss, void* stream) {
+  if (!pred || !target || !grad) return fail(MS_ERR_INVALID_ARG, "null argument");
+  if (channels < 1 || channels > 16) return fail(MS_ERR_INVALID_ARG, "channels = %d outside [1, 16]", channels);
+  if (width < 1 || width > 16384 || height < 1 || height > 16384)
+    return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", width, height);
+  if (!std::isfinite(weight)) return fail(MS_ERR_INVALID_ARG, "non-finite loss weight");
+  if (accumulate != 0 && accumulate != 1) return fail(MS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  hipStream_t st = (hipStream_t)stream;
+  SsimArgs a;
+  a.pred = pred;
+  a.target = target;
+  a.grad = grad;
+  a.loss = loss;
+  a.C = channels;
+  a.W = width;
+  a.H = height;
+  a.accumulate = accumulate;
+  a.weight = weight;
+  a.dS = (float)(-(double)weight / ((double)channels * (double)width * (double)height));
+  // Gaussian window, standard deviation 1.5 px, normalised in binary64
+  double wsum = 0.0, w[11];
+  for (int k = 0; k < 11; k++) {
+    const double d = k - 5;
+    w[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    wsum += w[k];
+  }
+  for (int k = 0; k < 11; k++) a.w[k] = (float)(w[k] / wsum);
+  hipError_t e = hipSuccess;
+  if (loss && !accumulate) e = launch_zero_scalar(loss, st);
+  if (e == hipSuccess) e = launch_ssim_grad(a, st);
+  if (e != hipSuccess) return hip_fail(e, "ssim loss");
+  return MS_OK;
+}
+
 int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state, float lr, float beta1, float beta2,
                           float eps, void* stream) {
   if (!viewmat || !twist_grad || !state) return fail(MS_ERR_INVALID_ARG, "null argument");

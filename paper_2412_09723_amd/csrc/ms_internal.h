@@ -199,6 +199,20 @@ hipError_t launch_fill_u32(uint32_t* dst, uint32_t value, int64_t count, hipStre
 hipError_t launch_l1_grad(const float* const pred[3], const float* const target[3], float* const grad[3], int64_t P,
                           const float scale[3], float* loss, hipStream_t st);
 hipError_t launch_zero_scalar(float* p, hipStream_t st);
+// SSIM term of the mapping loss over `C` planes of W x H (the kernel in
+// ssim.hip): grad = (accumulate ? grad : 0) + d/dpred [weight (1 - mean S)],
+// and *loss += weight (1 - mean S) when loss is not null. w: the 11 window
+// weights; dS = -weight / (C W H).
+struct SsimArgs {
+  const float* pred;
+  const float* target;
+  float* grad;
+  float* loss;
+  int C, W, H, accumulate;
+  float weight, dS;
+  float w[11];
+};
+hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st);
 hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,
                             hipStream_t st);
 

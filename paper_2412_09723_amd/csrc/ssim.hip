@@ -1,0 +1,184 @@
+// SSIM term of the mapping objective (Eq. 7), with the SSIM of the
+// evaluation-metrics appendix: S = (2 mx my + C1)(2 sxy + C2) /
+// ((mx^2 + my^2 + C1)(sx^2 + sy^2 + C2)) from local statistics under an
+// 11x11 Gaussian window (std 1.5 px, weights summing to 1), zero outside the
+// image. The loss is weight * (1 - mean S) over all channels and pixels and
+// its gradient with respect to the rendered image x is
+//   dL/dx(p) = sum_q w(q - p) (a(q) + 2 x(p) b(q) + y(p) c(q)),
+// a = dS/dmx, b = dS/dE[x^2] = -S / B2, c = dS/dE[xy] = 2 S / A2, each times
+// dL/dS = -weight / (channels * pixels).
+//
+// One workgroup per 32x32 output tile and channel, everything in LDS:
+//   0. x and y on the 52x52 region the tile's gradient depends on;
+//   1. row sums (11 taps) of x, y, x^2, y^2, xy on 52 rows x 42 columns;
+//   2. column sums: the five statistics on the 42x42 region whose windows
+//      reach the tile, then S and a, b, c there (zero outside the image);
+//   3. row sums of a, b, c on 42 rows x 32 columns;
+//   4. column sums on the 32x32 tile and the gradient.
+// The tile's own pixels add their S to the loss (one atomic per workgroup).
+#include "ms_internal.h"
+
+namespace ms {
+namespace {
+
+constexpr int kSsimTile = 32;                         // output tile edge
+constexpr int kSsimRad = 5;                           // window radius
+constexpr int kSsimTaps = 2 * kSsimRad + 1;
+constexpr int kSsimStat = kSsimTile + 2 * kSsimRad;   // 42: statistics region edge
+constexpr int kSsimIn = kSsimTile + 4 * kSsimRad;     // 52: input region edge
+constexpr int kSsimThreads = 256;
+constexpr float kC1 = 0.01f * 0.01f;
+constexpr float kC2 = 0.03f * 0.03f;
+
+// region 1: x, y (2 x 52 x 52), later a, b, c (3 x 42 x 42)
+constexpr int kR1 = 2 * kSsimIn * kSsimIn;
+// region 2: five row-sum planes (5 x 52 x 42), later three (3 x 42 x 32)
+constexpr int kR2 = 5 * kSsimIn * kSsimStat;
+static_assert(3 * kSsimStat * kSsimStat <= kR1, "a, b, c fit region 1");
+static_assert(3 * kSsimStat * kSsimTile <= kR2, "their row sums fit region 2");
+
+__global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
+  __shared__ float r1[kR1];
+  __shared__ float r2[kR2];
+  __shared__ float red[kSsimThreads / 64];
+  const int t = threadIdx.x;
+  const int W = A.W, H = A.H;
+  const int64_t P = (int64_t)W * H;
+  const int X0 = (int)blockIdx.x * kSsimTile, Y0 = (int)blockIdx.y * kSsimTile;
+  const float* __restrict__ x = A.pred + (int64_t)blockIdx.z * P;
+  const float* __restrict__ y = A.target + (int64_t)blockIdx.z * P;
+  float* __restrict__ grad = A.grad + (int64_t)blockIdx.z * P;
+  float g[kSsimTaps];
+#pragma unroll
+  for (int k = 0; k < kSsimTaps; k++) g[k] = A.w[k];
+
+  // 0. input region, origin (X0 - 2R, Y0 - 2R)
+  float* xs = r1;
+  float* ys = r1 + kSsimIn * kSsimIn;
+  for (int i = t; i < kSsimIn * kSsimIn; i += kSsimThreads) {
+    const int r = i / kSsimIn, c = i - r * kSsimIn;
+    const int gx = X0 - 2 * kSsimRad + c, gy = Y0 - 2 * kSsimRad + r;
+    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const int64_t o = (int64_t)gy * W + gx;
+    xs[i] = in ? x[o] : 0.f;
+    ys[i] = in ? y[o] : 0.f;
+  }
+  __syncthreads();
+  // 1. row sums: plane q at (row r, column c) sums input columns c .. c + 2R
+  constexpr int kP1 = kSsimIn * kSsimStat;
+  for (int i = t; i < kP1; i += kSsimThreads) {
+    const int r = i / kSsimStat, c = i - r * kSsimStat;
+    const float* xr = xs + r * kSsimIn + c;
+    const float* yr = ys + r * kSsimIn + c;
+    float sx = 0.f, sy = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSsimTaps; k++) {
+      const float xv = xr[k], yv = yr[k];
+      sx = __builtin_fmaf(g[k], xv, sx);
+      sy = __builtin_fmaf(g[k], yv, sy);
+      sxx = __builtin_fmaf(g[k], xv * xv, sxx);
+      syy = __builtin_fmaf(g[k], yv * yv, syy);
+      sxy = __builtin_fmaf(g[k], xv * yv, sxy);
+    }
+    r2[i] = sx;
+    r2[kP1 + i] = sy;
+    r2[2 * kP1 + i] = sxx;
+    r2[3 * kP1 + i] = syy;
+    r2[4 * kP1 + i] = sxy;
+  }
+  __syncthreads();
+  // 2. statistics on the 42x42 region, origin (X0 - R, Y0 - R); S and a, b, c
+  constexpr int kP2 = kSsimStat * kSsimStat;
+  float* pa = r1;
+  float* pb = r1 + kP2;
+  float* pc = r1 + 2 * kP2;
+  float ssum = 0.f;
+  for (int i = t; i < kP2; i += kSsimThreads) {
+    const int r = i / kSsimStat, c = i - r * kSsimStat;
+    const int gx = X0 - kSsimRad + c, gy = Y0 - kSsimRad + r;
+    float st[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+      const float* col = r2 + q * kP1 + r * kSsimStat + c;
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < kSsimTaps; k++) s = __builtin_fmaf(g[k], col[k * kSsimStat], s);
+      st[q] = s;
+    }
+    float va = 0.f, vb = 0.f, vc = 0.f;
+    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+      const float mx = st[0], my = st[1];
+      const float a1 = 2.f * mx * my + kC1;
+      const float a2 = 2.f * (st[4] - mx * my) + kC2;
+      const float b1 = mx * mx + my * my + kC1;
+      const float b2 = (st[2] - mx * mx) + (st[3] - my * my) + kC2;
+      const float s = (a1 * a2) / (b1 * b2);
+      const float ds = A.dS * s;
+      va = ds * (2.f * my / a1 - 2.f * my / a2 - 2.f * mx / b1 + 2.f * mx / b2);
+      vb = -ds / b2;
+      vc = 2.f * ds / a2;
+      if (r >= kSsimRad && r < kSsimRad + kSsimTile && c >= kSsimRad && c < kSsimRad + kSsimTile) ssum += s;
+    }
+    pa[i] = va;
+    pb[i] = vb;
+    pc[i] = vc;
+  }
+  __syncthreads();
+  // 3. row sums of a, b, c: (row r of the statistics region, tile column c)
+  constexpr int kP3 = kSsimStat * kSsimTile;
+  for (int i = t; i < kP3; i += kSsimThreads) {
+    const int r = i / kSsimTile, c = i - r * kSsimTile;
+    const int o = r * kSsimStat + c;
+    float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSsimTaps; k++) {
+      sa = __builtin_fmaf(g[k], pa[o + k], sa);
+      sb = __builtin_fmaf(g[k], pb[o + k], sb);
+      sc = __builtin_fmaf(g[k], pc[o + k], sc);
+    }
+    r2[i] = sa;
+    r2[kP3 + i] = sb;
+    r2[2 * kP3 + i] = sc;
+  }
+  __syncthreads();
+  // 4. column sums on the tile and the gradient
+  for (int i = t; i < kSsimTile * kSsimTile; i += kSsimThreads) {
+    const int r = i / kSsimTile, c = i - r * kSsimTile;
+    const int gx = X0 + c, gy = Y0 + r;
+    if (gx >= W || gy >= H) continue;
+    float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSsimTaps; k++) {
+      const int o = (r + k) * kSsimTile + c;
+      sa = __builtin_fmaf(g[k], r2[o], sa);
+      sb = __builtin_fmaf(g[k], r2[kP3 + o], sb);
+      sc = __builtin_fmaf(g[k], r2[2 * kP3 + o], sc);
+    }
+    const int64_t o = (int64_t)gy * W + gx;
+    const float v = sa + 2.f * x[o] * sb + y[o] * sc;
+    grad[o] = A.accumulate ? grad[o] + v : v;
+  }
+  if (!A.loss) return;
+  for (int off = 32; off > 0; off >>= 1) ssum += __shfl_xor(ssum, off, 64);
+  if ((t & 63) == 0) red[t >> 6] = ssum;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.f;
+    for (int w = 0; w < kSsimThreads / 64; w++) s += red[w];
+    // weight * (1 - mean S): the constant once, from the first workgroup
+    const bool first = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
+    unsafeAtomicAdd(A.loss, A.dS * s + (first ? A.weight : 0.f));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st) {
+  if (a.W <= 0 || a.H <= 0 || a.C <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.W + kSsimTile - 1) / kSsimTile), (unsigned)((a.H + kSsimTile - 1) / kSsimTile),
+                  (unsigned)a.C);
+  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSsimThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace ms

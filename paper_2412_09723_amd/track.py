@@ -64,3 +64,33 @@ class Tracker:
     def step(self, iters: int = 10):
         for _ in range(iters):
             self.iteration()
+
+
+def ssim_loss_grad(pred: torch.Tensor, target: torch.Tensor, weight: float = 0.2, grad: torch.Tensor | None = None,
+                   accumulate: bool = False, loss: torch.Tensor | None = None):
+    """The SSIM term weight * (1 - mean SSIM(pred, target)) of the mapping
+    objective (Eq. 7) and its gradient with respect to pred, through
+    ms_ssim_loss_grad. pred, target: contiguous float32 [C, H, W] on the
+    device. grad (same shape) is written, or added to with accumulate; loss
+    (a one-element device tensor) receives the value, or is added to with
+    accumulate. Returns grad."""
+    if pred.dim() != 3 or pred.shape != target.shape:
+        raise ValueError(f"pred {tuple(pred.shape)} and target {tuple(target.shape)} must both be [C, H, W]")
+    for name, t in (("pred", pred), ("target", target)):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if grad is None:
+        if accumulate:
+            raise ValueError("accumulate needs a grad tensor")
+        grad = torch.empty_like(pred)
+    elif grad.shape != pred.shape or grad.dtype != torch.float32 or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float32 tensor shaped like pred")
+    if loss is not None and (loss.dtype != torch.float32 or loss.numel() < 1 or not loss.is_cuda):
+        raise ValueError("loss must be a float32 device tensor")
+    C, H, W = pred.shape
+    lib = _lib.load()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(pred.device).cuda_stream)
+    check(lib.ms_ssim_loss_grad(ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(target.data_ptr()), int(C), int(W),
+                                int(H), float(weight), ctypes.c_void_p(grad.data_ptr()), int(bool(accumulate)),
+                                ctypes.c_void_p(loss.data_ptr() if loss is not None else 0), stream))
+    return grad

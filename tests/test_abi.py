@@ -123,6 +123,20 @@ def test_read_stats_and_view_reject_bad_workspace(lib):
         == _lib.MS_ERR_INVALID_ARG
 
 
+def test_ssim_loss_rejects_bad_arguments(lib):
+    def call(pred=FAKE, target=FAKE, C=3, W=64, H=48, weight=0.2, grad=FAKE + 64, acc=0):
+        return lib.ms_ssim_loss_grad(ctypes.c_void_p(pred), ctypes.c_void_p(target), C, W, H, weight,
+                                     ctypes.c_void_p(grad), acc, None, None)
+    assert call(pred=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(grad=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(C=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(C=17) == _lib.MS_ERR_INVALID_ARG
+    assert call(W=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(H=16385) == _lib.MS_ERR_INVALID_ARG
+    assert call(weight=float("inf")) == _lib.MS_ERR_INVALID_ARG
+    assert call(acc=2) == _lib.MS_ERR_INVALID_ARG
+
+
 def test_product_path_has_no_oracle_dependency():
     """The package never imports the oracle (test infrastructure only)."""
     pkg = os.path.join(ROOT, "paper_2412_09723_amd")
