@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4-agent batched-vs-plain measurement")
     ap.add_argument("--batch-rounds", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the 8-agent serving measurement")
+    ap.add_argument("--no-ssim", action="store_true", help="skip the SSIM loss measurement")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
     ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
@@ -111,6 +112,49 @@ def cpu_baseline(scene, target_s: float):
                       f"({el:.1f} s, OpenMP over {cores} threads)",
             "counters": {"visible": int(fwd["counters"][0]), "evaluated": int(fwd["counters"][1]),
                          "accepted": int(fwd["counters"][2]), "composited": int(fwd["counters"][3])}}
+
+
+SSIM_FLOPS_PER_VALUE = 390   # separable window sums: 5 statistics x 2 x 11 FMAs + 3 partials x 2 x 11 FMAs, + ~40
+
+
+def ssim_bench(pred, target, calls: int = 50):
+    """The SSIM term of the mapping loss and its gradient (ms_ssim_loss_grad)
+    on a rendered RGB frame against the observed one, timed with HIP events
+    on the stream it is launched on."""
+    import torch
+    from paper_2412_09723_amd.track import ssim_loss_grad
+    grad = torch.empty_like(pred)
+    loss = torch.zeros(1, dtype=torch.float32, device=pred.device)
+    for _ in range(5):
+        ssim_loss_grad(pred, target, 0.2, grad=grad, loss=loss)
+    st = torch.cuda.current_stream(pred.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(calls):
+        ssim_loss_grad(pred, target, 0.2, grad=grad, loss=loss)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    C, H, W = pred.shape
+    values = C * H * W
+    return {"workload": f"SSIM term of the mapping loss (11x11 Gaussian window) and its gradient, {C}x{H}x{W} "
+                        "rendered frame against the observed frame",
+            "ms_per_call": round(ms, 4), "Mpix_s": round(H * W / ms / 1e3, 1),
+            "hbm_bytes_per_call": 12 * values, "hbm_TB_s": round(12 * values / ms / 1e9, 3),
+            "flops_per_value": SSIM_FLOPS_PER_VALUE,
+            "alu_TFLOP_s": round(SSIM_FLOPS_PER_VALUE * values / ms / 1e9, 2), "loss": float(loss.cpu()[0])}
+
+
+def ssim_cpu_baseline(pred, target):
+    """The binary64 SSIM oracle (unchanged) on the same frame, once."""
+    from oracle import ssim
+    x, y = pred.cpu().numpy(), target.cpu().numpy()
+    t0 = time.perf_counter()
+    ssim.ssim_loss_grad(x, y, 0.2)
+    el = time.perf_counter() - t0
+    return {"value": round(x.shape[1] * x.shape[2] / el / 1e6, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"one SSIM loss and gradient of the {x.shape[0]}x{x.shape[1]}x{x.shape[2]} frame ({el:.2f} s, numpy)"}
 
 
 COPY_BYTES = 512 << 20
@@ -350,6 +394,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
+    ssim_frames = None
+    if not args.no_ssim:
+        ssim_frames = (tracker.out[0].clone(), target[0].clone())
+        out["ssim_loss"] = ssim_bench(*ssim_frames)
     if not args.no_batch:
         del tracker, job, obs_job_state
         torch.cuda.empty_cache()
@@ -361,6 +409,8 @@ def main():
                                      args.serve_small_gb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        if ssim_frames is not None:
+            out["cpu_baseline"]["ssim_loss"] = ssim_cpu_baseline(*ssim_frames)
     print(json.dumps(out), flush=True)
 
 

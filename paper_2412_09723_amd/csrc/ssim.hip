@@ -8,7 +8,8 @@
 // a = dS/dmx, b = dS/dE[x^2] = -S / B2, c = dS/dE[xy] = 2 S / A2, each times
 // dL/dS = -weight / (channels * pixels).
 //
-// One workgroup per 32x32 output tile and channel, everything in LDS:
+// One workgroup of 512 threads per 32x32 output tile and channel, everything
+// in LDS (65 KB: two workgroups per CU):
 //   0. x and y on the 52x52 region the tile's gradient depends on;
 //   1. row sums (11 taps) of x, y, x^2, y^2, xy on 52 rows x 42 columns;
 //   2. column sums: the five statistics on the 42x42 region whose windows
@@ -16,6 +17,7 @@
 //   3. row sums of a, b, c on 42 rows x 32 columns;
 //   4. column sums on the 32x32 tile and the gradient.
 // The tile's own pixels add their S to the loss (one atomic per workgroup).
+// Every pass is separable and register-blocked along its direction.
 #include "ms_internal.h"
 
 namespace ms {
@@ -26,7 +28,9 @@ constexpr int kSsimRad = 5;                           // window radius
 constexpr int kSsimTaps = 2 * kSsimRad + 1;
 constexpr int kSsimStat = kSsimTile + 2 * kSsimRad;   // 42: statistics region edge
 constexpr int kSsimIn = kSsimTile + 4 * kSsimRad;     // 52: input region edge
-constexpr int kSsimThreads = 256;
+constexpr int kSsimThreads = 512;
+constexpr int kRunStat = 7;    // statistics pass: 42 columns x 6 runs, one per thread
+constexpr int kRunGrad = 4;    // the two passes over a, b, c: 42 x 8 and 32 x 8 runs
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -64,27 +68,41 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
     ys[i] = in ? y[o] : 0.f;
   }
   __syncthreads();
+  // Each thread produces a run of kRun consecutive outputs of a pass from the
+  // kRun + 2R inputs it loads once, instead of 2R + 1 loads per output.
   // 1. row sums: plane q at (row r, column c) sums input columns c .. c + 2R
   constexpr int kP1 = kSsimIn * kSsimStat;
-  for (int i = t; i < kP1; i += kSsimThreads) {
-    const int r = i / kSsimStat, c = i - r * kSsimStat;
-    const float* xr = xs + r * kSsimIn + c;
-    const float* yr = ys + r * kSsimIn + c;
-    float sx = 0.f, sy = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+  {
+    constexpr int kRun = 6, kGroups = kSsimStat / kRun, kLen = kRun + 2 * kSsimRad;
+    static_assert(kGroups * kRun == kSsimStat, "row-sum runs tile the statistics columns");
+    for (int it = t; it < kSsimIn * kGroups; it += kSsimThreads) {
+      const int r = it / kGroups, c0 = (it - r * kGroups) * kRun;
+      float xv[kLen], yv[kLen];
 #pragma unroll
-    for (int k = 0; k < kSsimTaps; k++) {
-      const float xv = xr[k], yv = yr[k];
-      sx = __builtin_fmaf(g[k], xv, sx);
-      sy = __builtin_fmaf(g[k], yv, sy);
-      sxx = __builtin_fmaf(g[k], xv * xv, sxx);
-      syy = __builtin_fmaf(g[k], yv * yv, syy);
-      sxy = __builtin_fmaf(g[k], xv * yv, sxy);
+      for (int j = 0; j < kLen; j++) {
+        xv[j] = xs[r * kSsimIn + c0 + j];
+        yv[j] = ys[r * kSsimIn + c0 + j];
+      }
+#pragma unroll
+      for (int o = 0; o < kRun; o++) {
+        float sx = 0.f, sy = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+          const float xk = xv[o + k], yk = yv[o + k];
+          sx = __builtin_fmaf(g[k], xk, sx);
+          sy = __builtin_fmaf(g[k], yk, sy);
+          sxx = __builtin_fmaf(g[k], xk * xk, sxx);
+          syy = __builtin_fmaf(g[k], yk * yk, syy);
+          sxy = __builtin_fmaf(g[k], xk * yk, sxy);
+        }
+        const int i = r * kSsimStat + c0 + o;
+        r2[i] = sx;
+        r2[kP1 + i] = sy;
+        r2[2 * kP1 + i] = sxx;
+        r2[3 * kP1 + i] = syy;
+        r2[4 * kP1 + i] = sxy;
+      }
     }
-    r2[i] = sx;
-    r2[kP1 + i] = sy;
-    r2[2 * kP1 + i] = sxx;
-    r2[3 * kP1 + i] = syy;
-    r2[4 * kP1 + i] = sxy;
   }
   __syncthreads();
   // 2. statistics on the 42x42 region, origin (X0 - R, Y0 - R); S and a, b, c
@@ -93,70 +111,116 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
   float* pb = r1 + kP2;
   float* pc = r1 + 2 * kP2;
   float ssum = 0.f;
-  for (int i = t; i < kP2; i += kSsimThreads) {
-    const int r = i / kSsimStat, c = i - r * kSsimStat;
-    const int gx = X0 - kSsimRad + c, gy = Y0 - kSsimRad + r;
-    float st[5];
+  {
+    constexpr int kRun = kRunStat, kGroups = kSsimStat / kRun, kLen = kRun + 2 * kSsimRad;
+    for (int it = t; it < kSsimStat * kGroups; it += kSsimThreads) {
+      const int c = it % kSsimStat, r0 = (it / kSsimStat) * kRun;   // neighbouring threads: neighbouring columns
+      float st[5][kRun];
 #pragma unroll
-    for (int q = 0; q < 5; q++) {
-      const float* col = r2 + q * kP1 + r * kSsimStat + c;
-      float s = 0.f;
+      for (int q = 0; q < 5; q++) {
+        float v[kLen];
 #pragma unroll
-      for (int k = 0; k < kSsimTaps; k++) s = __builtin_fmaf(g[k], col[k * kSsimStat], s);
-      st[q] = s;
+        for (int j = 0; j < kLen; j++) v[j] = r2[q * kP1 + (r0 + j) * kSsimStat + c];
+#pragma unroll
+        for (int o = 0; o < kRun; o++) {
+          float s = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSsimTaps; k++) s = __builtin_fmaf(g[k], v[o + k], s);
+          st[q][o] = s;
+        }
+      }
+      const int gx = X0 - kSsimRad + c;
+      const bool own_col = c >= kSsimRad && c < kSsimRad + kSsimTile;
+#pragma unroll
+      for (int o = 0; o < kRun; o++) {
+        const int r = r0 + o, gy = Y0 - kSsimRad + r;
+        float va = 0.f, vb = 0.f, vc = 0.f;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+          const float mx = st[0][o], my = st[1][o];
+          const float a1 = 2.f * mx * my + kC1;
+          const float a2 = 2.f * (st[4][o] - mx * my) + kC2;
+          const float b1 = mx * mx + my * my + kC1;
+          const float b2 = (st[2][o] - mx * mx) + (st[3][o] - my * my) + kC2;
+          // hardware reciprocals (about 1 ulp): the partials need no
+          // correctly rounded quotients
+          const float ra1 = __builtin_amdgcn_rcpf(a1), ra2 = __builtin_amdgcn_rcpf(a2);
+          const float rb1 = __builtin_amdgcn_rcpf(b1), rb2 = __builtin_amdgcn_rcpf(b2);
+          const float sv = (a1 * a2) * (rb1 * rb2);
+          const float ds = A.dS * sv;
+          va = ds * (2.f * my * (ra1 - ra2) + 2.f * mx * (rb2 - rb1));
+          vb = -ds * rb2;
+          vc = 2.f * ds * ra2;
+          if (own_col && r >= kSsimRad && r < kSsimRad + kSsimTile) ssum += sv;
+        }
+        const int i = r * kSsimStat + c;
+        pa[i] = va;
+        pb[i] = vb;
+        pc[i] = vc;
+      }
     }
-    float va = 0.f, vb = 0.f, vc = 0.f;
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      const float mx = st[0], my = st[1];
-      const float a1 = 2.f * mx * my + kC1;
-      const float a2 = 2.f * (st[4] - mx * my) + kC2;
-      const float b1 = mx * mx + my * my + kC1;
-      const float b2 = (st[2] - mx * mx) + (st[3] - my * my) + kC2;
-      const float s = (a1 * a2) / (b1 * b2);
-      const float ds = A.dS * s;
-      va = ds * (2.f * my / a1 - 2.f * my / a2 - 2.f * mx / b1 + 2.f * mx / b2);
-      vb = -ds / b2;
-      vc = 2.f * ds / a2;
-      if (r >= kSsimRad && r < kSsimRad + kSsimTile && c >= kSsimRad && c < kSsimRad + kSsimTile) ssum += s;
-    }
-    pa[i] = va;
-    pb[i] = vb;
-    pc[i] = vc;
   }
   __syncthreads();
   // 3. row sums of a, b, c: (row r of the statistics region, tile column c)
   constexpr int kP3 = kSsimStat * kSsimTile;
-  for (int i = t; i < kP3; i += kSsimThreads) {
-    const int r = i / kSsimTile, c = i - r * kSsimTile;
-    const int o = r * kSsimStat + c;
-    float sa = 0.f, sb = 0.f, sc = 0.f;
+  {
+    constexpr int kRun = kRunGrad, kGroups = kSsimTile / kRun, kLen = kRun + 2 * kSsimRad;
+    for (int it = t; it < kSsimStat * kGroups; it += kSsimThreads) {
+      const int r = it / kGroups, c0 = (it - r * kGroups) * kRun;
+      float va[kLen], vb[kLen], vc[kLen];
 #pragma unroll
-    for (int k = 0; k < kSsimTaps; k++) {
-      sa = __builtin_fmaf(g[k], pa[o + k], sa);
-      sb = __builtin_fmaf(g[k], pb[o + k], sb);
-      sc = __builtin_fmaf(g[k], pc[o + k], sc);
+      for (int j = 0; j < kLen; j++) {
+        const int i = r * kSsimStat + c0 + j;
+        va[j] = pa[i];
+        vb[j] = pb[i];
+        vc[j] = pc[i];
+      }
+#pragma unroll
+      for (int o = 0; o < kRun; o++) {
+        float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+          sa = __builtin_fmaf(g[k], va[o + k], sa);
+          sb = __builtin_fmaf(g[k], vb[o + k], sb);
+          sc = __builtin_fmaf(g[k], vc[o + k], sc);
+        }
+        const int i = r * kSsimTile + c0 + o;
+        r2[i] = sa;
+        r2[kP3 + i] = sb;
+        r2[2 * kP3 + i] = sc;
+      }
     }
-    r2[i] = sa;
-    r2[kP3 + i] = sb;
-    r2[2 * kP3 + i] = sc;
   }
   __syncthreads();
   // 4. column sums on the tile and the gradient
-  for (int i = t; i < kSsimTile * kSsimTile; i += kSsimThreads) {
-    const int r = i / kSsimTile, c = i - r * kSsimTile;
-    const int gx = X0 + c, gy = Y0 + r;
-    if (gx >= W || gy >= H) continue;
-    float sa = 0.f, sb = 0.f, sc = 0.f;
+  {
+    constexpr int kRun = kRunGrad, kGroups = kSsimTile / kRun, kLen = kRun + 2 * kSsimRad;
+    for (int it = t; it < kSsimTile * kGroups; it += kSsimThreads) {
+      const int c = it % kSsimTile, r0 = (it / kSsimTile) * kRun;
+      const int gx = X0 + c;
+      if (gx >= W) continue;
+      float sum[3][kRun];
 #pragma unroll
-    for (int k = 0; k < kSsimTaps; k++) {
-      const int o = (r + k) * kSsimTile + c;
-      sa = __builtin_fmaf(g[k], r2[o], sa);
-      sb = __builtin_fmaf(g[k], r2[kP3 + o], sb);
-      sc = __builtin_fmaf(g[k], r2[2 * kP3 + o], sc);
+      for (int q = 0; q < 3; q++) {
+        float v[kLen];
+#pragma unroll
+        for (int j = 0; j < kLen; j++) v[j] = r2[q * kP3 + (r0 + j) * kSsimTile + c];
+#pragma unroll
+        for (int o = 0; o < kRun; o++) {
+          float s = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSsimTaps; k++) s = __builtin_fmaf(g[k], v[o + k], s);
+          sum[q][o] = s;
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < kRun; o++) {
+        const int gy = Y0 + r0 + o;
+        if (gy >= H) break;
+        const int64_t q = (int64_t)gy * W + gx;
+        const float v = sum[0][o] + 2.f * x[q] * sum[1][o] + y[q] * sum[2][o];
+        grad[q] = A.accumulate ? grad[q] + v : v;
+      }
     }
-    const int64_t o = (int64_t)gy * W + gx;
-    const float v = sa + 2.f * x[o] * sb + y[o] * sc;
-    grad[o] = A.accumulate ? grad[o] + v : v;
   }
   if (!A.loss) return;
   for (int off = 32; off > 0; off >>= 1) ssum += __shfl_xor(ssum, off, 64);
