@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--batch-rounds", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the 8-agent serving measurement")
     ap.add_argument("--no-ssim", action="store_true", help="skip the SSIM loss measurement")
+    ap.add_argument("--no-views", action="store_true", help="skip the one-map multi-view mapping measurement")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
     ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
@@ -112,6 +113,61 @@ def cpu_baseline(scene, target_s: float):
                       f"({el:.1f} s, OpenMP over {cores} threads)",
             "counters": {"visible": int(fwd["counters"][0]), "evaluated": int(fwd["counters"][1]),
                          "accepted": int(fwd["counters"][2]), "composited": int(fwd["counters"][3])}}
+
+
+def views_bench(rounds: int = 10):
+    """A mapping step over keyframes of one map: eight 640x480 views of a
+    500k-Gaussian map, forward + backward with the map gradient summed over
+    the views. Batched: one launch sequence per pass, the views' gradients
+    added into one set of arrays. Plain: eight render calls one after
+    another, each into its own arrays, then summed."""
+    import numpy as np
+    import torch
+    from paper_2412_09723_amd import raster, scenes
+    sc, vms = scenes.keyframe_ring()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    keys = ("means", "scales", "quats", "opacity", "colors")
+    m = {k: t(getattr(sc, k)) for k in keys}
+    vmt = [t(vm) for vm in vms]
+    ups = [[t(u) for u in scenes.upstream_grads(sc.intr, scenes.rng_for(2, v, salt=2), 1.0, 0.5)]
+           for v in range(len(vms))]
+    opts = raster.RenderOptions()
+    batch = raster.BatchJob([m] * len(vms), vmt, [sc.intr] * len(vms), opts)
+    shared = {k: torch.empty_like(m[k]) for k in keys}
+    jobs = [raster.Job(m, vm, sc.intr, opts) for vm in vmt]
+    total = {k: torch.empty_like(m[k]) for k in keys}
+
+    def batched():
+        batch.forward()
+        batch.backward(ups, pose_grads=False, shared_map_grads=shared)
+
+    def plain():
+        for k in keys:
+            total[k].zero_()
+        for j, u in zip(jobs, ups):
+            j.forward()
+            g = j.backward(*u, pose_grads=False)
+            for k in keys:
+                total[k] += g[k]
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / rounds * 1e3
+
+    pb, pp = timed(batched), timed(plain)
+    px = sc.intr.width * sc.intr.height * len(vms)
+    return {"workload": f"{len(vms)} keyframes of one {sc.n // 1000}k-Gaussian map at {sc.intr.width}x{sc.intr.height}, "
+                        "forward + backward, map gradient summed over the views",
+            "rounds": rounds, "batched_ms": round(pb, 4), "plain_ms": round(pp, 4),
+            "batched_Mpix_s": round(px / pb / 1e3, 1), "plain_Mpix_s": round(px / pp / 1e3, 1),
+            "speedup": round(pp / pb, 3)}
 
 
 SSIM_FLOPS_PER_VALUE = 390   # separable window sums: 5 statistics x 2 x 11 FMAs + 3 partials x 2 x 11 FMAs, + ~40
@@ -402,6 +458,9 @@ def main():
         del tracker, job, obs_job_state
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(args.batch_rounds)
+    if not args.no_views:
+        torch.cuda.empty_cache()
+        out["mapping_views"] = views_bench()
     if not args.no_serve:
         torch.cuda.empty_cache()
         sweep = [float(x) for x in args.serve_sweep.split(",") if x]

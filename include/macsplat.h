@@ -128,6 +128,11 @@ typedef struct {
 #define MS_FLAG_SCALAR_FWD 4u       /* forward compositing reads each Gaussian's record with wave-uniform
                                        scalar loads instead of staging wave_batch records through LDS */
 #define MS_FLAG_SCALAR_BWD 8u       /* the same for backward compositing */
+#define MS_FLAG_ACCUMULATE_MAP_GRADS 32u /* backward (per job): add this job's map gradients into grads
+                                           instead of writing them; the caller zeroes the arrays first.
+                                           Jobs of one batch that share a map (several views of one map)
+                                           then sum into one set of arrays. Float atomics: the summation
+                                           order, and so the last bits, vary from run to run. */
 #define MS_FLAG_MFMA_BWD 16u        /* backward compositing with the per-Gaussian reduction over each 8x8
                                        sub-block done as a matrix-core product */
 

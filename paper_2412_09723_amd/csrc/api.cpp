@@ -382,7 +382,7 @@ void set_backward_job(JobDesc& J, const ms_images& grad_out, const ms_grads& g, 
   J.gc = g.colors;
   J.gview = g.viewmat;
   J.gtwist = g.twist;
-  J.flags = flags & (MS_FLAG_POSE_GRAD_ONLY | MS_FLAG_NO_POSE_GRAD);
+  J.flags = flags & (MS_FLAG_POSE_GRAD_ONLY | MS_FLAG_NO_POSE_GRAD | MS_FLAG_ACCUMULATE_MAP_GRADS);
 }
 
 constexpr uint32_t kPoseFlags = MS_FLAG_POSE_GRAD_ONLY | MS_FLAG_NO_POSE_GRAD;
@@ -413,6 +413,28 @@ int32_t batch_table(int32_t njobs, const ms_job* jobs, const ms_options* opts, i
       t.job[j].rgb = b.out.rgb;
       t.job[j].depth = b.out.depth;
       t.job[j].sil = b.out.silhouette;
+    }
+  }
+  if (backward) {
+    // map gradient arrays written by more than one job must be accumulated
+    // by all of them (plain writes of one job would race with the others)
+    for (int j = 0; j < njobs; j++) {
+      const JobDesc& A = t.job[j];
+      if ((A.flags & MS_FLAG_POSE_GRAD_ONLY) || A.n == 0) continue;
+      for (int k = j + 1; k < njobs; k++) {
+        const JobDesc& B = t.job[k];
+        if ((B.flags & MS_FLAG_POSE_GRAD_ONLY) || B.n == 0) continue;
+        const float* a[5] = {A.gm, A.gs, A.gq, A.go, A.gc};
+        const float* b[5] = {B.gm, B.gs, B.gq, B.go, B.gc};
+        bool shared = false;
+        for (int u = 0; u < 5; u++)
+          for (int v = 0; v < 5; v++) shared |= a[u] == b[v];
+        if (shared && !((A.flags & B.flags) & MS_FLAG_ACCUMULATE_MAP_GRADS))
+          return fail(MS_ERR_INVALID_ARG, "jobs %d and %d share a map gradient array without MS_FLAG_ACCUMULATE_MAP_GRADS",
+                      j, k);
+        if (shared && A.n != B.n)
+          return fail(MS_ERR_INVALID_ARG, "jobs %d and %d share map gradient arrays but not the map size", j, k);
+      }
     }
   }
   int64_t total = 0;

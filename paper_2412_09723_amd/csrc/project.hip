@@ -299,8 +299,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const float* viewmat = J.viewmat;
   const bool map_grads = !(J.flags & MS_FLAG_POSE_GRAD_ONLY);
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
+  const bool accumulate = (J.flags & MS_FLAG_ACCUMULATE_MAP_GRADS) != 0;   // several views of one map
   const bool overflow = counters[C_OVERFLOW] != 0;
-  if (map_grads) {
+  if (map_grads && !accumulate) {
 #pragma unroll
     for (int u = 0; u < kSub; u++) {
       const int64_t li = li0 + u * 256 + threadIdx.x;
@@ -462,7 +463,15 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       for (int k = 0; k < 4; k++) gq[k] = nanv;
       go = nanv;
     }
-    if (map_grads) {
+    if (map_grads && accumulate) {
+      for (int k = 0; k < 3; k++) {
+        unsafeAtomicAdd(J.gm + k * n + li, gm[k]);
+        unsafeAtomicAdd(J.gs + k * n + li, gs[k]);
+        unsafeAtomicAdd(J.gc + k * n + li, gc[k]);
+      }
+      for (int k = 0; k < 4; k++) unsafeAtomicAdd(J.gq + k * n + li, gq[k]);
+      unsafeAtomicAdd(J.go + li, go);
+    } else if (map_grads) {
       for (int k = 0; k < 3; k++) {
         J.gm[k * n + li] = gm[k];
         J.gs[k * n + li] = gs[k];

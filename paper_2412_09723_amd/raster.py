@@ -288,17 +288,30 @@ class BatchJob:
                 return self.forward(outs)
         return outs
 
-    def backward(self, upstream: list, map_grads=True, pose_grads=True, outs: list | None = None) -> list:
+    def backward(self, upstream: list, map_grads=True, pose_grads=True, outs: list | None = None,
+                 shared_map_grads: dict | None = None) -> list:
         """Backward of the last forward. upstream: [(g_rgb, g_depth, g_sil)] in
         job order; map_grads / pose_grads: a bool or one bool per job.
-        Returns one gradient dict per job, as Job.backward."""
+        Returns one gradient dict per job, as Job.backward. shared_map_grads:
+        for jobs that are views of one map, a dict of gradient tensors shaped
+        like that map; it is zeroed and every job with map gradients adds its
+        gradients into it (MS_FLAG_ACCUMULATE_MAP_GRADS), so it ends up with
+        their sum over the views."""
         k = len(self.maps)
         mg = [map_grads] * k if isinstance(map_grads, bool) else list(map_grads)
         pg = [pose_grads] * k if isinstance(pose_grads, bool) else list(pose_grads)
+        if shared_map_grads is not None:
+            for key in ("means", "scales", "quats", "opacity", "colors"):
+                for j in range(k):
+                    if mg[j] and self.maps[j][key].shape != shared_map_grads[key].shape:
+                        raise ValueError(f"job {j}: map {key} shape differs from the shared gradient")
+                shared_map_grads[key].zero_()
         res = []
         for j in range(k):
             g = outs[j] if outs is not None else {}
-            if mg[j] and outs is None:
+            if mg[j] and shared_map_grads is not None:
+                g.update({key: shared_map_grads[key] for key in ("means", "scales", "quats", "opacity", "colors")})
+            elif mg[j] and outs is None:
                 for key in ("means", "scales", "quats", "opacity", "colors"):
                     g[key] = torch.empty_like(self.maps[j][key])
             if pg[j] and outs is None:
@@ -309,7 +322,8 @@ class BatchJob:
             self.c_jobs[j].grads = MsGrads(*[g[key].data_ptr() if key in g else 0 for key in
                                              ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist")])
             self.c_jobs[j].flags = (0 if mg[j] else _lib.MS_FLAG_POSE_GRAD_ONLY) | \
-                (0 if pg[j] else _lib.MS_FLAG_NO_POSE_GRAD)
+                (0 if pg[j] else _lib.MS_FLAG_NO_POSE_GRAD) | \
+                (_lib.MS_FLAG_ACCUMULATE_MAP_GRADS if mg[j] and shared_map_grads is not None else 0)
             res.append(g)
         lib = _lib.load()
         check(lib.ms_backward_batch(k, self.c_jobs, ref(opts_struct(self.opts)), _ptr(self.ws), self.ws_bytes,

@@ -123,6 +123,30 @@ def test_read_stats_and_view_reject_bad_workspace(lib):
         == _lib.MS_ERR_INVALID_ARG
 
 
+def test_shared_map_gradients_need_the_accumulate_flag(lib):
+    """Two views of one map writing one set of map gradient arrays race
+    unless both accumulate; the batch is rejected before any launch."""
+    from paper_2412_09723_amd._lib import MsGrads, MsJob
+    m = MsMap(4096, FAKE, FAKE, FAKE, FAKE, FAKE)
+    shared = MsGrads(FAKE + 0x10000, FAKE + 0x20000, FAKE + 0x30000, FAKE + 0x40000, FAKE + 0x50000, 0, 0)
+    other = MsGrads(FAKE + 0x60000, FAKE + 0x70000, FAKE + 0x80000, FAKE + 0x90000, FAKE + 0xA0000, 0, 0)
+    img = MsImages(FAKE, FAKE, FAKE)
+
+    def job(grads, flags):
+        return MsJob(m, FAKE, INTR, img, img, grads, flags | _lib.MS_FLAG_NO_POSE_GRAD)
+
+    def batch(*js):
+        arr = (MsJob * len(js))(*js)
+        # the workspace size is far too small: a batch that passes validation fails there
+        return lib.ms_backward_batch(len(js), arr, ref(OPTS), ctypes.c_void_p(FAKE), 256, 1 << 20, None)
+
+    acc = _lib.MS_FLAG_ACCUMULATE_MAP_GRADS
+    assert batch(job(shared, 0), job(shared, 0)) == _lib.MS_ERR_INVALID_ARG
+    assert batch(job(shared, acc), job(shared, 0)) == _lib.MS_ERR_INVALID_ARG
+    assert batch(job(shared, acc), job(shared, acc)) == _lib.MS_ERR_WORKSPACE
+    assert batch(job(shared, 0), job(other, 0)) == _lib.MS_ERR_WORKSPACE
+
+
 def test_ssim_loss_rejects_bad_arguments(lib):
     def call(pred=FAKE, target=FAKE, C=3, W=64, H=48, weight=0.2, grad=FAKE + 64, acc=0):
         return lib.ms_ssim_loss_grad(ctypes.c_void_p(pred), ctypes.c_void_p(target), C, W, H, weight,

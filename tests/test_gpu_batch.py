@@ -159,3 +159,44 @@ def test_autotuner_picks_a_measured_candidate():
     assert res.options.bin_tile >= res.options.tile
     again = tuner.tune_batch([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], ups)
     assert again.options == res.options         # cached
+
+
+def test_views_of_one_map_accumulate_into_one_gradient():
+    """Eight keyframes of one 500k-Gaussian map at 640x480 in one batch, the
+    map gradients summed into one set of arrays (MS_FLAG_ACCUMULATE_MAP_GRADS):
+    against the sum of the views rendered alone and against the oracle's sum
+    over the views; pose gradients per view against the lone ones."""
+    _log("keyframe_ring batch with shared map gradients: 8 views 640x480, 500k Gaussians")
+    sc, vms = scenes.keyframe_ring()
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    m = {k: t(getattr(sc, k)) for k in KEYS}
+    vmt = [t(vm) for vm in vms]
+    opts = raster.RenderOptions(check=True)
+    batch = raster.BatchJob([m] * len(vms), vmt, [sc.intr] * len(vms), opts)
+    batch.forward()
+    ups = [scenes.upstream_grads(sc.intr, scenes.rng_for(2, v, salt=2), 1.0, 0.5) for v in range(len(vms))]
+    shared = {k: torch.full_like(m[k], 7.0) for k in KEYS}        # stale values: the call zeroes them
+    gbs = batch.backward([_dev(u) for u in ups], shared_map_grads=shared)
+    torch.cuda.synchronize()
+    alone_sum = {k: torch.zeros_like(m[k]) for k in KEYS}
+    for v, vm in enumerate(vmt):
+        job = raster.Job(m, vm, sc.intr, opts)
+        job.forward()
+        ga = job.backward(*_dev(ups[v]))
+        torch.cuda.synchronize()
+        for k in KEYS:
+            alone_sum[k] += ga[k]
+        check_reordered_grads(gbs[v], ga, ("viewmat", "twist"))
+        assert all(gbs[v][k] is shared[k] for k in KEYS)
+        del job, ga
+    check_reordered_grads(shared, alone_sum, KEYS)
+    ref = {k: 0.0 for k in KEYS}
+    gflags = np.zeros(sc.n, np.uint8)
+    for vm, up in zip(vms, ups):
+        rb = oracle.backward(scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacity, sc.colors, vm, sc.intr), *up)
+        for k in KEYS:
+            ref[k] = ref[k] + rb[k]
+        gflags |= rb["gflags"]
+    ref["gflags"] = gflags
+    _log(f"  shared map gradients vs oracle: {check_grads(shared, ref, pose=False)}")
