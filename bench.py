@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the 8-agent serving measurement")
     ap.add_argument("--no-ssim", action="store_true", help="skip the SSIM loss measurement")
     ap.add_argument("--no-views", action="store_true", help="skip the one-map multi-view mapping measurement")
+    ap.add_argument("--no-prune", action="store_true", help="skip the map-pruning measurement")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
     ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
@@ -168,6 +169,45 @@ def views_bench(rounds: int = 10):
             "rounds": rounds, "batched_ms": round(pb, 4), "plain_ms": round(pp, 4),
             "batched_Mpix_s": round(px / pb / 1e3, 1), "plain_Mpix_s": round(px / pp / 1e3, 1),
             "speedup": round(pp / pb, 3)}
+
+
+def prune_bench(m: dict, calls: int = 20):
+    """Map pruning (ms_prune, the paper's thresholds) on the benchmark map,
+    timed with HIP events on the stream it is launched on."""
+    import ctypes
+    import torch
+    from paper_2412_09723_amd import _lib
+    from paper_2412_09723_amd._lib import MsMap, check, ref
+    keys = ("means", "scales", "quats", "opacity", "colors")
+    rows = {"means": 3, "scales": 3, "quats": 4, "opacity": 1, "colors": 3}
+    n = m["means"].shape[1]
+    dev = m["means"].device
+    bufs = {k: torch.empty(rows[k] * n, dtype=torch.float32, device=dev) for k in keys}
+    kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = _lib.load()
+    ws = torch.empty(int(lib.ms_prune_workspace_bytes(n)) + 256, dtype=torch.uint8, device=dev)
+    src = MsMap(n, *[m[k].data_ptr() for k in keys])
+    dst = MsMap(n, *[bufs[k].data_ptr() for k in keys])
+    st = torch.cuda.current_stream(dev)
+
+    def call():
+        check(lib.ms_prune(ref(src), 0.005, 0.25, 10.0, ref(dst), ctypes.c_void_p(kept.data_ptr()),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st.cuda_stream)))
+    for _ in range(3):
+        call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(calls):
+        call()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    k = int(kept.item())
+    algo = 2 * 16 * n + 2 * 56 * k   # opacity + scales read by both passes; survivors read and written
+    return {"workload": f"map pruning (opacity 0.005, scale 0.25, elongation 10) of the {n // 1000}k-Gaussian room map",
+            "ms_per_call": round(ms, 4), "kept": k, "n": n, "algorithmic_bytes": algo,
+            "hbm_TB_s": round(algo / ms / 1e9, 3), "hbm_frac_of_8TB_s": round(algo / ms / 1e9 / 8.0, 3)}
 
 
 SSIM_FLOPS_PER_VALUE = 390   # separable window sums: 5 statistics x 2 x 11 FMAs + 3 partials x 2 x 11 FMAs, + ~40
@@ -450,6 +490,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
+    if not args.no_prune:
+        out["prune"] = prune_bench(m)
     ssim_frames = None
     if not args.no_ssim:
         ssim_frames = (tracker.out[0].clone(), target[0].clone())

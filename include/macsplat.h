@@ -321,6 +321,25 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
 int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channels, int32_t width, int32_t height,
                           float weight, float* grad, int32_t accumulate, float* loss, void* stream);
 
+/* ----------------------------------------------------------------- map upkeep
+ * Map pruning (App. C.1, Algorithm 1). A Gaussian is removed when its opacity
+ * is below tau_o (0.005 in the paper), or, when tau_s > 0, when its largest
+ * scale exceeds tau_s (0.25) or exceeds tau_e (10) times the sum of its other
+ * two scales; tau_s <= 0 runs the opacity test alone. The comparisons are
+ * strict and taken in binary32: the largest scale is the first of s0, s1, s2
+ * that no later one exceeds, the other two are added in index order.
+ * in: the map (device, planar [k][n]). out: device arrays with room for
+ * k x out->n floats each, out->n >= in->n, aliasing no input array; the
+ * survivors are written in their original order as planar [k][kept] (row
+ * stride kept). kept: device int64 receiving the survivor count. workspace:
+ * device scratch of ms_prune_workspace_bytes(n) bytes. Errors:
+ * MS_ERR_INVALID_ARG (null or aliased arrays, capacity, non-finite
+ * thresholds, tau_e < 0), MS_ERR_WORKSPACE; nothing is enqueued then.
+ * Enqueued on `stream`. */
+size_t ms_prune_workspace_bytes(int64_t n);
+int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
+                 void* workspace, size_t ws_bytes, void* stream);
+
 /* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
  * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
  * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]

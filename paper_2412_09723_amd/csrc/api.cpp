@@ -659,6 +659,31 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
   return MS_OK;
 }
 
+size_t ms_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
+
+int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
+                 void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_map(in);
+  if (s != MS_OK) return s;
+  if (in->n < 0) return fail(MS_ERR_INVALID_ARG, "n = %lld < 0", (long long)in->n);
+  if (!out || !kept) return fail(MS_ERR_INVALID_ARG, "null output");
+  if (in->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->colors))
+    return fail(MS_ERR_INVALID_ARG, "null output array");
+  if (out->n < in->n) return fail(MS_ERR_INVALID_ARG, "output capacity %lld < n = %lld", (long long)out->n, (long long)in->n);
+  const float* ia[5] = {in->means, in->scales, in->quats, in->opacity, in->colors};
+  const float* oa[5] = {out->means, out->scales, out->quats, out->opacity, out->colors};
+  for (int u = 0; u < 5 && in->n > 0; u++)
+    for (int v = 0; v < 5; v++)
+      if (ia[u] == oa[v]) return fail(MS_ERR_INVALID_ARG, "output array aliases an input array");
+  if (!std::isfinite(tau_o) || !std::isfinite(tau_s) || !std::isfinite(tau_e) || tau_e < 0.f)
+    return fail(MS_ERR_INVALID_ARG, "thresholds must be finite and tau_e >= 0");
+  if (!workspace) return fail(MS_ERR_WORKSPACE, "null workspace");
+  if (ws_bytes < prune_workspace_bytes(in->n)) return fail(MS_ERR_WORKSPACE, "workspace too small");
+  hipError_t e = launch_prune(*in, *out, tau_o, tau_s, tau_e, kept, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "prune");
+  return MS_OK;
+}
+
 int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state, float lr, float beta1, float beta2,
                           float eps, void* stream) {
   if (!viewmat || !twist_grad || !state) return fail(MS_ERR_INVALID_ARG, "null argument");

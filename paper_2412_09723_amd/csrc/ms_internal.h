@@ -213,6 +213,11 @@ struct SsimArgs {
   float w[11];
 };
 hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st);
+// Map pruning (prune.hip): scratch bytes for n Gaussians, and the three
+// launches writing the survivors into `out` (row stride *kept) and *kept.
+size_t prune_workspace_bytes(int64_t n);
+hipError_t launch_prune(const ms_map& in, const ms_map& out, float tau_o, float tau_s, float tau_e, int64_t* kept,
+                        void* ws, hipStream_t st);
 hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,
                             hipStream_t st);
 

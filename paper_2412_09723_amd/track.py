@@ -94,3 +94,30 @@ def ssim_loss_grad(pred: torch.Tensor, target: torch.Tensor, weight: float = 0.2
                                 int(H), float(weight), ctypes.c_void_p(grad.data_ptr()), int(bool(accumulate)),
                                 ctypes.c_void_p(loss.data_ptr() if loss is not None else 0), stream))
     return grad
+
+
+def prune_map(m: dict, tau_o: float = 0.005, tau_s: float = 0.25, tau_e: float = 10.0) -> dict:
+    """Map pruning of App. C.1 (Algorithm 1) through ms_prune: a new map of
+    the surviving Gaussians in their original order. One host synchronisation
+    reads the survivor count."""
+    from ._lib import MsMap
+    keys = ("means", "scales", "quats", "opacity", "colors")
+    n = m["means"].shape[1]
+    dev = m["means"].device
+    for k in keys:
+        if m[k].dtype != torch.float32 or not m[k].is_contiguous() or m[k].shape[-1] != n:
+            raise ValueError(f"map {k} must be contiguous float32 with n = {n} columns")
+    rows = {"means": 3, "scales": 3, "quats": 4, "opacity": 1, "colors": 3}
+    bufs = {k: torch.empty(rows[k] * max(n, 1), dtype=torch.float32, device=dev) for k in keys}
+    kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = _lib.load()
+    wsb = int(lib.ms_prune_workspace_bytes(n))
+    ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
+    src = MsMap(n, *[m[k].data_ptr() for k in keys])
+    dst = MsMap(n, *[bufs[k].data_ptr() for k in keys])
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    check(lib.ms_prune(ref(src), float(tau_o), float(tau_s), float(tau_e), ref(dst), ctypes.c_void_p(kept.data_ptr()),
+                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream))
+    k = int(kept.item())
+    return {key: (bufs[key][:rows[key] * k].view(rows[key], k) if key != "opacity" else bufs[key][:k])
+            for key in keys}

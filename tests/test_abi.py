@@ -147,6 +147,26 @@ def test_shared_map_gradients_need_the_accumulate_flag(lib):
     assert batch(job(shared, 0), job(other, 0)) == _lib.MS_ERR_WORKSPACE
 
 
+def test_prune_rejects_bad_arguments(lib):
+    m = MsMap(4096, FAKE, FAKE + 0x100000, FAKE + 0x200000, FAKE + 0x300000, FAKE + 0x400000)
+    out = MsMap(4096, FAKE + 0x500000, FAKE + 0x600000, FAKE + 0x700000, FAKE + 0x800000, FAKE + 0x900000)
+    kept = ctypes.c_void_p(FAKE + 0xA00000)
+
+    def call(src=m, dst=out, to=0.005, ts=0.25, te=10.0, ws=FAKE + 0xB00000, wsb=1 << 20, k=kept):
+        return lib.ms_prune(ref(src) if src is not None else None, to, ts, te, ref(dst) if dst is not None else None,
+                            k, ctypes.c_void_p(ws), wsb, None)
+    assert call(src=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(dst=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(k=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(dst=MsMap(4095, *[getattr(out, f) for f in ("means", "scales", "quats", "opacity", "colors")])) \
+        == _lib.MS_ERR_INVALID_ARG                                          # capacity below n
+    assert call(dst=MsMap(4096, out.means, out.scales, m.quats, out.opacity, out.colors)) == _lib.MS_ERR_INVALID_ARG
+    assert call(te=-1.0) == _lib.MS_ERR_INVALID_ARG
+    assert call(to=float("nan")) == _lib.MS_ERR_INVALID_ARG
+    assert call(ws=0) == _lib.MS_ERR_WORKSPACE
+    assert call(wsb=lib.ms_prune_workspace_bytes(4096) - 1) == _lib.MS_ERR_WORKSPACE
+
+
 def test_ssim_loss_rejects_bad_arguments(lib):
     def call(pred=FAKE, target=FAKE, C=3, W=64, H=48, weight=0.2, grad=FAKE + 64, acc=0):
         return lib.ms_ssim_loss_grad(ctypes.c_void_p(pred), ctypes.c_void_p(target), C, W, H, weight,
