@@ -48,10 +48,17 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
   const int t = threadIdx.x;
   const int W = A.W, H = A.H;
   const int64_t P = (int64_t)W * H;
-  const int X0 = (int)blockIdx.x * kSsimTile, Y0 = (int)blockIdx.y * kSsimTile;
-  const float* __restrict__ x = A.pred + (int64_t)blockIdx.z * P;
-  const float* __restrict__ y = A.target + (int64_t)blockIdx.z * P;
-  float* __restrict__ grad = A.grad + (int64_t)blockIdx.z * P;
+  // workgroups go to the eight XCDs in turn: give each XCD a contiguous run
+  // of tiles so that neighbouring tiles' halos meet in one L2
+  const int gx = (W + kSsimTile - 1) / kSsimTile, gy = (H + kSsimTile - 1) / kSsimTile;
+  const int total = gx * gy * A.C, per = (total + 7) / 8;
+  const int tile = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+  if (tile >= total) return;
+  const int bz = tile / (gx * gy), rem = tile - bz * gx * gy, by = rem / gx, bx = rem - by * gx;
+  const int X0 = bx * kSsimTile, Y0 = by * kSsimTile;
+  const float* __restrict__ x = A.pred + (int64_t)bz * P;
+  const float* __restrict__ y = A.target + (int64_t)bz * P;
+  float* __restrict__ grad = A.grad + (int64_t)bz * P;
   float g[kSsimTaps];
 #pragma unroll
   for (int k = 0; k < kSsimTaps; k++) g[k] = A.w[k];
@@ -230,7 +237,7 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
     float s = 0.f;
     for (int w = 0; w < kSsimThreads / 64; w++) s += red[w];
     // weight * (1 - mean S): the constant once, from the first workgroup
-    const bool first = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
+    const bool first = bx == 0 && by == 0 && bz == 0;
     unsafeAtomicAdd(A.loss, A.dS * s + (first ? A.weight : 0.f));
   }
 }
@@ -239,8 +246,9 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
 
 hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st) {
   if (a.W <= 0 || a.H <= 0 || a.C <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((a.W + kSsimTile - 1) / kSsimTile), (unsigned)((a.H + kSsimTile - 1) / kSsimTile),
-                  (unsigned)a.C);
+  // one workgroup per (tile, channel), rounded up to a multiple of the eight XCDs
+  const int total = ((a.W + kSsimTile - 1) / kSsimTile) * ((a.H + kSsimTile - 1) / kSsimTile) * a.C;
+  const dim3 grid((unsigned)((total + 7) / 8 * 8));
   hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSsimThreads), 0, st, a);
   return hipGetLastError();
 }
