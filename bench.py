@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--pose-only", action="store_true", help="pose gradients only (tracking variant)")
     ap.add_argument("--fwd-records", choices=("lds", "scalar"), default="lds",
                     help="forward compositing record path: LDS staging or scalar (SGPR) loads")
-    ap.add_argument("--bwd-records", choices=("lds", "scalar", "mfma"), default="mfma",
+    ap.add_argument("--bwd-records", choices=("lds", "scalar", "mfma", "mfma_bf16x3"), default="mfma",
                     help="backward compositing record path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")

@@ -134,7 +134,12 @@ typedef struct {
                                            then sum into one set of arrays. Float atomics: the summation
                                            order, and so the last bits, vary from run to run. */
 #define MS_FLAG_MFMA_BWD 16u        /* backward compositing with the per-Gaussian reduction over each 8x8
-                                       sub-block done as a matrix-core product */
+                                       sub-block done as a matrix-core product in binary32 (fp32
+                                       operands and accumulation, v_mfma_f32_16x16x4_f32) */
+#define MS_FLAG_BWD_BF16X3 64u      /* with MS_FLAG_MFMA_BWD: form that product from bf16 high/low parts
+                                       (hi*hi + hi*lo + lo*hi, about 16 significant bits per term,
+                                       fp32 accumulation; v_mfma_f32_16x16x32_bf16). Faster, less
+                                       precise; not the default */
 
 /* Launch options. tile: edge in pixels of the screen tile one compositing
  * workgroup owns, 8 | 16 | 32. bin_tile: edge of the tiles whose

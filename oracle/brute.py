@@ -9,7 +9,12 @@ two can pin each other on tiny scenes (<= 64 Gaussians, <= 32x32 pixels):
   * the conic is numpy's matrix inverse of the 2x2 screen covariance;
   * the pinned decision values (pixel box, depth key, binary32 Mahalanobis
     test) are re-implemented here in numpy with an exact emulation of the
-    binary32 fused multiply-add.
+    binary32 fused multiply-add;
+  * render(acceptance="plain") drops that recipe altogether: candidates,
+    order and per-pixel acceptance come from the plain binary64 definition
+    (d^2 <= 9 and o exp(-d^2/2) >= 1/255 from numpy's inverse of the screen
+    covariance), so comparing it with the oracle tests the recipe instead of
+    restating it.
 
 Compositing follows Eq. 2 of the paper (front-to-back "over"), with the
 readings stated in oracle.cpp (alpha clamp 0.99, 3-sigma footprint, 1/255
@@ -193,13 +198,59 @@ def continuous(scene):
     return out
 
 
-def render(scene, near_z=0.2):
-    """Per-pixel brute force: every pixel against every Gaussian, in
-    (zkey, index) order. Returns rgb [3,H,W], depth, sil, tfinal, ncomp."""
+PLAIN_MARGIN = 1e-5   # relative closeness to a threshold that makes a plain decision ambiguous
+
+
+def plain_accept(c, opacity, x, y):
+    """The plain definition of "Gaussian counts at pixel (x, y)", in binary64
+    from the continuous projection: d^2 <= 9 and o exp(-d^2 / 2) >= 1/255,
+    d^2 = (p - mu')^T Sigma'^-1 (p - mu'). Returns (accepted, ambiguous):
+    ambiguous when d^2 lies within PLAIN_MARGIN (relative) of 9, or
+    o exp(-d^2 / 2) within PLAIN_MARGIN of 1/255."""
+    dx, dy = np.asarray(x, np.float64) - c["u"], np.asarray(y, np.float64) - c["v"]
+    Q = c["conic"]
+    d2 = Q[0, 0] * dx * dx + 2.0 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+    at = opacity * np.exp(-0.5 * d2)
+    acc = (d2 <= 9.0) & (at >= 1.0 / 255.0)
+    amb = (np.abs(d2 - 9.0) <= PLAIN_MARGIN * 9.0) | (np.abs(at * 255.0 - 1.0) <= PLAIN_MARGIN)
+    return acc, amb
+
+
+def render(scene, near_z=0.2, acceptance="recipe"):
+    """Per-pixel brute force: every pixel against every Gaussian. Returns
+    rgb [3,H,W], depth, sil, tfinal, ncomp.
+
+    acceptance="recipe": visibility, order and the per-pixel test follow the
+    pinned binary32 recipe (depth key, then index; q <= qcut inside the pixel
+    box). acceptance="plain": they follow the definition alone, in binary64:
+    a Gaussian is a candidate when its mean lies beyond the near plane with
+    finite attributes and a non-zero quaternion, candidates are visited by
+    (binary64 camera depth, index), and one counts at a pixel by
+    plain_accept. The result then also holds `ambiguous`, the pixels where
+    some candidate's decision lies within PLAIN_MARGIN of its threshold."""
+    if acceptance not in ("recipe", "plain"):
+        raise ValueError(acceptance)
+    plain = acceptance == "plain"
     pins = pinned(scene, near_z)
     cont = continuous(scene)
     W, H = scene.intr.width, scene.intr.height
-    order = sorted([i for i in range(scene.n) if pins[i]["visible"]], key=lambda i: (pins[i]["zkey"], i))
+    if plain:
+        near = float(np.float32(near_z))
+        cand = []
+        for i in range(scene.n):
+            p = cont[i]["p"]
+            attrs = np.concatenate([scene.scales[:, i], scene.colors[:, i], [scene.opacity[i]]])
+            if (p[2] > near and np.all(np.isfinite(p)) and np.all(np.isfinite(attrs))
+                    and np.any(scene.quats[:, i] != 0) and np.all(np.isfinite(cont[i]["conic"]))):
+                cand.append(i)
+        order = sorted(cand, key=lambda i: (cont[i]["p"][2], i))
+        ys, xs = np.mgrid[0:H, 0:W]
+        dec = {i: plain_accept(cont[i], float(scene.opacity[i]), xs, ys) for i in order}
+        ambiguous = np.zeros((H, W), bool)
+        for i in order:
+            ambiguous |= dec[i][1]
+    else:
+        order = sorted([i for i in range(scene.n) if pins[i]["visible"]], key=lambda i: (pins[i]["zkey"], i))
     rgb = np.zeros((3, H, W))
     depth = np.zeros((H, W))
     tfin = np.ones((H, W))
@@ -211,11 +262,15 @@ def render(scene, near_z=0.2):
             D = 0.0
             k = 0
             for i in order:
-                r = pins[i]
-                if not (r["xlo"] <= x <= r["xhi"] and r["ylo"] <= y <= r["yhi"]):
-                    continue
-                if not (pinned_q(r, x, y) <= r["qcut"]):
-                    continue
+                if plain:
+                    if not dec[i][0][y, x]:
+                        continue
+                else:
+                    r = pins[i]
+                    if not (r["xlo"] <= x <= r["xhi"] and r["ylo"] <= y <= r["yhi"]):
+                        continue
+                    if not (pinned_q(r, x, y) <= r["qcut"]):
+                        continue
                 c = cont[i]
                 d = np.array([x - c["u"], y - c["v"]])
                 pw = -0.5 * float(d @ c["conic"] @ d)
@@ -231,4 +286,7 @@ def render(scene, near_z=0.2):
             depth[y, x] = D
             tfin[y, x] = T
             ncomp[y, x] = k
-    return dict(rgb=rgb, depth=depth, sil=1.0 - tfin, tfinal=tfin, ncomp=ncomp, pinned=pins, cont=cont)
+    out = dict(rgb=rgb, depth=depth, sil=1.0 - tfin, tfinal=tfin, ncomp=ncomp, pinned=pins, cont=cont)
+    if plain:
+        out["ambiguous"] = ambiguous
+    return out

@@ -24,6 +24,7 @@ MS_FLAG_SCALAR_FWD = 4
 MS_FLAG_SCALAR_BWD = 8
 MS_FLAG_MFMA_BWD = 16
 MS_FLAG_ACCUMULATE_MAP_GRADS = 32
+MS_FLAG_BWD_BF16X3 = 64
 
 EXPORTED = [
     "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes",

@@ -632,6 +632,15 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
     return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", width, height);
   if (!std::isfinite(weight)) return fail(MS_ERR_INVALID_ARG, "non-finite loss weight");
   if (accumulate != 0 && accumulate != 1) return fail(MS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  {
+    // every workgroup reads a halo of neighbouring pixels: a gradient written
+    // over an input would race with those reads
+    const size_t bytes = (size_t)channels * (size_t)width * (size_t)height * sizeof(float);
+    const uintptr_t g0 = (uintptr_t)grad, g1 = g0 + bytes;
+    const uintptr_t p0 = (uintptr_t)pred, t0 = (uintptr_t)target;
+    if ((g0 < p0 + bytes && p0 < g1) || (g0 < t0 + bytes && t0 < g1))
+      return fail(MS_ERR_INVALID_ARG, "grad overlaps pred or target");
+  }
   hipStream_t st = (hipStream_t)stream;
   SsimArgs a;
   a.pred = pred;

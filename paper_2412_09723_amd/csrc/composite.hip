@@ -40,7 +40,7 @@ struct Staged {
   float4 geo;    // gx = X0 - ui, gy = Y0 - vi (exact), uf, vf
   float4 conic;  // a, b, c, qcut
   float4 app;    // log2 o, z, r, g
-  float4 misc;   // b(lue), rank bits, list position + 1 (bits), moment flag (backward) or 0
+  float4 misc;   // b(lue), rank bits, list position + 1 (bits), 0
 };
 
 // An entry that accepts no pixel, with finite fields (pads a packed chunk to
@@ -54,15 +54,6 @@ __device__ inline Staged inert_entry() {
   return s;
 }
 
-#ifndef MS_MOMENT_SPREAD
-#define MS_MOMENT_SPREAD 16.f
-#endif
-// Where (|a U| + (|b| + |c|) |V|)^2 exceeds this multiple of qcut, with (U, V)
-// the Gaussian's centre relative to the sub-block centre (a spread of 4
-// acceptance radii), the backward takes the record's conic sums from
-// per-pixel products rather than from block-centred moments.
-constexpr float kMomentSpread = MS_MOMENT_SPREAD;
-
 // Conservative test that a record's acceptance ellipse can reach a pixel of
 // the 8x8 sub-block at (X0, Y0), from the record's centre words ctr = (ui,
 // vi, uf, vf) and conic words con = (a, b, c, qcut). The offsets the pixels use, dx = (x - ui) - uf rounded, lie in
@@ -72,10 +63,7 @@ constexpr float kMomentSpread = MS_MOMENT_SPREAD;
 // those exact forms, so reducing m1, m2 by 2^-20 (|a| |dx|max + |b| |dy|max + 3)
 // and 2^-20 |c| |dy|max, and allowing qcut (1 + 2^-20), leaves no accepted
 // pixel out: a record that fails composites nowhere in the sub-block.
-// With kSpread, `wide` tells whether the record's moments about the sub-block
-// centre are badly conditioned (kMomentSpread).
-template <bool kSpread>
-__device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X0, int Y0, bool& wide) {
+__device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X0, int Y0) {
   constexpr float kEps = 0x1p-20f;
   const float ui = __uint_as_float(ctr.x), vi = __uint_as_float(ctr.y);
   const float uf = __uint_as_float(ctr.z), vf = __uint_as_float(ctr.w);
@@ -93,11 +81,6 @@ __device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X
   const float e1 = kEps * ((fabsf(a) * fmaxf(fabsf(x0), fabsf(x1)) + fabsf(b) * ym) + 3.f);
   const float e2 = kEps * (fabsf(c) * ym);
   const float r1 = fmaxf(m1 - e1, 0.f), r2 = fmaxf(m2 - e2, 0.f);
-  if (kSpread) {
-    const float U = ((-gx) - 3.5f) + uf, V = ((-gy) - 3.5f) + vf;
-    const float spread = fabsf(a) * fabsf(U) + (fabsf(b) + fabsf(c)) * fabsf(V);
-    wide = spread * spread > kMomentSpread * qc;
-  }
   return __builtin_fmaf(r1, r1, r2 * r2) <= qc * (1.f + kEps);
 }
 
@@ -110,18 +93,14 @@ __device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X
 // against the sub-block (ellipse_reaches, one record per lane); the quad's
 // last lane then holds the record's pixel box, a record is packed when the
 // box meets the sub-block and the ellipse test held, and a ballot plus a
-// masked bit count gives each packed record its slot. With kSpread, misc.w
-// of a packed record is 1 where its block-centred moments are badly
-// conditioned.
-template <bool kSpread>
+// masked bit count gives each packed record its slot.
 __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                   uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
                                   Staged* __restrict__ dst) {
   const uint32_t rank = lane < n ? (pval[start + lo + (uint32_t)lane] & rank_mask) : 0u;
-  bool reach = false, wide = false;
-  if (lane < n) reach = ellipse_reaches<kSpread>(rec[4 * (int64_t)rank], rec[4 * (int64_t)rank + 1], X0, Y0, wide);
+  bool reach = false;
+  if (lane < n) reach = ellipse_reaches(rec[4 * (int64_t)rank], rec[4 * (int64_t)rank + 1], X0, Y0);
   const uint64_t rm = __builtin_amdgcn_ballot_w64(reach);
-  const uint64_t wm = kSpread ? __builtin_amdgcn_ballot_w64(wide) : 0u;
   const int part = lane & 3, sub = lane >> 2;
   uint4 v[4];
   uint32_t rk[4];
@@ -156,8 +135,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
           o.x = (float)X0 - o.x;   // exact: both are integers below 2^24
           o.y = (float)Y0 - o.y;
         } else if (part == 3) {
-          o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u),
-                          ((wm >> e) & 1u) ? 1.f : 0.f);
+          o = make_float4(o.x, __uint_as_float(rk[k]), __uint_as_float(lo + (uint32_t)e + 1u), 0.f);
         }
         reinterpret_cast<float4*>(dst + slot)[part] = o;
       }
@@ -170,7 +148,7 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
 // Packs a chunk of up to WB entries (WB / 64 rounds of stage_chunk) and pads
 // the packed count to a multiple of `group` with inert entries; returns the
 // padded count.
-template <int WB, bool kSpread = false>
+template <int WB>
 __device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
                                          uint32_t rank_mask, uint32_t start, uint32_t lo, int nb, int X0, int Y0,
                                          int lane, Staged* __restrict__ dst, int group, int& packed) {
@@ -179,7 +157,7 @@ __device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const ui
   for (int h = 0; h < WB; h += 64) {
     const int n = nb - h;
     if (n > 0)
-      cnt += stage_chunk<kSpread>(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane,
+      cnt += stage_chunk(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane,
                                   dst + cnt);
   }
   const int padded = (cnt + group - 1) / group * group;
@@ -694,11 +672,10 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
 // product M A^T yields both sets of sums: per 32-pixel half, three
 // v_mfma_f32_16x16x32_bf16 on high and low bf16 parts (about 16 significant
 // bits per term). One lane per Gaussian then shifts the moments to the
-// Gaussian's centre and forms the ten sums; rows where that shift is badly
-// conditioned (needle-like Gaussians far from their centre) take their conic
-// sums from per-pixel products instead. The sums leave as whole-Gaussian
-// atomics, through the workgroup's LDS accumulator where the list position
-// allows.
+// Gaussian's centre and forms the ten sums, as the binary32 kernel below
+// does (its error bound holds here with the bf16 product error, about
+// 2^-15 per term, in place of u). The sums leave as whole-Gaussian atomics,
+// through the workgroup's LDS accumulator where the list position allows.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -857,58 +834,24 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     const float S4 = __shfl(d[0], 16 + l, 64), S5 = __shfl(d[1], 16 + l, 64);
     const float W6 = __shfl(d[2], 24 + l, 64), W7 = __shfl(d[3], 24 + l, 64);
     const float W8 = __shfl(d[0], 40 + l, 64), W9 = __shfl(d[1], 40 + l, 64);
-    // The moment form multiplies the sums by the centre offset (U, V) of the
-    // Gaussian from the sub-block centre, which loses precision where the
-    // conic terms a U, b V, c V are large next to the acceptance radius (a
-    // needle-like Gaussian crossing the sub-block far from its centre). Such
-    // rows get their five conic sums from the pixels' own offsets instead:
-    // per pixel e t1, e t2, e t1 dx, e t1 dy, e t2 dy, summed over the wave.
-    const bool bad = lane < count && my[rowent].misc.w != 0.f;   // flagged when staged
-    uint64_t badm = __builtin_amdgcn_ballot_w64(bad);
-    float X1 = 0.f, X2 = 0.f, X3 = 0.f, X4 = 0.f, X5 = 0.f;
-    while (badm != 0) {   // uniform
-      const int g = __builtin_ctzll(badm);
-      badm &= badm - 1;
-      const Staged& sg = my[__builtin_amdgcn_readlane(rowent, g)];
-      const float e = A[g * kRow + eaddr];
-      const float dx = (xf + sg.geo.x) - sg.geo.z;
-      const float dy = (yf + sg.geo.y) - sg.geo.w;
-      const float t1 = __builtin_fmaf(sg.conic.x, dx, sg.conic.y * dy);
-      const float et1 = e * t1, et2 = e * (sg.conic.z * dy);
-      const float s1 = wave_sum_dpp(et1), s2 = wave_sum_dpp(et2);
-      const float s3 = wave_sum_dpp(et1 * dx), s4 = wave_sum_dpp(et1 * dy), s5 = wave_sum_dpp(et2 * dy);
-      if (lane == g) {
-        X1 = s1;
-        X2 = s2;
-        X3 = s3;
-        X4 = s4;
-        X5 = s5;
-      }
-    }
     if (lane < count) {
       const Staged& sg = my[rowent];
       const float S1 = d[0], Sx = d[1], Sy = d[2], Sxx = d[3], Sxy = S4, Syy = S5;
       const float U = ((-sg.geo.x) - 3.5f) + sg.geo.z;   // ui - X0 - 3.5 + uf
       const float V = ((-sg.geo.y) - 3.5f) + sg.geo.w;
       const float a = sg.conic.x, b = sg.conic.y, c = sg.conic.z;
-      const float Edx = Sx - U * S1, Edy = Sy - V * S1;
-      const float Edxx = Sxx - 2.f * U * Sx + U * U * S1;
-      const float Edxy = Sxy - V * Sx - U * Sy + U * V * S1;
-      const float Edyy = Syy - 2.f * V * Sy + V * V * S1;
+      // the moments shift to the Gaussian's centre through k1 = a U + b V,
+      // which stays bounded for any Gaussian composited in the sub-block (see
+      // the binary32 kernel below for the bound)
+      const float k1 = __builtin_fmaf(a, U, b * V);
+      const float P1 = __builtin_fmaf(a, Sx, __builtin_fmaf(b, Sy, -(k1 * S1)));
       float f[kGradFields];
       f[0] = S1;
-      f[1] = a * Edx + b * Edy;
-      f[2] = c * Edy;
-      f[3] = a * Edxx + b * Edxy;
-      f[4] = a * Edxy + b * Edyy;
-      f[5] = c * Edyy;
-      if (bad) {
-        f[1] = X1;
-        f[2] = X2;
-        f[3] = X3;
-        f[4] = X4;
-        f[5] = X5;
-      }
+      f[1] = P1;
+      f[2] = c * __builtin_fmaf(-V, S1, Sy);
+      f[3] = __builtin_fmaf(a, Sxx, __builtin_fmaf(b, Sxy, -(k1 * Sx))) - U * P1;
+      f[4] = __builtin_fmaf(a, Sxy, __builtin_fmaf(b, Syy, -(k1 * Sy))) - V * P1;
+      f[5] = c * __builtin_fmaf(V * V, S1, __builtin_fmaf(-2.f * V, Sy, Syy));
       f[6] = W6;
       f[7] = W7;
       f[8] = W8;
@@ -946,8 +889,8 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<kBwdChunk, true>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
-                                                        kBwdStep, packed);
+    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
+                                                   kBwdStep, packed);
     wave_sync();
     reduced += (uint32_t)packed;
     int rows = 0;   // uniform: rows of A filled since the last product
@@ -1015,6 +958,322 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       }
     }
   }
+}
+
+// Backward with the per-Gaussian reduction over the wave's 64 pixels on the
+// matrix cores in binary32 (v_mfma_f32_16x16x4_f32: fp32 operands, fp32
+// accumulation). Each Gaussian the wave composites gets two columns of a
+// wave-private 16-column LDS matrix, one value per pixel:
+//   e = dL/dalpha * alpha~,   w = alpha T.
+// The moment operand holds, per pixel, the rows
+//   1, xi, eta, xi^2, xi eta, eta^2, G_r, G_g, G_b, G_D
+// (xi, eta the pixel's offset from the sub-block centre), so one product
+// yields, for eight Gaussians at a time, the moments
+//   S = sum e (1, xi, eta, xi^2, xi eta, eta^2)   and   sum w (G_r, G_g, G_b, G_D).
+// With (U, V) the Gaussian centre's offset from the sub-block centre, a pixel
+// has dx = xi - U, dy = eta - V, t2 = c dy and
+//   t1 = a dx + b dy = (a xi + b eta) - k1,   k1 = a U + b V,
+// so the ten screen-space sums are
+//   E = S1,  P1 = a Sx + b Sy - k1 S1,  P2 = c (Sy - V S1),
+//   P1x = (a Sxx + b Sxy - k1 Sx) - U P1,  P1y = (a Sxy + b Syy - k1 Sy) - V P1,
+//   P2y = c ((Syy - 2 V Sy) + V^2 S1),
+// and the four weighted upstream sums.
+//
+// Error bound. The screen covariance carries the 0.3 px^2 dilation, which
+// bounds the scaled Cholesky factors: |a|, |b|, |c| <= K / sqrt(0.3) ~ 1.55
+// (K^2 = log2(e) / 2). A Gaussian that composites at some pixel of the
+// sub-block has |t1| <= sqrt(qcut) there, and |xi|, |eta| <= 3.5, so
+//   |k1| <= 3.5 (|a| + |b|) + sqrt(qcut),     |c V| <= 3.5 |c| + sqrt(qcut).
+// Forming k1 first (one rounding of relative size u = 2^-24, the same
+// rounding the pixel's own t1 carries) and with gamma the binary32 error of
+// a 64-term sum, each moment errs by at most gamma sum |e| |monomial|, and
+//   |dP1| <= (gamma + 3u) L sum|e|,        L = 3.5 (|a| + |b|) + |k1| <= 13.5,
+//   |dP1x| <= (gamma + 4u) (3.5 + |U|) L sum|e|,   |dP1y| likewise with V,
+//   |dP2| <= (gamma + 2u) (7 |c| + sqrt(qcut)) sum|e|,
+//   |dP2y| <= (gamma + 4u) (7 |c| + sqrt(qcut)) (3.5 + |V|) sum|e|,
+// while the sums themselves are bounded by sqrt(qcut) sum|e| times the same
+// offset factors. Relative to that size the error is (gamma + 4u) times at
+// most (13.5 + sqrt(qcut)) / sqrt(qcut): no Gaussian shape (elongation,
+// distance of its centre from the sub-block) makes it grow; only opacity
+// within a few per cent of the 1/255 floor (qcut near 0, where every sum is
+// small) does, and there the absolute error stays below 16 (gamma + 4u)
+// sum|e|. (Shifting by U and V separately, as Sx - U S1 and Sy - V S1, adds
+// roundings of size u |a U| and u |b V|, which grow with the distance of an
+// elongated Gaussian's centre; k1 does not.)
+constexpr int kGrpF = 8;                       // Gaussians per product (two columns each)
+
+template <int TILE>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
+    k_composite_bwd_f(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
+                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobTable tbl,
+                      JobTable* __restrict__ tbl_dst, int bshift, const float* __restrict__ tfinal,
+                      const uint32_t* __restrict__ last, float* __restrict__ g2d) {
+  constexpr int SB = TILE / 8;
+  constexpr int NW = SB * SB;
+  const JobDesc* jobs = tbl.job;
+  const int njobs = tbl.njobs;
+  if (blockIdx.x == 0) {   // leave the job table for the projection adjoint
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&tbl);
+    uint32_t* d = reinterpret_cast<uint32_t*>(tbl_dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
+  }
+  __shared__ __attribute__((aligned(16))) float lds[NW * kWaveLds];
+  __shared__ Staged stage[NW][kBwdChunk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int W = J.W, H = J.H;
+  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tx = tile_id % J.tx, ty = tile_id / J.tx;
+  const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
+  const float* __restrict__ g_rgb = J.g_rgb;
+  const float* __restrict__ g_depth = J.g_depth;
+  const float* __restrict__ g_sil = J.g_sil;
+  const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
+  if (counters_rw[C_OVERFLOW] != 0) return;   // uniform over the launch
+  // sums of the block's waves for one Gaussian meet in LDS, indexed by list
+  // position (the same in every wave of the block); positions past kAcc go
+  // straight to HBM
+  constexpr int kAcc = NW > 1 ? kAccRows : 0;
+  __shared__ float acc[kAcc > 0 ? kAcc * kGradFields : 1];
+  if (kAcc > 0) {
+    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
+    __syncthreads();
+  }
+  if (X0 < W && Y0 < H) {   // wave-uniform: sub-blocks wholly outside the image do nothing
+  float* A = lds + wave * kWaveLds;   // [16 columns][kRow]: column j, pixel p at j * kRow + p
+  Staged* my = stage[wave];
+  const int xl = lane & 7, yl = lane >> 3;
+  const int x = X0 + xl, y = Y0 + yl;
+  const bool inside = x < W && y < H;
+  const int64_t P = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GS = 0.f, Tf = 1.f;
+  uint32_t L = 0u;
+  if (inside) {
+    G0 = g_rgb[pix];
+    G1 = g_rgb[P + pix];
+    G2 = g_rgb[2 * P + pix];
+    GD = g_depth[pix];
+    GS = g_sil[pix];
+    Tf = tfinal[J.pix0 + pix];
+    L = last[J.pix0 + pix];
+  }
+  // Moment operand of v_mfma_f32_16x16x4_f32, constant per wave. Product k
+  // (0..15) covers the pixels 16 q + k, q = 0..3; lane (q, i) = (lane / 16,
+  // lane % 16) supplies row i of the moment matrix at pixel 16 q + k, and
+  // later column i of the value matrix at the same pixel.
+  const int pq = lane >> 4, pi = lane & 15;
+  float Mf[16];
+  A[lane * 4 + 0] = G0;
+  A[lane * 4 + 1] = G1;
+  A[lane * 4 + 2] = G2;
+  A[lane * 4 + 3] = GD;
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int p = 16 * pq + k;
+    const float px = (float)(p & 7) - 3.5f, py = (float)(p >> 3) - 3.5f;
+    float m = 0.f;
+    m = pi == 0 ? 1.f : m;
+    m = pi == 1 ? px : m;
+    m = pi == 2 ? py : m;
+    m = pi == 3 ? px * px : m;
+    m = pi == 4 ? px * py : m;
+    m = pi == 5 ? py * py : m;
+    m = (pi >= 6 && pi < 10) ? A[p * 4 + (pi - 6)] : m;
+    Mf[k] = m;
+  }
+  wave_sync();
+  const uint32_t Lmax = __builtin_amdgcn_readfirstlane(wave_max_u32(L));
+  const uint32_t start = trange[2 * bin_id];
+  const float xf = (float)xl, yf = (float)yl;
+  float T = Tf;
+  float Rs = -(GS * Tf);   // suffix sum of (G_rgb . c + G_depth z) alpha T, minus G_sil T_final
+  uint32_t reduced = 0u;
+  // Lane g < count holds in `rowent` the staged slot of the product's entry
+  // g, whose columns are g (e) and 8 + g (w).
+  int rowent = 0;
+  // sums bound for HBM and their accumulator rows, in columns 14 and 15 (w
+  // columns, read into registers before these are written)
+  float* Fg = A + 14 * kRow;                                              // [kGrpF][10]
+  uint32_t* Fslot = reinterpret_cast<uint32_t*>(Fg + kGrpF * kGradFields);   // [kGrpF]
+  static_assert(kGrpF * (kGradFields + 1) <= 2 * kRow, "HBM staging fits two columns");
+  auto flush = [&](int count) {
+    wave_sync();
+    const float4* r4 = reinterpret_cast<const float4*>(A + pi * kRow + 16 * pq);
+    const float4 v0 = r4[0], v1 = r4[1], v2 = r4[2], v3 = r4[3];
+    f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[0], v0.x, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[1], v0.y, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[2], v0.z, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[3], v0.w, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[4], v1.x, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[5], v1.y, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[6], v1.z, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[7], v1.w, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[8], v2.x, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[9], v2.y, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[10], v2.z, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[11], v2.w, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[12], v3.x, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[13], v3.y, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[14], v3.z, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[15], v3.w, d1, 0, 0, 0);
+    // lane (q, i) holds rows 4q .. 4q + 3 of column i. Entry g: lane g has
+    // S1, Sx, Sy, Sxx; lane 16 + g has Sxy, Syy; lane 24 + g the w-sums of
+    // G_r, G_g (rows 6, 7); lane 40 + g those of G_b, G_D (rows 8, 9).
+    const float s0 = d0[0] + d1[0], s1 = d0[1] + d1[1], s2 = d0[2] + d1[2], s3 = d0[3] + d1[3];
+    const int l = lane & 7;
+    const float Sxy = __shfl(s0, 16 + l, 64), Syy = __shfl(s1, 16 + l, 64);
+    const int ent = __shfl(rowent, l, 64);   // entry l's staged slot
+    bool to_global = false;
+    int i0 = 0;
+    float v0f = 0.f, v1f = 0.f;
+    const bool is_e = lane < count;
+    const bool is_w = (lane >= 24 && lane < 24 + count) || (lane >= 40 && lane < 40 + count);
+    if (is_e || is_w) {
+      const Staged& sg = my[ent];
+      const uint32_t pos = __float_as_uint(sg.misc.z) - 1u;   // list position
+      to_global = !(kAcc > 0 && pos < (uint32_t)kAcc);
+      float f[6];
+      if (is_e) {
+        const float S1 = s0, Sx = s1, Sy = s2, Sxx = s3;
+        const float U = ((-sg.geo.x) - 3.5f) + sg.geo.z;   // ui - X0 - 3.5 + uf
+        const float V = ((-sg.geo.y) - 3.5f) + sg.geo.w;   // vi - Y0 - 3.5 + vf
+        const float a = sg.conic.x, b = sg.conic.y, c = sg.conic.z;
+        const float k1 = __builtin_fmaf(a, U, b * V);
+        const float P1 = __builtin_fmaf(a, Sx, __builtin_fmaf(b, Sy, -(k1 * S1)));
+        f[0] = S1;
+        f[1] = P1;
+        f[2] = c * __builtin_fmaf(-V, S1, Sy);
+        f[3] = __builtin_fmaf(a, Sxx, __builtin_fmaf(b, Sxy, -(k1 * Sx))) - U * P1;
+        f[4] = __builtin_fmaf(a, Sxy, __builtin_fmaf(b, Syy, -(k1 * Sy))) - V * P1;
+        f[5] = c * __builtin_fmaf(V * V, S1, __builtin_fmaf(-2.f * V, Sy, Syy));
+      } else {
+        // rows 6, 7 in d[2], d[3] of lanes 24 + g; rows 8, 9 in d[0], d[1] of lanes 40 + g
+        const bool hi = lane >= 40;
+        v0f = hi ? s0 : s2;
+        v1f = hi ? s1 : s3;
+        i0 = hi ? 8 : 6;
+      }
+      if (!to_global) {
+        float* dst = &acc[pos * kGradFields];
+        if (is_e) {
+#pragma unroll
+          for (int k = 0; k < 6; k++) atomicAdd(dst + k, f[k]);
+        } else {
+          atomicAdd(dst + i0, v0f);
+          atomicAdd(dst + i0 + 1, v1f);
+        }
+      } else {
+        // global sums go through LDS so that each atomic instruction covers
+        // whole Gaussians (ten consecutive floats)
+        float* fg = Fg + l * kGradFields;
+        if (is_e) {
+#pragma unroll
+          for (int k = 0; k < 6; k++) fg[k] = f[k];
+          Fslot[l] = __float_as_uint(sg.misc.y);
+        } else {
+          fg[i0] = v0f;
+          fg[i0 + 1] = v1f;
+        }
+      }
+    }
+    const uint64_t gmask = __builtin_amdgcn_ballot_w64(is_e && to_global);
+    if (gmask != 0) {   // uniform
+      wave_sync();
+      for (int idx = lane; idx < count * kGradFields; idx += 64) {
+        const int ge = idx / kGradFields, fi = idx - ge * kGradFields;
+        if ((gmask >> ge) & 1u) {
+          const float v = Fg[idx];
+          if (v != 0.f) unsafeAtomicAdd(g2d + (int64_t)Fslot[ge] * kGradFields + fi, v);
+        }
+      }
+    }
+    wave_sync();   // the next columns overwrite Fg
+  };
+  for (uint32_t hi = Lmax; hi > 0;) {
+    const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
+    const int nb = (int)(hi - lo);
+    wave_sync();
+    int packed;
+    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
+                                                   kBwdStep, packed);
+    wave_sync();
+    reduced += (uint32_t)packed;
+    int rows = 0;   // uniform: entries with columns since the last product
+    for (int top = cnt - 1; top >= 0; top -= kBwdStep) {   // cnt is a multiple of kBwdStep
+      if (rows > kGrpF - kBwdStep) {   // room for a whole step of entries
+        flush(rows);
+        rows = 0;
+      }
+      float at[kBwdStep], alpha[kBwdStep], inv[kBwdStep], gcz[kBwdStep];
+      bool acc_k[kBwdStep];
+      int lo_slot = top - (kBwdStep - 1);
+      __asm__ volatile("" : "+v"(lo_slot));
+      const Staged* sp = my + lo_slot;
+#pragma unroll
+      for (int k = 0; k < kBwdStep; k++) {
+        const Staged& sk = sp[kBwdStep - 1 - k];
+        const float4 ge = sk.geo, cn = sk.conic, ap = sk.app;
+        const float2 mi = make_float2(sk.misc.x, sk.misc.z);
+        const float dx = (xf + ge.x) - ge.z;
+        const float dy = (yf + ge.y) - ge.w;
+        const float t1 = __builtin_fmaf(cn.x, dx, cn.y * dy);
+        const float t2 = cn.z * dy;
+        const float q = __builtin_fmaf(t1, t1, t2 * t2);
+        acc_k[k] = __float_as_uint(mi.y) <= L && q <= cn.w;   // list position < last
+        // a pixel that does not composite the entry takes alpha~ = 0: its
+        // weight, its e and its share of the suffix sum are then exactly zero
+        at[k] = acc_k[k] ? __builtin_amdgcn_exp2f(ap.x - q) : 0.f;
+        alpha[k] = fminf(kAlphaMax, at[k]);
+        inv[k] = __builtin_amdgcn_rcpf(1.f - alpha[k]);
+        gcz[k] = __builtin_fmaf(G0, ap.z, __builtin_fmaf(G1, ap.w, __builtin_fmaf(G2, mi.x, GD * ap.y)));
+      }
+#pragma unroll
+      for (int k = 0; k < kBwdStep; k++) {
+        const float Tk = T * inv[k];
+        const float w = alpha[k] * Tk;
+        const float dalpha = __builtin_fmaf(Tk, gcz[k], -Rs * inv[k]);
+        const float e = at[k] > kAlphaMax ? 0.f : dalpha * at[k];
+        Rs = __builtin_fmaf(gcz[k], w, Rs);
+        T = acc_k[k] ? Tk : T;
+        if (__builtin_amdgcn_ballot_w64(acc_k[k]) != 0) {   // uniform
+          A[rows * kRow + lane] = e;
+          A[(kGrpF + rows) * kRow + lane] = w;
+          rowent = writelane_u(top - k, rows, rowent);
+          rows++;
+        }
+      }
+    }
+    if (rows > 0) flush(rows);
+    hi = lo;
+  }
+  if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
+  }
+  if (kAcc > 0) {
+    __syncthreads();
+    const uint32_t start = trange[2 * bin_id];
+    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) {
+      const float v = acc[i];
+      if (v != 0.f) {   // only rows of list entries some wave packed
+        const int pos = i / kGradFields, fi = i - pos * kGradFields;
+        const uint32_t r = pval[start + (uint32_t)pos] & rank_mask;
+        unsafeAtomicAdd(g2d + (int64_t)r * kGradFields + fi, v);
+      }
+    }
+  }
+}
+
+template <int TILE>
+hipError_t bwd_mfma32(const Plan& p, const JobTable& t, char* ws, hipStream_t st) {
+  constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
+  hipLaunchKernelGGL((k_composite_bwd_f<TILE>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
+                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
+                     t, at<JobTable>(ws, p.jobs), p.bshift, at<float>(ws, p.tfinal), at<uint32_t>(ws, p.last),
+                     at<float>(ws, p.g2d));
+  return hipGetLastError();
 }
 
 template <int TILE>
@@ -1099,11 +1358,19 @@ hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, c
 hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, const JobTable& t, char* ws,
                                 hipStream_t st) {
   if (p.tiles == 0) return hipSuccess;
-  if (flags & MS_FLAG_MFMA_BWD) {
+  if ((flags & MS_FLAG_MFMA_BWD) && (flags & MS_FLAG_BWD_BF16X3)) {
     switch (p.tile) {
       case 8: return bwd_mfma<8>(p, t, ws, st);
       case 16: return bwd_mfma<16>(p, t, ws, st);
       case 32: return bwd_mfma<32>(p, t, ws, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (flags & MS_FLAG_MFMA_BWD) {
+    switch (p.tile) {
+      case 8: return bwd_mfma32<8>(p, t, ws, st);
+      case 16: return bwd_mfma32<16>(p, t, ws, st);
+      case 32: return bwd_mfma32<32>(p, t, ws, st);
       default: return hipErrorInvalidValue;
     }
   }

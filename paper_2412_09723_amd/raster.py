@@ -29,8 +29,9 @@ class RenderOptions:
     pair_capacity: int | None = None     # None: sized from the map (see default_capacity)
     check: bool = False                  # read the device counters after the forward (synchronises)
     fwd_records: str = "lds"             # forward compositing record path: "lds" staging or "scalar" (SGPR)
-    bwd_records: str = "mfma"            # backward compositing: "lds", "scalar" or "mfma" (scalar records,
-                                         # pixel reduction on the matrix cores; tile 8 or 16)
+    bwd_records: str = "mfma"            # backward compositing: "mfma" (per-Gaussian pixel reduction on the
+                                         # matrix cores in binary32), "mfma_bf16x3" (the same product from
+                                         # bf16 high/low parts), "lds" or "scalar" (wave reductions)
     grow: bool = True                    # with check: enlarge the pair capacity and redo on overflow
 
 
@@ -57,8 +58,10 @@ def opts_struct(opts: RenderOptions, flags: int = 0) -> MsOptions:
         flags |= _lib.MS_FLAG_SCALAR_FWD
     if opts.bwd_records == "scalar":
         flags |= _lib.MS_FLAG_SCALAR_BWD
-    if opts.bwd_records == "mfma":
+    if opts.bwd_records in ("mfma", "mfma_bf16x3"):
         flags |= _lib.MS_FLAG_MFMA_BWD
+    if opts.bwd_records == "mfma_bf16x3":
+        flags |= _lib.MS_FLAG_BWD_BF16X3
     return MsOptions(int(opts.tile), int(opts.wave_batch), float(opts.near_z), int(flags), int(opts.bin_tile))
 
 
@@ -87,11 +90,20 @@ def _check_map(m: dict):
     return n
 
 
+def _stamp(ws: torch.Tensor) -> int:
+    """Marks a new forward in workspace `ws` and returns its generation."""
+    gen = getattr(ws, "_ms_generation", 0) + 1
+    ws._ms_generation = gen
+    return gen
+
+
 class Job:
     """One render job: its map, pose, intrinsics, options and workspace.
 
     The workspace is a caller-owned uint8 tensor; the forward state stays in
-    it until the next forward on the same Job."""
+    it until the next forward in the same workspace, by this Job or another
+    one sharing it. backward() raises if such a forward has run since this
+    Job's forward (the state it would read is gone)."""
 
     def __init__(self, m: dict, viewmat: torch.Tensor, intr, opts: RenderOptions = RenderOptions(),
                  workspace: torch.Tensor | None = None):
@@ -114,6 +126,7 @@ class Job:
         if workspace is None or workspace.numel() < self.ws_bytes:
             workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=m["means"].device)
         self.ws = workspace
+        self._gen = None       # generation of this Job's last forward in self.ws
 
     # -- forward -----------------------------------------------------------
     def forward(self, out: tuple | None = None):
@@ -127,6 +140,7 @@ class Job:
             rgb, depth, sil = out
         imgs = MsImages(rgb.data_ptr(), depth.data_ptr(), sil.data_ptr())
         lib = _lib.load()
+        self._gen = _stamp(self.ws)
         check(lib.ms_forward(ref(self.c_map), _ptr(self.viewmat), ref(self.c_intr), ref(opts_struct(self.opts)),
                              _ptr(self.ws), self.ws_bytes, self.cap, ref(imgs), _stream_ptr(dev)))
         if self.opts.check:
@@ -151,6 +165,11 @@ class Job:
     # -- backward ----------------------------------------------------------
     def backward(self, g_rgb, g_depth, g_sil, map_grads: bool = True, pose_grads: bool = True,
                  out: dict | None = None) -> dict:
+        if self._gen is None:
+            raise RuntimeError("backward() needs a forward() on this Job first")
+        if getattr(self.ws, "_ms_generation", None) != self._gen:
+            raise RuntimeError("another forward has run in this Job's workspace since its forward(); the forward "
+                               "state the backward reads is gone (give each pending render its own workspace)")
         dev = self.m["means"].device
         flags = 0
         if not map_grads:
@@ -252,6 +271,7 @@ class BatchJob:
             self.c_jobs[j].viewmat = vm.data_ptr()
             self.c_jobs[j].intr = intr_struct(intr)
         self.ws = workspace
+        self._gen = None
         self._size_workspace()
 
     def _size_workspace(self):
@@ -275,6 +295,7 @@ class BatchJob:
         for j, (rgb, depth, sil) in enumerate(outs):
             self.c_jobs[j].out = MsImages(rgb.data_ptr(), depth.data_ptr(), sil.data_ptr())
         lib = _lib.load()
+        self._gen = _stamp(self.ws)
         check(lib.ms_forward_batch(len(self.maps), self.c_jobs, ref(opts_struct(self.opts)), _ptr(self.ws),
                                    self.ws_bytes, self.cap, _stream_ptr(self.device)))
         if self.opts.check:
@@ -297,6 +318,9 @@ class BatchJob:
         like that map; it is zeroed and every job with map gradients adds its
         gradients into it (MS_FLAG_ACCUMULATE_MAP_GRADS), so it ends up with
         their sum over the views."""
+        if self._gen is None or getattr(self.ws, "_ms_generation", None) != self._gen:
+            raise RuntimeError("backward() needs this batch's forward state, and another forward has run in its "
+                               "workspace since (or none has run)")
         k = len(self.maps)
         mg = [map_grads] * k if isinstance(map_grads, bool) else list(map_grads)
         pg = [pose_grads] * k if isinstance(pose_grads, bool) else list(pose_grads)
@@ -351,18 +375,38 @@ class RasterizeRGBD(torch.autograd.Function):
     def forward(ctx, means, scales, quats, opacity, colors, viewmat, intr, opts, holder):
         m = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
                  opacity=opacity.contiguous(), colors=colors.contiguous())
-        job = Job(m, viewmat.contiguous(), intr, opts, holder.get("workspace"))
+        vm = viewmat.contiguous()
+        # the holder keeps a pool of workspaces; one whose forward still awaits
+        # its backward is never handed out again (two renders before one
+        # backward, as in a multi-view mapping step, each get their own)
+        pool = holder.setdefault("pool", [])
+        free = [e for e in pool if not e["busy"]]
+        entry = free[0] if free else None
+        job = Job(m, vm, intr, opts, entry["ws"] if entry is not None else None)
+        if entry is None:
+            entry = {"ws": job.ws, "busy": False}
+            pool.append(entry)
+        entry["ws"] = job.ws
         holder["workspace"] = job.ws
         holder["job"] = job
         rgb, depth, sil = job.forward()
+        entry["ws"] = job.ws          # a checked forward may have grown it
+        if any(ctx.needs_input_grad[:6]):
+            entry["busy"] = True
         ctx.job = job
+        ctx.entry = entry
         ctx.needs = ctx.needs_input_grad
+        # saved so that autograd refuses a backward after an in-place update of
+        # the map or the pose
+        ctx.save_for_backward(m["means"], m["scales"], m["quats"], m["opacity"], m["colors"], vm)
         return rgb, depth, sil
 
     @staticmethod
     @torch.autograd.function.once_differentiable
     def backward(ctx, g_rgb, g_depth, g_sil):
+        ctx.saved_tensors              # version check of the map and pose tensors
         job = ctx.job
+        ctx.entry["busy"] = False
         H, W = job.intr.height, job.intr.width
         dev = job.m["means"].device
         z = lambda shp: torch.zeros(shp, dtype=torch.float32, device=dev)
@@ -381,8 +425,9 @@ class RasterizeRGBD(torch.autograd.Function):
 def render(m: dict, viewmat: torch.Tensor, intr, opts: RenderOptions = RenderOptions(), holder: dict | None = None):
     """Differentiable render of a map (dict of SoA tensors) from `viewmat`.
 
-    `holder` (optional dict) keeps the workspace across calls and receives the
-    Job under "job"."""
+    `holder` (optional dict) keeps workspaces across calls (a pool: a render
+    whose backward is still pending keeps its own) and receives the last Job
+    under "job"."""
     holder = {} if holder is None else holder
     return RasterizeRGBD.apply(m["means"], m["scales"], m["quats"], m["opacity"], m["colors"], viewmat, intr, opts,
                                holder)

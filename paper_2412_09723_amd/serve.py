@@ -138,8 +138,10 @@ class Server:
             for entry in list(inflight):
                 handle, reqs, nbytes, launched = entry
                 if self.executor.done(handle):
-                    fin = self.clock() - t0
+                    # collect() may re-run the round (capacity overflow); the
+                    # result is ready only when it returns
                     outs = self.executor.collect(handle)
+                    fin = self.clock() - t0
                     for k, r in enumerate(reqs):
                         done.append(Done(r.rid, r.agent, r.arrival, launched, fin, len(reqs),
                                          outs[k] if outs is not None else None))

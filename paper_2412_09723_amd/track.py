@@ -85,8 +85,15 @@ def ssim_loss_grad(pred: torch.Tensor, target: torch.Tensor, weight: float = 0.2
         grad = torch.empty_like(pred)
     elif grad.shape != pred.shape or grad.dtype != torch.float32 or not grad.is_contiguous():
         raise ValueError("grad must be a contiguous float32 tensor shaped like pred")
-    if loss is not None and (loss.dtype != torch.float32 or loss.numel() < 1 or not loss.is_cuda):
-        raise ValueError("loss must be a float32 device tensor")
+    for name, t in (("target", target), ("grad", grad)):
+        if t.device != pred.device:
+            raise ValueError(f"{name} is on device {t.device}, pred on device {pred.device}")
+    nbytes = pred.numel() * 4
+    for name, t in (("pred", pred), ("target", target)):
+        if grad.data_ptr() < t.data_ptr() + nbytes and t.data_ptr() < grad.data_ptr() + nbytes:
+            raise ValueError(f"grad overlaps {name}: neighbouring windows would read pixels already overwritten")
+    if loss is not None and (loss.dtype != torch.float32 or loss.numel() < 1 or loss.device != pred.device):
+        raise ValueError("loss must be a float32 tensor on pred's device")
     C, H, W = pred.shape
     lib = _lib.load()
     stream = ctypes.c_void_p(torch.cuda.current_stream(pred.device).cuda_stream)

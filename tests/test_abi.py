@@ -168,7 +168,9 @@ def test_prune_rejects_bad_arguments(lib):
 
 
 def test_ssim_loss_rejects_bad_arguments(lib):
-    def call(pred=FAKE, target=FAKE, C=3, W=64, H=48, weight=0.2, grad=FAKE + 64, acc=0):
+    n_bytes = 3 * 64 * 48 * 4
+
+    def call(pred=FAKE, target=FAKE + (1 << 24), C=3, W=64, H=48, weight=0.2, grad=FAKE + (2 << 24), acc=0):
         return lib.ms_ssim_loss_grad(ctypes.c_void_p(pred), ctypes.c_void_p(target), C, W, H, weight,
                                      ctypes.c_void_p(grad), acc, None, None)
     assert call(pred=0) == _lib.MS_ERR_INVALID_ARG
@@ -179,6 +181,12 @@ def test_ssim_loss_rejects_bad_arguments(lib):
     assert call(H=16385) == _lib.MS_ERR_INVALID_ARG
     assert call(weight=float("inf")) == _lib.MS_ERR_INVALID_ARG
     assert call(acc=2) == _lib.MS_ERR_INVALID_ARG
+    # the gradient may not overlap an input (halo reads of other workgroups)
+    assert call(grad=FAKE) == _lib.MS_ERR_INVALID_ARG
+    assert call(grad=FAKE + (1 << 24)) == _lib.MS_ERR_INVALID_ARG
+    assert call(grad=FAKE + n_bytes - 4) == _lib.MS_ERR_INVALID_ARG
+    assert call(grad=FAKE + (1 << 24) - n_bytes + 4) == _lib.MS_ERR_INVALID_ARG
+    assert "overlaps" in lib.ms_last_error().decode()
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -120,3 +120,57 @@ def test_autograd_requested_inputs_only():
     for k, _ in KINDS:
         assert torch.allclose(m_map[k].grad, m_all[k].grad, rtol=1e-4, atol=1e-9)
     assert torch.allclose(vm_pose.grad, vm_all.grad, rtol=1e-5, atol=1e-9)
+
+
+def test_holder_keeps_a_workspace_per_pending_backward():
+    """Two renders through one holder before their backward (the multi-view
+    mapping pattern): each keeps its own workspace, so both gradients equal
+    those of renders without a holder. A Job whose workspace another forward
+    has reused refuses its backward, and autograd refuses a backward after
+    an in-place update of the map."""
+    sc = scenes.small_frustum()
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    vms = [sc.viewmat, scenes.perturb_pose(sc.viewmat, scenes.rng_for(0, 0, salt=3))]
+    ups = [[t(u) for u in scenes.upstream_grads(sc.intr, scenes.rng_for(0, v, salt=2), 1.0, 0.5)]
+           for v in range(2)]
+
+    def grads(holder):
+        m = {k: t(getattr(sc, k)).requires_grad_(True) for k, _ in KINDS}
+        outs = []
+        for vm in vms:
+            outs.append(raster.render(m, t(vm), sc.intr, raster.RenderOptions(check=True), holder))
+        for o, u in zip(outs, ups):           # both forwards ran before either backward
+            torch.autograd.backward(list(o), u)
+        return {k: m[k].grad.clone() for k, _ in KINDS}
+
+    holder = {}
+    shared = grads(holder)
+    assert len(holder["pool"]) == 2 and not any(e["busy"] for e in holder["pool"])
+    alone = grads(None)
+    for k, _ in KINDS:
+        assert torch.allclose(shared[k], alone[k], rtol=1e-5, atol=1e-9), k
+    again = grads(holder)                     # the pool is reused, not grown
+    assert len(holder["pool"]) == 2
+    for k, _ in KINDS:
+        assert torch.allclose(again[k], alone[k], rtol=1e-5, atol=1e-9), k
+
+    # two Jobs on one workspace: the first one's state is gone
+    m = {k: t(getattr(sc, k)) for k, _ in KINDS}
+    a = raster.Job(m, t(vms[0]), sc.intr, raster.RenderOptions())
+    b = raster.Job(m, t(vms[1]), sc.intr, raster.RenderOptions(), workspace=a.ws)
+    a.forward()
+    b.forward()
+    with pytest.raises(RuntimeError, match="another forward"):
+        a.backward(*ups[0])
+    b.backward(*ups[1])
+
+    # in-place update of a map tensor between forward and backward
+    m = {k: t(getattr(sc, k)).requires_grad_(True) for k, _ in KINDS}
+    leaf = {k: v for k, v in m.items()}
+    mc = {k: v * 1.0 for k, v in leaf.items()}
+    outs = raster.render(mc, t(vms[0]), sc.intr)
+    with torch.no_grad():
+        mc["opacity"].mul_(0.5)
+    with pytest.raises(RuntimeError):
+        torch.autograd.backward(list(outs), ups[0])

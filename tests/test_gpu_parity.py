@@ -35,7 +35,8 @@ def _dev_grads(g):
     (8, 64, False, 0, None), (32, 32, False, 0, None), (8, 64, True, 0, None), (16, 64, True, 0, None),
     (32, 64, True, 0, None), (16, 64, False, 64, None), (16, 64, True, 128, None), (32, 64, False, 128, None),
     (8, 32, True, 32, None), (16, 64, False, 128, "mfma"), (8, 64, False, 0, "mfma"), (16, 64, True, 0, "mfma"),
-    (32, 64, False, 128, "mfma"), (32, 128, False, 0, "mfma")])
+    (32, 64, False, 128, "mfma"), (32, 128, False, 0, "mfma"), (16, 64, False, 128, "mfma_bf16x3"),
+    (8, 64, False, 0, "mfma_bf16x3")])
 def test_small_frustum_forward_backward(tile, wb, scalar, bin_tile, bwd):
     _log(f"small_frustum tile={tile} wb={wb} scalar={scalar} bin={bin_tile} bwd={bwd}")
     sc = scenes.small_frustum()
@@ -63,7 +64,7 @@ def test_rotated_pose_and_ragged_image():
     sc.means[2, 20:25] = 0.1          # behind the near plane
     for tile, scalar, bwd in ((8, False, None), (16, False, None), (32, False, None), (8, True, None),
                               (16, True, None), (32, True, None), (8, False, "mfma"), (16, False, "mfma"),
-                              (32, False, "mfma")):
+                              (32, False, "mfma"), (16, False, "mfma_bf16x3")):
         job, imgs = run_job(sc, tile=tile, wave_batch=32, scalar=scalar, bwd=bwd)
         check_structure(job, sc, tile)
         ref = oracle.forward(sc)
@@ -75,11 +76,15 @@ def test_rotated_pose_and_ragged_image():
 
 @pytest.mark.parametrize("scalar,tile,bin_tile,bwd", [(False, 16, 0, None), (True, 16, 0, None),
                                                      (False, 32, 128, None), (False, 16, 128, "mfma"),
-                                                     (False, 32, 128, "mfma"), (False, 32, 256, "mfma")])
+                                                     (False, 32, 128, "mfma"), (False, 32, 256, "mfma"),
+                                                     (False, 16, 128, "mfma_bf16x3")])
 def test_room_1m_full_size(scalar, tile, bin_tile, bwd):
     """1200x680, 1M Gaussians (the benchmark workload). Bin 0 (3225 bins)
     takes the global depth-sort path, bins of 128 the per-bin sort, and bins
-    of 256 hold up to 30k pairs each, beyond one block's in-LDS sort."""
+    of 256 hold up to 30k pairs each, beyond one block's in-LDS sort. The
+    upstream gradient carries a silhouette term, so the G_S T_final / (1 -
+    alpha) part of every composited Gaussian's gradient is exercised at full
+    size."""
     _log(f"room_view full size scalar={scalar} tile={tile} bin={bin_tile} bwd={bwd}")
     sc = scenes.room_view()
     job, imgs = run_job(sc, tile=tile, wave_batch=64, scalar=scalar, bin_tile=bin_tile, bwd=bwd)
@@ -87,7 +92,7 @@ def test_room_1m_full_size(scalar, tile, bin_tile, bwd):
     ref = oracle.forward(sc)
     errs, flagged = check_images(imgs, ref)
     _log(f"  image max rel err {errs}, flagged {flagged}")
-    up = _up(sc, 0.5, 0.0)
+    up = _up(sc, 0.5, 0.5)
     g = job.backward(*_dev_grads(up))
     torch.cuda.synchronize()
     worst = check_grads(g, oracle.backward(sc, *up))
@@ -180,13 +185,14 @@ def test_exact_depth_ties_keep_index_order(W, H, tile):
     check_grads(g, oracle.backward(sc, *up))
 
 
-@pytest.mark.parametrize("tile,wb", [(16, 64), (8, 32), (32, 128)])
-def test_needle_gaussians_grazing_sub_blocks(tile, wb):
+@pytest.mark.parametrize("tile,wb,bwd", [(16, 64, "mfma"), (8, 32, "mfma"), (32, 128, "mfma"),
+                                         (16, 64, "mfma_bf16x3")])
+def test_needle_gaussians_grazing_sub_blocks(tile, wb, bwd):
     """Thin, strongly anisotropic Gaussians at random orientations, with
     opacities down to the 1/255 cut-off: their acceptance ellipses cover a
     small part of their pixel boxes and graze many 8x8 sub-blocks, which is
     where the compositing kernels' record skipping must stay conservative."""
-    _log(f"needles tile {tile} wb {wb}")
+    _log(f"needles tile {tile} wb {wb} bwd {bwd}")
     intr = scenes.Intrinsics(160, 120, 150.0, 150.0, 80.0, 60.0)
     rng = scenes.rng_for(9, 321)
     sc = scenes.frustum_scene(2500, intr, rng, zmin=1.0, zmax=4.0)
@@ -195,7 +201,7 @@ def test_needle_gaussians_grazing_sub_blocks(tile, wb):
     sc.scales[:] = np.float32(0.0015)
     sc.scales[long_axis, np.arange(n)] = rng.uniform(0.05, 0.4, size=n).astype(np.float32)
     sc.opacity[:] = np.exp(rng.uniform(np.log(1.0 / 255.0), 0.0, size=n)).astype(np.float32)
-    job, imgs = run_job(sc, tile=tile, wave_batch=wb, bwd="mfma")
+    job, imgs = run_job(sc, tile=tile, wave_batch=wb, bwd=bwd)
     check_structure(job, sc, tile)
     errs, flagged = check_images(imgs, oracle.forward(sc))
     _log(f"  image max rel err {errs}, flagged {flagged}")

@@ -94,3 +94,23 @@ def test_ssim_optimum():
     # far below the scale of a gradient away from the optimum
     scale = WEIGHT / x.size
     assert np.abs(g).max() <= 1e-2 * scale, float(np.abs(g).max() / scale)
+
+
+def test_ssim_wrapper_rejects_misplaced_or_aliased_gradient():
+    """A gradient on the host or aliasing an input is refused before any
+    launch (the kernel would read a host pointer, or race with the halo
+    reads of neighbouring workgroups)."""
+    from paper_2412_09723_amd.track import ssim_loss_grad
+    x, y = _images(3, 30, 40, 21)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    with pytest.raises(ValueError, match="device"):
+        ssim_loss_grad(xd, yd, WEIGHT, grad=torch.empty_like(xd, device="cpu"))
+    with pytest.raises(ValueError, match="overlaps"):
+        ssim_loss_grad(xd, yd, WEIGHT, grad=xd)
+    with pytest.raises(ValueError, match="overlaps"):
+        ssim_loss_grad(xd, yd, WEIGHT, grad=yd)
+    big = torch.zeros(2 * xd.numel(), dtype=torch.float32, device="cuda")
+    big[:xd.numel()] = xd.reshape(-1)
+    pred = big[:xd.numel()].view_as(xd)
+    with pytest.raises(ValueError, match="overlaps"):
+        ssim_loss_grad(pred, yd, WEIGHT, grad=big[5:5 + xd.numel()].view_as(xd))

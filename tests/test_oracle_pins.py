@@ -252,6 +252,96 @@ def test_brute_force_matches_oracle(seed):
     assert np.abs(b["sil"] - f["sil"]).max() < 1e-12
 
 
+def _shaped(sc, kind, rng):
+    """Gives a scene's Gaussians one of the shapes that stress the recipe."""
+    n = sc.n
+    if kind == "needle":          # one axis 5 cm - 1 m, the others 1 mm
+        la = rng.integers(0, 3, n)
+        sc.scales[:] = np.float32(0.001)
+        sc.scales[la, np.arange(n)] = rng.uniform(0.05, 1.0, n).astype(np.float32)
+    elif kind == "anisotropic":   # axes log-uniform over two decades
+        sc.scales[:] = np.exp(rng.uniform(np.log(0.002), np.log(0.4), (3, n))).astype(np.float32)
+    elif kind == "faint":         # opacity within 5% of the 1/255 floor
+        sc.opacity[:] = ((1.0 / 255.0) * np.exp(rng.uniform(0.0, 0.05, n))).astype(np.float32)
+    if kind != "faint":
+        sc.opacity[:] = np.exp(rng.uniform(np.log(1.0 / 255.0), 0.0, n)).astype(np.float32)
+    return sc
+
+
+def _stress_scenes():
+    rng = np.random.default_rng(7)
+    out = []
+    for trial, kind in enumerate(["needle", "anisotropic", "faint", "plain"] * 3):
+        intr = scenes.Intrinsics(128, 96, 110.0, 115.0, 63.7, 47.2)
+        R0 = Rotation.from_euler("xyz", rng.uniform(-10, 10, 3), degrees=True).as_matrix()
+        vm = np.concatenate([R0, rng.uniform(-0.05, 0.05, (3, 1))], axis=1).reshape(12).astype(np.float32)
+        out.append((kind, _shaped(scenes.frustum_scene(80, intr, rng, viewmat=vm), kind, rng)))
+    return out
+
+
+def test_recipe_acceptance_equals_plain_definition():
+    """The pinned binary32 recipe (kappa-scaled Cholesky factors of the conic,
+    two fused multiply-adds, one cut-off min(4.5 log2 e, log2(255 o)) in
+    log2 space, the pinned log2, the pixel box) accepts exactly the pixels of
+    the plain definition -- d^2 <= 9 and o exp(-d^2/2) >= 1/255, with d^2
+    from numpy's inverse of J R Sigma R^T J^T + 0.3 I and Sigma from scipy's
+    rotation, in binary64 -- for rotated, anisotropic, needle-like and faint
+    Gaussians. Pixels whose plain decision lies within brute.PLAIN_MARGIN
+    (1e-5, relative) of either threshold are left out and counted. A recipe
+    with a 1/256 floor instead of 1/255 is caught on the faint Gaussians."""
+    accepted = excluded = disagree = planted = 0
+    for kind, sc in _stress_scenes():
+        pins, cont = brute.pinned(sc), brute.continuous(sc)
+        H, W = sc.intr.height, sc.intr.width
+        ys, xs = np.mgrid[0:H, 0:W]
+        for i in range(sc.n):
+            r = pins[i]
+            if not r["visible"]:
+                continue
+            acc, amb = brute.plain_accept(cont[i], float(sc.opacity[i]), xs, ys)
+            q = brute.pinned_q(r, xs, ys)
+            inbox = (xs >= r["xlo"]) & (xs <= r["xhi"]) & (ys >= r["ylo"]) & (ys <= r["yhi"])
+            rec = (q <= r["qcut"]) & inbox
+            accepted += int(acc.sum())
+            excluded += int(amb.sum())
+            disagree += int(((rec != acc) & ~amb).sum())
+            if kind == "faint":
+                o = float(sc.opacity[i])
+                wrong = np.float32(min(brute.Q9, brute.pinned_log2(256.0 * o)))
+                planted += int((((q <= wrong) & inbox) != acc).sum())
+    assert accepted > 50_000
+    assert disagree == 0
+    assert excluded <= 1e-3 * accepted, (excluded, accepted)
+    assert planted > 10, planted
+
+
+@pytest.mark.parametrize("seed,kind", [(0, "plain"), (1, "plain"), (2, "plain"), (3, "plain"),
+                                       (4, "needle"), (5, "anisotropic"), (6, "faint")])
+def test_plain_definition_brute_force_matches_oracle(seed, kind):
+    """Numpy brute force with nothing of the recipe -- binary64 acceptance
+    d^2 <= 9 and o exp(-d^2/2) >= 1/255, candidates in binary64 depth order --
+    against the oracle, on pixels where no decision lies within the margins
+    (brute.PLAIN_MARGIN for acceptance, the oracle's flags for the stop and
+    the clamp)."""
+    pose = None
+    if seed >= 2:
+        R0 = Rotation.from_euler("xyz", [8 * seed, -5, 3], degrees=True).as_matrix()
+        pose = np.concatenate([R0, np.array([[0.05], [-0.1], [0.2]])], axis=1).reshape(12).astype(np.float32)
+    sc = tiny_scene(seed, pose=pose)
+    _shaped(sc, kind, np.random.default_rng(seed))
+    if seed == 1:       # push a few Gaussians off-screen and one behind the near plane
+        sc.means[0, :6] *= 3.0
+        sc.means[2, 7] = 0.1
+    b = brute.render(sc, acceptance="plain")
+    f = oracle.forward(sc)
+    ok = ~b["ambiguous"] & ((f["flags"] & 1) == 0)
+    assert ok.mean() > 0.98, ok.mean()
+    assert np.array_equal(b["ncomp"][ok], f["ncomp"][ok])
+    assert np.abs(b["rgb"] - f["rgb"])[:, ok].max() < 1e-12
+    assert np.abs(b["depth"] - f["depth"])[ok].max() < 1e-12
+    assert np.abs(b["sil"] - f["sil"])[ok].max() < 1e-12
+
+
 def test_pixel_box_contains_every_accepted_pixel():
     """The binary32 test q <= qcut can only accept pixels inside the pixel
     box (the box has a 2^-8 margin over 3 sigma), so skipping pixels outside
@@ -456,3 +546,34 @@ def test_culled_gaussians_get_zero_gradient():
     for k in ("means", "scales", "quats", "colors"):
         assert not out[k][:, :10].any()
     assert not out["opacity"][:10].any()
+
+
+# ----------------------------------------------------------- pose update
+
+def test_apply_twist_equals_matrix_exponential():
+    """oracle.apply_twist (the checker of the device pose update) is the
+    left perturbation exp(xi^) [R|t] of Sec. 3.1's SE(3) pose: it equals
+    scipy's matrix exponential of the 4x4 twist matrix [[phi^, rho], [0, 0]]
+    at finite rotation angles from 1e-3 to 0.5 rad, to 1e-12. A wrong
+    translation Jacobian V (for instance the identity) would be off by about
+    |phi| |rho| / 2, far outside."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(11)
+    hat = lambda w: np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    worst = 0.0
+    for th in (1e-3, 1e-2, 0.1, 0.3, 0.5):
+        for _ in range(6):
+            axis = rng.standard_normal(3)
+            phi = th * axis / np.linalg.norm(axis)
+            rho = rng.uniform(-0.2, 0.2, 3)
+            X = np.zeros((4, 4))
+            X[:3, :3] = hat(phi)
+            X[:3, 3] = rho
+            R0 = Rotation.random(random_state=int(rng.integers(1 << 30))).as_matrix()
+            P = np.eye(4)
+            P[:3, :3] = R0
+            P[:3, 3] = rng.uniform(-2.0, 2.0, 3)
+            want = (expm(X) @ P)[:3].reshape(12)
+            got = oracle.apply_twist(P[:3].reshape(12), np.concatenate([rho, phi]))
+            worst = max(worst, float(np.abs(got - want).max()))
+    assert worst <= 1e-12, worst

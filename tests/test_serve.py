@@ -29,8 +29,9 @@ class SimExecutor:
     run concurrently (as on separate streams). Requests of agent `bad` make
     the launch raise, as an invalid job does."""
 
-    def __init__(self, clock, fixed=1e-3, per_job=5e-4, bad=None, cost=lambda r: 100):
+    def __init__(self, clock, fixed=1e-3, per_job=5e-4, bad=None, cost=lambda r: 100, rerun=0.0):
         self.clock, self.fixed, self.per_job, self.bad, self._cost = clock, fixed, per_job, bad, cost
+        self.rerun = rerun      # seconds a collect spends redoing the round (a capacity overflow)
         self.launches = []
         self.live = 0
         self.max_live = 0
@@ -51,6 +52,8 @@ class SimExecutor:
 
     def collect(self, h):
         self.live -= 1
+        if self.rerun:
+            self.clock.t += self.rerun
         return [dict(rid=r.rid) for r in h["reqs"]]
 
 
@@ -175,3 +178,14 @@ def test_poisson_trace_is_reproducible_and_poisson():
         assert [e[2] for e in a if e[1] == k] == list(range(per_agent[k]))
     reqs = requests_from_trace(a)
     assert [r.rid for r in reqs] == list(range(len(a))) and reqs[3].arrival == a[3][0]
+
+
+def test_latency_includes_a_round_that_collect_reruns():
+    """A round whose collect redoes the work (capacity overflow: a checked
+    forward and the backward again) finishes when collect returns; the
+    latency of its requests includes the re-run."""
+    reqs = [Request(0, 0, 0.0, 0, True)]
+    _, base, _, _ = _run(reqs)
+    _, slow, _, _ = _run(reqs, rerun=5e-3)
+    lat = lambda d: d[0].finished - d[0].arrival
+    assert lat(slow) >= lat(base) + 5e-3 - 1e-9
