@@ -345,6 +345,23 @@ size_t ms_prune_workspace_bytes(int64_t n);
 int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
                  void* workspace, size_t ws_bytes, void* stream);
 
+/* ms_prune for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and results, with the scratch in a static device
+ * array of the library instead of a workspace. Maps of at most
+ * MS_PRUNE_NOALLOC_MAX_N Gaussians (2^26); larger n returns
+ * MS_ERR_INVALID_ARG and enqueues nothing. The array (256 KB) is held on
+ * each GPU the library runs on until the process ends; its device address
+ * is looked up on the first call on a device (the current device, which
+ * must be the device of `stream`, else MS_ERR_INVALID_ARG). It allocates
+ * nothing (no hipMalloc, hipFree or allocating library call). Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller. Other arguments and errors as ms_prune. */
+#define MS_PRUNE_NOALLOC_MAX_N (1LL << 26)
+int32_t ms_prune_noalloc(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
+                         void* stream);
+
 /* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
  * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
  * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]

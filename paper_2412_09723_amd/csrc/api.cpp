@@ -670,8 +670,9 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
 
 size_t ms_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
 
-int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
-                 void* workspace, size_t ws_bytes, void* stream) {
+namespace {
+// Host checks shared by ms_prune and ms_prune_noalloc.
+int32_t check_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, const int64_t* kept) {
   int32_t s = check_map(in);
   if (s != MS_OK) return s;
   if (in->n < 0) return fail(MS_ERR_INVALID_ARG, "n = %lld < 0", (long long)in->n);
@@ -686,9 +687,41 @@ int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const 
       if (ia[u] == oa[v]) return fail(MS_ERR_INVALID_ARG, "output array aliases an input array");
   if (!std::isfinite(tau_o) || !std::isfinite(tau_s) || !std::isfinite(tau_e) || tau_e < 0.f)
     return fail(MS_ERR_INVALID_ARG, "thresholds must be finite and tau_e >= 0");
+  return MS_OK;
+}
+}  // namespace
+
+int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
+                 void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_prune(in, tau_o, tau_s, tau_e, out, kept);
+  if (s != MS_OK) return s;
   if (!workspace) return fail(MS_ERR_WORKSPACE, "null workspace");
   if (ws_bytes < prune_workspace_bytes(in->n)) return fail(MS_ERR_WORKSPACE, "workspace too small");
   hipError_t e = launch_prune(*in, *out, tau_o, tau_s, tau_e, kept, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "prune");
+  return MS_OK;
+}
+
+int32_t ms_prune_noalloc(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
+                         void* stream) {
+  int32_t s = check_prune(in, tau_o, tau_s, tau_e, out, kept);
+  if (s != MS_OK) return s;
+  if (in->n > kPruneNoAllocMaxN)
+    return fail(MS_ERR_INVALID_ARG, "n = %lld exceeds the %lld Gaussians of the static scratch", (long long)in->n,
+                (long long)kPruneNoAllocMaxN);
+  hipStream_t st = (hipStream_t)stream;
+  if (st) {   // the scratch is the current device's copy: the stream must run there
+    int cur = 0;
+    hipDevice_t sdev = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess) e = hipStreamGetDevice(st, &sdev);
+    if (e != hipSuccess) return hip_fail(e, "prune (device of the stream)");
+    if ((int)sdev != cur) return fail(MS_ERR_INVALID_ARG, "stream on device %d, current device %d", (int)sdev, cur);
+  }
+  uint32_t* ws = nullptr;
+  hipError_t e = prune_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "prune scratch address");
+  e = launch_prune(*in, *out, tau_o, tau_s, tau_e, kept, ws, st);
   if (e != hipSuccess) return hip_fail(e, "prune");
   return MS_OK;
 }

@@ -216,6 +216,8 @@ hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st);
 // Map pruning (prune.hip): scratch bytes for n Gaussians, and the three
 // launches writing the survivors into `out` (row stride *kept) and *kept.
 size_t prune_workspace_bytes(int64_t n);
+constexpr int64_t kPruneNoAllocMaxN = int64_t(1) << 26;   // largest map of ms_prune_noalloc
+hipError_t prune_scratch(uint32_t** out);
 hipError_t launch_prune(const ms_map& in, const ms_map& out, float tau_o, float tau_s, float tau_e, int64_t* kept,
                         void* ws, hipStream_t st);
 hipError_t launch_pose_adam(float* viewmat, const float* g, float* state, float lr, float b1, float b2, float eps,

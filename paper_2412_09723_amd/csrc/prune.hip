@@ -13,6 +13,8 @@
 //      their 14 floats.
 #include "ms_internal.h"
 
+#include <mutex>
+
 namespace ms {
 namespace {
 
@@ -144,6 +146,41 @@ __global__ void __launch_bounds__(kPruneThreads) k_prune_scatter(PruneArgs A, co
 }
 
 }  // namespace
+
+// Scratch of the allocation-free entry point (ms_prune_noalloc): one survivor
+// count per block of kPruneSlots Gaussians, for maps of up to
+// kPruneNoAllocMaxN Gaussians (256 KB). Every GPU the library runs on holds
+// its own copy until the process ends. In host code `scratch` names a host
+// stand-in, not the device copy: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr int64_t kPruneNoAllocBlocks = kPruneNoAllocMaxN / kPruneSlots;
+static_assert(kPruneNoAllocMaxN % kPruneSlots == 0, "whole blocks");
+static __device__ __align__(256) uint32_t scratch[kPruneNoAllocBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, once looked up
+}  // namespace
+
+// The device address of `scratch` on the current device (looked up on the
+// first call on that device, with it current).
+hipError_t prune_scratch(uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 size_t prune_workspace_bytes(int64_t n) {
   const int64_t blocks = n > 0 ? (n + kPruneSlots - 1) / kPruneSlots : 1;

@@ -227,3 +227,25 @@ def test_batch_rejects_bad_arguments(lib):
     # backward: a job that wants map gradients needs the arrays
     assert lib.ms_backward_batch(2, jobs, ref(OPTS), ctypes.c_void_p(FAKE), 1 << 40, 1 << 20, None) \
         == _lib.MS_ERR_INVALID_ARG
+
+
+def test_prune_noalloc_rejects_bad_arguments(lib):
+    """The allocation-free pruning call takes ms_prune's host checks, and
+    refuses maps beyond its static scratch before touching the device."""
+    m = MsMap(4096, FAKE, FAKE + 0x100000, FAKE + 0x200000, FAKE + 0x300000, FAKE + 0x400000)
+    out = MsMap(4096, FAKE + 0x500000, FAKE + 0x600000, FAKE + 0x700000, FAKE + 0x800000, FAKE + 0x900000)
+    kept = ctypes.c_void_p(FAKE + 0xA00000)
+
+    def call(src=m, dst=out, to=0.005, ts=0.25, te=10.0, k=kept):
+        return lib.ms_prune_noalloc(ref(src) if src is not None else None, to, ts, te,
+                                    ref(dst) if dst is not None else None, k, None)
+    assert call(src=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(dst=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(k=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(dst=MsMap(4096, out.means, out.scales, m.quats, out.opacity, out.colors)) == _lib.MS_ERR_INVALID_ARG
+    assert call(te=-1.0) == _lib.MS_ERR_INVALID_ARG
+    big = (1 << 26) + 1
+    fields = ("means", "scales", "quats", "opacity", "colors")
+    assert call(src=MsMap(big, *[getattr(m, f) for f in fields]),
+                dst=MsMap(big, *[getattr(out, f) for f in fields])) == _lib.MS_ERR_INVALID_ARG
+    assert "static scratch" in lib.ms_last_error().decode()
