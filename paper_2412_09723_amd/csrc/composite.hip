@@ -84,33 +84,52 @@ __device__ inline bool ellipse_reaches(const uint4& ctr, const uint4& con, int X
   return __builtin_fmaf(r1, r1, r2 * r2) <= qc * (1.f + kEps);
 }
 
-// Packs the bin-list entries at list positions [lo, lo + n) (n <= 64) that
-// can composite in the 8x8 sub-block at (X0, Y0) into dst[0 ..), in list
-// order, and returns how many there are (wave-uniform). Lane j reads pair
-// word j (coalesced); the records are then read four lanes per 64-byte
-// record, so each load instruction covers 16 whole records rather than 64
-// scattered 16-byte pieces. Lane j first tests record j's acceptance ellipse
-// against the sub-block (ellipse_reaches, one record per lane); the quad's
-// last lane then holds the record's pixel box, a record is packed when the
-// box meets the sub-block and the ellipse test held, and a ballot plus a
-// masked bit count gives each packed record its slot.
-__device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
-                                  uint32_t rank_mask, uint32_t start, uint32_t lo, int n, int X0, int Y0, int lane,
-                                  Staged* __restrict__ dst) {
-  const uint32_t rank = lane < n ? (pval[start + lo + (uint32_t)lane] & rank_mask) : 0u;
-  bool reach = false;
-  if (lane < n) reach = ellipse_reaches(rec[4 * (int64_t)rank], rec[4 * (int64_t)rank + 1], X0, Y0);
-  const uint64_t rm = __builtin_amdgcn_ballot_w64(reach);
+// The pair words of one chunk of a bin list, one per lane and 64-entry
+// round: lane j of round h holds the word of list position lo + 64 h + j, 0
+// past the chunk. Loaded one chunk ahead, so that staging the next chunk
+// waits for its records only.
+template <int WB>
+struct PairWords {
+  uint32_t w[(WB + 63) / 64];
+};
+
+template <int WB>
+__device__ inline PairWords<WB> load_pair_words(const uint32_t* __restrict__ pval, uint32_t base, int nb, int lane) {
+  PairWords<WB> pw;
+#pragma unroll
+  for (int h = 0; h < (WB + 63) / 64; h++) {
+    const int j = 64 * h + lane;
+    pw.w[h] = j < nb ? pval[base + (uint32_t)j] : 0u;
+  }
+  return pw;
+}
+
+// Packs the bin-list entries at list positions [lo, lo + n) (1 <= n <= 64),
+// whose pair words lane j holds in `pw`, that can composite in the 8x8
+// sub-block at (X0, Y0) into dst[0 ..), in list order, and returns how many
+// there are (wave-uniform). Every record load is issued at once: lane j
+// reads the centre and conic words of record j for the ellipse test, and a
+// lane quad reads each 64-byte record with one 16-byte load per lane (each
+// load instruction covers 16 whole records); lanes past n read list entry
+// 0's record instead, which is never packed. A record is packed when its
+// pixel box meets the sub-block and its ellipse can reach a pixel of it; a
+// ballot plus a masked bit count gives each packed record its slot.
+__device__ inline int stage_chunk(const uint4* __restrict__ rec, uint32_t pw, uint32_t rank_mask, uint32_t lo, int n,
+                                  int X0, int Y0, int lane, Staged* __restrict__ dst) {
+  const uint32_t rank = pw & rank_mask;
+  const uint32_t r0 = __builtin_amdgcn_readfirstlane(rank);   // entry 0 (n >= 1): a valid record
+  const uint32_t rs = lane < n ? rank : r0;
+  const uint4 ctr = rec[4 * (int64_t)rs], con = rec[4 * (int64_t)rs + 1];
   const int part = lane & 3, sub = lane >> 2;
   uint4 v[4];
   uint32_t rk[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int e = 16 * k + sub;
-    rk[k] = (uint32_t)__shfl((int)rank, e, 64);
-    v[k] = make_uint4(0u, 0u, 0u, 0u);
-    if (e < n) v[k] = rec[4 * (int64_t)rk[k] + part];
+    rk[k] = (uint32_t)__shfl((int)rs, 16 * k + sub, 64);
+    v[k] = rec[4 * (int64_t)rk[k] + part];
   }
+  const bool reach = lane < n && ellipse_reaches(ctr, con, X0, Y0);
+  const uint64_t rm = __builtin_amdgcn_ballot_w64(reach);
   int base = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
@@ -145,20 +164,20 @@ __device__ inline int stage_chunk(const uint4* __restrict__ rec, const uint32_t*
   return base;
 }
 
-// Packs a chunk of up to WB entries (WB / 64 rounds of stage_chunk) and pads
-// the packed count to a multiple of `group` with inert entries; returns the
-// padded count.
+// Packs a chunk of nb <= WB entries at list positions [lo, lo + nb) (WB / 64
+// rounds of stage_chunk) and pads the packed count to a multiple of `group`
+// with inert entries; returns the padded count.
 template <int WB>
-__device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval,
-                                         uint32_t rank_mask, uint32_t start, uint32_t lo, int nb, int X0, int Y0,
-                                         int lane, Staged* __restrict__ dst, int group, int& packed) {
+__device__ inline int stage_chunk_padded(const uint4* __restrict__ rec, const PairWords<WB>& pw, uint32_t rank_mask,
+                                         uint32_t lo, int nb, int X0, int Y0, int lane, Staged* __restrict__ dst,
+                                         int group, int& packed) {
   int cnt = 0;
 #pragma unroll
-  for (int h = 0; h < WB; h += 64) {
-    const int n = nb - h;
+  for (int h = 0; h < (WB + 63) / 64; h++) {
+    const int n = nb - 64 * h;
     if (n > 0)
-      cnt += stage_chunk(rec, pval, rank_mask, start, lo + (uint32_t)h, n < 64 ? n : 64, X0, Y0, lane,
-                                  dst + cnt);
+      cnt += stage_chunk(rec, pw.w[h], rank_mask, lo + (uint32_t)(64 * h), n < 64 ? n : 64, X0, Y0, lane,
+                         dst + cnt);
   }
   const int padded = (cnt + group - 1) / group * group;
   if (lane < padded - cnt) dst[cnt + lane] = inert_entry();
@@ -219,15 +238,17 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
   uint32_t lastpos = 0u, ncomp = 0u, staged = 0u;
   bool done = !inside;
   Staged* my = stage[wave];
+  PairWords<WB> pw = load_pair_words<WB>(pval, start, (int)min((uint32_t)WB, end - start), lane);
   for (uint32_t b0 = start; b0 < end; b0 += WB) {
     if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
     const int nb = (int)min((uint32_t)WB, end - b0);
     staged += (uint32_t)nb;
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<WB>(rec, pval, rank_mask, start, b0 - start, nb, X0, Y0, lane, my, kFwdGroup,
-                                           packed);
+    const int cnt = stage_chunk_padded<WB>(rec, pw, rank_mask, b0 - start, nb, X0, Y0, lane, my, kFwdGroup, packed);
     wave_sync();
+    if (b0 + WB < end)   // uniform: the next chunk's pair words, while this one composites
+      pw = load_pair_words<WB>(pval, b0 + WB, (int)min((uint32_t)WB, end - (b0 + WB)), lane);
     for (int g = 0; g < cnt; g += kFwdGroup) {
       // acceptance values and alphas of the group: independent of each other
       float al[kFwdGroup];
@@ -493,13 +514,17 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   float T = Tf;      // transmittance after the current entry
   float R = 0.f;     // suffix sum of (G . c + G_D z) alpha T over later entries
   Staged* my = stage[wave];
+  PairWords<WB> pw = load_pair_words<WB>(pval, start + (Lmax > (uint32_t)WB ? Lmax - WB : 0u),
+                                         (int)min(Lmax, (uint32_t)WB), lane);
   for (uint32_t hi = Lmax; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)WB ? hi - WB : 0u;
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    stage_chunk_padded<WB>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my, 1, packed);
+    stage_chunk_padded<WB>(rec, pw, rank_mask, lo, nb, X0, Y0, lane, my, 1, packed);
     wave_sync();
+    if (lo > 0)   // uniform: the next (earlier) chunk's pair words
+      pw = load_pair_words<WB>(pval, start + (lo > (uint32_t)WB ? lo - WB : 0u), (int)min(lo, (uint32_t)WB), lane);
     for (int j = packed - 1; j >= 0; j--) {
       const Staged s = my[j];
       const uint32_t pos1 = __float_as_uint(s.misc.z);   // list position + 1
@@ -884,14 +909,18 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     }
     wave_sync();   // the next rows of A overwrite Fg
   };
+  PairWords<kBwdChunk> pw = load_pair_words<kBwdChunk>(
+      pval, start + (Lmax > (uint32_t)kBwdChunk ? Lmax - kBwdChunk : 0u), (int)min(Lmax, (uint32_t)kBwdChunk), lane);
   for (uint32_t hi = Lmax; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
-                                                   kBwdStep, packed);
+    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pw, rank_mask, lo, nb, X0, Y0, lane, my, kBwdStep, packed);
     wave_sync();
+    if (lo > 0)   // uniform: the next (earlier) chunk's pair words, while this one is reduced
+      pw = load_pair_words<kBwdChunk>(pval, start + (lo > (uint32_t)kBwdChunk ? lo - kBwdChunk : 0u),
+                                      (int)min(lo, (uint32_t)kBwdChunk), lane);
     reduced += (uint32_t)packed;
     int rows = 0;   // uniform: rows of A filled since the last product
     for (int top = cnt - 1; top >= 0; top -= kBwdStep) {   // cnt is a multiple of kBwdStep
@@ -1193,14 +1222,18 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     }
     wave_sync();   // the next columns overwrite Fg
   };
+  PairWords<kBwdChunk> pw = load_pair_words<kBwdChunk>(
+      pval, start + (Lmax > (uint32_t)kBwdChunk ? Lmax - kBwdChunk : 0u), (int)min(Lmax, (uint32_t)kBwdChunk), lane);
   for (uint32_t hi = Lmax; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBwdChunk ? hi - kBwdChunk : 0u;
     const int nb = (int)(hi - lo);
     wave_sync();
     int packed;
-    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pval, rank_mask, start, lo, nb, X0, Y0, lane, my,
-                                                   kBwdStep, packed);
+    const int cnt = stage_chunk_padded<kBwdChunk>(rec, pw, rank_mask, lo, nb, X0, Y0, lane, my, kBwdStep, packed);
     wave_sync();
+    if (lo > 0)   // uniform: the next (earlier) chunk's pair words, while this one is reduced
+      pw = load_pair_words<kBwdChunk>(pval, start + (lo > (uint32_t)kBwdChunk ? lo - kBwdChunk : 0u),
+                                      (int)min(lo, (uint32_t)kBwdChunk), lane);
     reduced += (uint32_t)packed;
     int rows = 0;   // uniform: entries with columns since the last product
     for (int top = cnt - 1; top >= 0; top -= kBwdStep) {   // cnt is a multiple of kBwdStep
