@@ -14,6 +14,7 @@ oracle's throughput on a bounded sample of the same frame.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -31,6 +32,64 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Algorithmic floating-point work per composited (pixel, Gaussian) pair,
 # counting an FMA as two flops and a transcendental as one.
 FLOPS_PER_PAIR = {"composite": 27, "composite_bwd": 52}
+
+
+ARITHMETIC = {
+    "mfma": "binary32 throughout; the backward's per-Gaussian pixel sums on v_mfma_f32_16x16x4_f32 "
+            "(fp32 operands and accumulation)",
+    "mfma_bf16x3": "binary32, except the backward's per-Gaussian pixel sums: v_mfma_f32_16x16x32_bf16 on bf16 "
+                   "high/low parts of the per-pixel values (hi*hi + hi*lo + lo*hi, about 16 significant bits per "
+                   "term), accumulated in fp32",
+    "lds": "binary32 throughout (wave reductions)",
+    "scalar": "binary32 throughout (wave reductions)",
+}
+
+
+def kernel_names(args) -> dict:
+    t, wb = args.tile, args.wave_batch
+    fwd = f"k_composite_fwd_s<{t}>" if args.fwd_records == "scalar" else f"k_composite_fwd<{t}, {wb}>"
+    bwd = {"mfma": f"k_composite_bwd_f<{t}>", "mfma_bf16x3": f"k_composite_bwd_m<{t}>",
+           "lds": f"k_composite_bwd<{t}, {wb}>", "scalar": f"k_composite_bwd_s<{t}>"}[args.bwd_records]
+    return {"project": "k_project_fwd", "bin_count": "k_unit_count + k_unit_scan", "bin_emit": "k_unit_emit",
+            "bin_sort": "k_bin_sort", "composite": fwd, "composite_bwd": bwd, "project_bwd": "k_project_bwd",
+            "pose": "k_pose_final", "loss": "k_l1_grad", "pose_step": "k_pose_adam"}
+
+
+def kernel_table(stage_ms: dict, names: dict, N: int, Nv: int, K: int, P: int, pairs: int) -> dict:
+    """Each kernel of the tracking iteration: live HIP-event time per launch
+    (one profiled step) against its roofline. Streaming kernels carry their
+    algorithmic HBM bytes per launch, the compositing kernels their
+    algorithmic flops."""
+    bytes_of = {
+        "project": (68 * N + 104 * Nv, "56 B of parameters read + 4 B depth key + 8 B pixel footprint written per "
+                                       "Gaussian; 64 B record + 40 B zeroed accumulator row per visible"),
+        "bin_count": (8 * N, "8 B pixel footprint read per Gaussian"),
+        "bin_emit": (12 * N + 8 * K, "8 B footprint + 4 B depth key read per Gaussian; 8 B (key, index) written per "
+                                     "pair"),
+        "bin_sort": (16 * K, "8 B per pair read and written once"),
+        "project_bwd": (60 * N + 96 * Nv, "4 B key read + 56 B gradients written per Gaussian; 40 B accumulator row "
+                                          "+ 56 B parameters read per visible"),
+        "loss": (60 * P, "5 planes x (prediction, target read + gradient written) x 4 B per pixel"),
+    }
+    out = {}
+    pose_ms = stage_ms.get("pose", 0.0)
+    for k, name in names.items():
+        ms = stage_ms.get(k, 0.0)
+        if k == "project_bwd":
+            ms = max(ms - pose_ms, 0.0)     # the stage includes the pose fold
+        if ms <= 0:
+            continue
+        row = {"kernel": name, "us": round(ms * 1e3, 2)}
+        if k in bytes_of:
+            nb, what = bytes_of[k]
+            row.update(bytes=nb, bytes_are=what, GB_s=round(nb / (ms * 1e-3) / 1e9, 1),
+                       hbm_frac=round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        elif k in ("composite", "composite_bwd"):
+            fl = FLOPS_PER_PAIR[k] * pairs
+            row.update(flops=fl, TFLOP_s=round(fl / (ms * 1e-3) / 1e12, 2),
+                       alu_frac=round(fl / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4))
+        out[k] = row
+    return out
 
 
 def parse():
@@ -56,6 +115,7 @@ def parse():
     ap.add_argument("--no-ssim", action="store_true", help="skip the SSIM loss measurement")
     ap.add_argument("--no-views", action="store_true", help="skip the one-map multi-view mapping measurement")
     ap.add_argument("--no-prune", action="store_true", help="skip the map-pruning measurement")
+    ap.add_argument("--no-alt", action="store_true", help="skip the bf16x3-backward comparison step")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
     ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
@@ -90,30 +150,95 @@ def read_traffic(kernel_stage: str):
     return d.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(scene, up, threads: int, target_s: float, max_reps: int = 1000):
+    """Forward + backward passes of the oracle (unchanged) on `threads` OpenMP
+    threads, repeated until about target_s seconds (at least one pass)."""
+    import oracle
+    reps, t0, fwd = 0, time.perf_counter(), None
+    while True:
+        fwd = oracle.forward(scene, nthreads=threads)
+        oracle.backward(scene, *up, nthreads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or el / reps * (reps + 1) > 2.0 * target_s or reps >= max_reps:
+            break
+    return scene.intr.pixels * reps / el / 1e6, reps, el, fwd
+
+
 def cpu_baseline(scene, target_s: float):
-    """The oracle (unchanged) on the same frame: forward + backward passes
-    repeated until about `target_s` seconds of work."""
-    import numpy as np
+    """The oracle (unchanged) on the host cores, on the benchmark frame
+    (1200x680, 1M-Gaussian room) and on the small 160x120 / 4,096-Gaussian
+    frame: once on every core of this process's affinity set and once on one
+    core, each a bounded sample of forward + backward passes."""
     import oracle
     from paper_2412_09723_amd import scenes
     cores = len(os.sched_getaffinity(0))
-    up = scenes.upstream_grads(scene.intr, scenes.rng_for(1, 0, salt=2), 0.5, 0.0)
     oracle.load()
-    reps, t0 = 0, time.perf_counter()
-    fwd = None
-    while True:
-        fwd = oracle.forward(scene, nthreads=cores)
-        oracle.backward(scene, *up, nthreads=cores)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or el / reps * (reps + 1) > 2.5 * target_s:
-            break
-    px = scene.intr.pixels * reps
-    return {"value": px / el / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} forward+backward passes of the 1200x680 frame of the 1M-Gaussian room "
-                      f"({el:.1f} s, OpenMP over {cores} threads)",
+    up1 = scenes.upstream_grads(scene.intr, scenes.rng_for(1, 0, salt=2), 0.5, 0.0)
+    small = scenes.small_frustum()
+    up0 = scenes.upstream_grads(small.intr, scenes.rng_for(0, 0, salt=2), 1.0, 0.0)
+    v_all, r_all, e_all, fwd = _oracle_rate(scene, up1, cores, target_s)
+    v_one, r_one, e_one, _ = _oracle_rate(scene, up1, 1, 0.0, max_reps=1)
+    s_all = _oracle_rate(small, up0, cores, 1.5)
+    s_one = _oracle_rate(small, up0, 1, 1.5)
+    return {"value": round(v_all, 4), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"{r_all} forward+backward passes of the 1200x680 frame of the 1M-Gaussian room "
+                      f"({e_all:.1f} s, OpenMP over {cores} threads)",
+            "cpu_model": cpu_model(),
+            "single_core": {"value": round(v_one, 4), "unit": "Mpix/s", "cores": 1,
+                            "sample": f"{r_one} forward+backward pass of the same frame ({e_one:.1f} s)"},
+            "small_frame": {"workload": "160x120, 4,096 Gaussians in the frustum at 1-5 m",
+                            "all_cores": {"value": round(s_all[0], 4), "cores": cores, "passes": s_all[1],
+                                          "seconds": round(s_all[2], 2)},
+                            "single_core": {"value": round(s_one[0], 4), "cores": 1, "passes": s_one[1],
+                                            "seconds": round(s_one[2], 2)}},
             "counters": {"visible": int(fwd["counters"][0]), "evaluated": int(fwd["counters"][1]),
                          "accepted": int(fwd["counters"][2]), "composited": int(fwd["counters"][3])}}
+
+
+def staged_entries_per_tile(state: dict, scene, tile: int) -> int:
+    """K_r: list entries that a compositing tile of tile x tile pixels must
+    stage, summed over tiles -- the Gaussians of the tile's own list (box
+    meets the tile) up to the deepest one composited at any of its pixels.
+    Counted from the forward state: bin lists, records (pixel boxes) and the
+    per-pixel last composited position."""
+    import numpy as np
+    H, W = scene.intr.height, scene.intr.width
+    last = state["last"].cpu().numpy().astype(np.int64)            # list position + 1 in the bin's list
+    rng = state["tile_range"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    ranks = state["pair_rank"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    rec = state["records"].cpu().numpy()
+    bx = rec[:, 13].view(np.uint32).astype(np.int64)
+    by = rec[:, 14].view(np.uint32).astype(np.int64)
+    x0, x1, y0, y1 = bx & 0xFFFF, bx >> 16, by & 0xFFFF, by >> 16
+    bt = state["bin_tile"]
+    nbx = (W + bt - 1) // bt
+    total = 0
+    for b in range(rng.shape[0]):
+        s, e = rng[b]
+        if e <= s:
+            continue
+        g = ranks[s:e]
+        X0b, Y0b = (b % nbx) * bt, (b // nbx) * bt
+        for ty in range(Y0b, min(Y0b + bt, H), tile):
+            for tx in range(X0b, min(X0b + bt, W), tile):
+                deep = int(last[ty:ty + tile, tx:tx + tile].max())
+                if deep == 0:
+                    continue
+                gg = g[:deep]
+                total += int(np.count_nonzero((x0[gg] <= tx + tile - 1) & (x1[gg] >= tx) &
+                                              (y0[gg] <= ty + tile - 1) & (y1[gg] >= ty)))
+    return total
 
 
 def views_bench(rounds: int = 10):
@@ -453,26 +578,27 @@ def main():
     kern_ms = dom[0] / max(dom[1], 1)
     flops = FLOPS_PER_PAIR[dominant] * st["composited"]
     achieved = flops / (kern_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": f"k_{dominant}", "achieved": round(achieved, 3),
+    names = kernel_names(args)
+    roofline = {"bound": "alu", "kernel": names[dominant], "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": read_traffic(dominant), "avg_launch_ms": round(kern_ms, 4), "launches": dom[1],
                 "units": {"composited_pairs": st["composited"], "flops_per_pair": FLOPS_PER_PAIR[dominant]},
                 "work": {"fwd_wave_entries": st["staged"], "bwd_wave_steps": st["reduced"]}}
 
-    # whole-path algorithmic HBM bytes per forward+backward
+    # whole-path algorithmic HBM bytes per forward+backward; K_r counted per
+    # 16 x 16 compositing tile
     state = job.state()
-    last = state["last"].cpu().numpy().astype(np.int64)
-    T = args.bin_tile or args.tile
+    state["bin_tile"] = args.bin_tile or args.tile
+    k_r = staged_entries_per_tile(state, sc, 16)
     H, W = sc.intr.height, sc.intr.width
-    pad = np.zeros(((H + T - 1) // T * T, (W + T - 1) // T * T), np.int64)
-    pad[:H, :W] = last
-    k_r = int(pad.reshape(pad.shape[0] // T, T, pad.shape[1] // T, T).max(axis=(1, 3)).sum())
     N, Nv, K, P = sc.n, st["visible"], st["pairs"], sc.intr.pixels
     alg_bytes = 68 * N + 280 * Nv + 4 * K + 96 * k_r + 68 * P
     fb_ms = ms_per_step / args.iters
     path_hbm = {"bytes_per_fwd_bwd": alg_bytes, "achieved_GBs": round(alg_bytes / (fb_ms * 1e-3) / 1e9, 1),
                 "frac_of_8TBs": round(alg_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "N": N, "N_visible": Nv, "K_pairs": K, "K_r_staged": k_r, "pixels": P}
+                "N": N, "N_visible": Nv, "K_pairs": K, "K_r_staged_per_16px_tile": k_r, "pixels": P,
+                "bytes_formula": "68 N + 280 N_v + 4 K + 96 K_r + 68 P"}
+    kernels = kernel_table(stage_ms, names, N, Nv, K, P, st["composited"])
 
     out = {
         "metric": "Mpix/s RGB-D fwd+bwd @1M Gaussians 1200x680; served frames/s + p99 vs plain",
@@ -485,11 +611,35 @@ def main():
                                f"bin tile {args.bin_tile or args.tile}, {args.fwd_records}/{args.bwd_records} records"
                                + (", pose-only gradients" if args.pose_only else ""),
                    "gaussians": sc.n, "width": W, "height": H, "iterations_per_step": args.iters},
+        "arithmetic": ARITHMETIC[args.bwd_records],
         "roofline": roofline,
+        "kernels": kernels,
         "path_hbm": path_hbm,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
+    if not args.no_alt and args.bwd_records == "mfma":
+        # the same step with the backward's products on bf16 high/low parts
+        alt_opts = dataclasses.replace(opts, bwd_records="mfma_bf16x3")
+        alt = Tracker(m, t(sc.viewmat), target, sc.intr, alt_opts, lr=1e-3, w_depth=0.5,
+                      map_grads=not args.pose_only)
+        for _ in range(2):
+            alt.step(args.iters)
+        aprof = _lib.Profiler(stages=("composite_bwd",))
+        torch.cuda.synchronize()
+        with aprof:
+            ta = time.perf_counter()
+            for _ in range(5):
+                alt.step(args.iters)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+        ab = aprof.read()["composite_bwd"]
+        aprof.close()
+        a_ms = (tb - ta) * 1e3 / 5
+        out["bwd_bf16x3"] = {"arithmetic": ARITHMETIC["mfma_bf16x3"], "kernel": "k_composite_bwd_m<16>",
+                             "Mpix_s": round(px / (a_ms / 1e3) / 1e6, 2), "ms_per_step": round(a_ms, 3),
+                             "composite_bwd_ms": round(ab[0] / max(ab[1], 1), 4)}
+        del alt
     if not args.no_prune:
         out["prune"] = prune_bench(m)
     ssim_frames = None

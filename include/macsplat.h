@@ -105,7 +105,7 @@
 extern "C" {
 #endif
 
-#define MS_ABI_VERSION 3
+#define MS_ABI_VERSION 4
 
 typedef enum {
   MS_OK = 0,
@@ -385,7 +385,15 @@ enum {
   MS_STAGE_COMPOSITE = 2,      /* compositing forward */
   MS_STAGE_COMPOSITE_BWD = 3,  /* compositing backward (includes zeroing its accumulators) */
   MS_STAGE_PROJECT_BWD = 4,    /* projection backward and pose reduction */
-  MS_STAGE_COUNT = 5
+  /* single kernels inside the stages above (timed within them) */
+  MS_STAGE_BIN_COUNT = 5,      /* per-bin path: pair counts per unit and bin, and their scan */
+  MS_STAGE_BIN_EMIT = 6,       /* per-bin path: pair emission into each bin's segment */
+  MS_STAGE_BIN_SORT = 7,       /* per-bin path: each bin's stable depth sort */
+  MS_STAGE_POSE = 8,           /* deterministic fold of the pose partials */
+  /* helpers, timed in their own calls */
+  MS_STAGE_LOSS = 9,           /* ms_l1_loss_grad, ms_ssim_loss_grad */
+  MS_STAGE_POSE_STEP = 10,     /* ms_pose_adam_step */
+  MS_STAGE_COUNT = 11
 };
 typedef struct ms_profiler ms_profiler;
 int32_t ms_profiler_create(uint32_t stage_mask, int32_t capacity, ms_profiler** out);

@@ -35,7 +35,8 @@ EXPORTED = [
 ]
 MS_MAX_BATCH = 12
 
-STAGES = ["project", "bin", "composite", "composite_bwd", "project_bwd"]
+STAGES = ["project", "bin", "composite", "composite_bwd", "project_bwd", "bin_count", "bin_emit", "bin_sort",
+          "pose", "loss", "pose_step"]
 
 
 class MsIntrinsics(ctypes.Structure):

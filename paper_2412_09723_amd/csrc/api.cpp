@@ -95,26 +95,24 @@ namespace {
 
 thread_local ms_profiler* g_prof = nullptr;
 
-// Records the start (open) or end (close) event of a stage on `st` when the
-// attached profiler selects it.
-struct StageTimer {
-  int slot = -1;
-  hipStream_t st;
-  StageTimer(int stage, hipStream_t s) : st(s) {
-    ms_profiler* p = g_prof;
-    if (!p || !(p->mask & (1u << stage)) || p->used >= p->cap) return;
-    slot = p->used++;
-    p->stage[slot] = stage;
-    hipEventRecord(p->ev[2 * slot], st);
-  }
-  void close() {
-    if (slot >= 0 && g_prof) hipEventRecord(g_prof->ev[2 * slot + 1], st);
-    slot = -1;
-  }
-  ~StageTimer() { close(); }
-};
+using StageTimer = StageScope;
 
 }  // namespace
+
+// Records the start event of a stage on `st` when the attached profiler
+// selects it; returns the event slot, or -1.
+int prof_begin(int stage, hipStream_t st) {
+  ms_profiler* p = g_prof;
+  if (!p || !(p->mask & (1u << stage)) || p->used >= p->cap) return -1;
+  const int slot = p->used++;
+  p->stage[slot] = stage;
+  hipEventRecord(p->ev[2 * slot], st);
+  return slot;
+}
+
+void prof_end(int slot, hipStream_t st) {
+  if (slot >= 0 && g_prof) hipEventRecord(g_prof->ev[2 * slot + 1], st);
+}
 
 bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, int& tiles, int& bins,
                  int64_t& pixels) {
@@ -618,6 +616,7 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
     const float* tg[3] = {target->rgb, target->depth, target->silhouette};
     float* gr[3] = {grad->rgb, grad->depth, grad->silhouette};
     const float sc[3] = {w_rgb / (3.0f * (float)P), w_depth / (float)P, w_sil / (float)P};
+    StageTimer tm(MS_STAGE_LOSS, st);
     e = launch_l1_grad(pr, tg, gr, P, sc, loss, st);
   }
   if (e != hipSuccess) return hip_fail(e, "l1 loss");
@@ -662,6 +661,7 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
   }
   for (int k = 0; k < 11; k++) a.w[k] = (float)(w[k] / wsum);
   hipError_t e = hipSuccess;
+  StageTimer tm(MS_STAGE_LOSS, st);
   if (loss && !accumulate) e = launch_zero_scalar(loss, st);
   if (e == hipSuccess) e = launch_ssim_grad(a, st);
   if (e != hipSuccess) return hip_fail(e, "ssim loss");
@@ -731,6 +731,7 @@ int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state,
   if (!viewmat || !twist_grad || !state) return fail(MS_ERR_INVALID_ARG, "null argument");
   if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
     return fail(MS_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+  StageTimer tm(MS_STAGE_POSE_STEP, (hipStream_t)stream);
   hipError_t e = launch_pose_adam(viewmat, twist_grad, state, lr, beta1, beta2, eps, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pose step");
   return MS_OK;

@@ -1057,15 +1057,24 @@ hipError_t launch_bin(const Plan& p, char* ws, hipStream_t st) {
     uint32_t* ucnt = at<uint32_t>(ws, p.ucnt);
     uint32_t *pk = at<uint32_t>(ws, p.pkey), *pv = at<uint32_t>(ws, p.pval);
     uint32_t* gcnt = at<uint32_t>(ws, p.gcnt);   // zeroed with the control region
-    hipLaunchKernelGGL(k_unit_count, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin, p.n, p.unit_rounds,
-                       p.bins, ucnt, gcnt, at<uint32_t>(ws, p.uvis));
-    hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kUScanThreads), 0, st, gcnt, at<uint32_t>(ws, p.uvis), p.units,
-                       p.groups, p.bins, p.cap, counters, trange);
-    hipLaunchKernelGGL(k_unit_emit, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin,
-                       at<uint32_t>(ws, p.key), p.n, p.unit_rounds, p.bins, tile_bits(p.bins), ucnt, gcnt, counters,
-                       pk, pv);
-    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)p.bins), dim3(kSortThreads), 0, st, pk, pv,
-                       at<uint32_t>(ws, p.pkey2), at<uint32_t>(ws, p.pval2), trange, counters);
+    {
+      StageScope tm(MS_STAGE_BIN_COUNT, st);
+      hipLaunchKernelGGL(k_unit_count, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin, p.n, p.unit_rounds,
+                         p.bins, ucnt, gcnt, at<uint32_t>(ws, p.uvis));
+      hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kUScanThreads), 0, st, gcnt, at<uint32_t>(ws, p.uvis), p.units,
+                         p.groups, p.bins, p.cap, counters, trange);
+    }
+    {
+      StageScope tm(MS_STAGE_BIN_EMIT, st);
+      hipLaunchKernelGGL(k_unit_emit, dim3((unsigned)p.units), dim3(kUnitThreads), 0, st, gbin,
+                         at<uint32_t>(ws, p.key), p.n, p.unit_rounds, p.bins, tile_bits(p.bins), ucnt, gcnt, counters,
+                         pk, pv);
+    }
+    {
+      StageScope tm(MS_STAGE_BIN_SORT, st);
+      hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)p.bins), dim3(kSortThreads), 0, st, pk, pv,
+                         at<uint32_t>(ws, p.pkey2), at<uint32_t>(ws, p.pval2), trange, counters);
+    }
     return hipGetLastError();
   }
   // 1. compaction of the visible Gaussians, placed so that the depth sort

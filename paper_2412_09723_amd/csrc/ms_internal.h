@@ -215,6 +215,17 @@ struct SsimArgs {
 hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st);
 // Map pruning (prune.hip): scratch bytes for n Gaussians, and the three
 // launches writing the survivors into `out` (row stride *kept) and *kept.
+// Stage timing of the profiler attached to the calling thread (no-ops when
+// none is attached or the stage is not selected).
+int prof_begin(int stage, hipStream_t st);
+void prof_end(int slot, hipStream_t st);
+struct StageScope {
+  int slot;
+  hipStream_t st;
+  StageScope(int stage, hipStream_t s) : slot(prof_begin(stage, s)), st(s) {}
+  ~StageScope() { prof_end(slot, st); }
+};
+
 size_t prune_workspace_bytes(int64_t n);
 constexpr int64_t kPruneNoAllocMaxN = int64_t(1) << 26;   // largest map of ms_prune_noalloc
 hipError_t prune_scratch(uint32_t** out);

@@ -604,6 +604,7 @@ hipError_t launch_project_bwd(const Plan& p, bool any_pose, char* ws, hipStream_
     if (e != hipSuccess) return e;
   }
   if (any_pose) {
+    StageScope tm(MS_STAGE_POSE, st);
     hipLaunchKernelGGL(k_pose_final, dim3((unsigned)p.njobs), dim3(kPoseThreads), 0, st, jobs, at<double>(ws, p.pose_part),
                        at<uint64_t>(ws, p.counters));
     return hipGetLastError();
