@@ -335,6 +335,47 @@ def prune_bench(m: dict, calls: int = 20):
             "hbm_TB_s": round(algo / ms / 1e9, 3), "hbm_frac_of_8TB_s": round(algo / ms / 1e9 / 8.0, 3)}
 
 
+def select_bench(m: dict, vm, intr, calls: int = 20, max_dist: float = 3.0):
+    """FOV + distance candidate selection (ms_select_candidates) on the
+    benchmark map at the benchmark pose, timed with HIP events on the stream
+    it is launched on."""
+    import ctypes
+    import torch
+    from paper_2412_09723_amd import _lib
+    from paper_2412_09723_amd._lib import MsIntrinsics, check, ref
+    means = m["means"]
+    n = means.shape[1]
+    dev = means.device
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = _lib.load()
+    ws = torch.empty(int(lib.ms_select_workspace_bytes(n)) + 256, dtype=torch.uint8, device=dev)
+    ci = MsIntrinsics(intr.width, intr.height, intr.fx, intr.fy, intr.cx, intr.cy)
+    st = torch.cuda.current_stream(dev)
+
+    def call():
+        check(lib.ms_select_candidates(ctypes.c_void_p(means.data_ptr()), n, ctypes.c_void_p(vm.data_ptr()), ref(ci),
+                                       0.2, max_dist, 0.0, ctypes.c_void_p(idx.data_ptr()),
+                                       ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       ctypes.c_void_p(st.cuda_stream)))
+    for _ in range(3):
+        call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(calls):
+        call()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    k = int(cnt.item())
+    algo = 2 * 12 * n + 4 * k   # the means read by both passes; one index written per candidate
+    return {"workload": f"FOV + distance candidate selection (max distance {max_dist} m, near 0.2 m) of the "
+                        f"{n // 1000}k-Gaussian room map at the tracking pose",
+            "ms_per_call": round(ms, 4), "selected": k, "n": n, "algorithmic_bytes": algo,
+            "hbm_TB_s": round(algo / ms / 1e9, 3), "hbm_frac_of_8TB_s": round(algo / ms / 1e9 / 8.0, 3)}
+
+
 SSIM_FLOPS_PER_VALUE = 390   # separable window sums: 5 statistics x 2 x 11 FMAs + 3 partials x 2 x 11 FMAs, + ~40
 
 
@@ -642,6 +683,7 @@ def main():
         del alt
     if not args.no_prune:
         out["prune"] = prune_bench(m)
+        out["select"] = select_bench(m, t(sc.viewmat), sc.intr)
     ssim_frames = None
     if not args.no_ssim:
         ssim_frames = (tracker.out[0].clone(), target[0].clone())

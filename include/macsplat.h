@@ -362,6 +362,32 @@ int32_t ms_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const 
 int32_t ms_prune_noalloc(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, int64_t* kept,
                          void* stream);
 
+/* Candidate selection (Sec. 3.4, "1) Selection"): the Gaussians of a local
+ * map within the camera's field of view and within max_dist of its pose,
+ * which the intra-agent association and alignment then work on. Gaussian i
+ * is a candidate when its mean, in camera coordinates p = R mu + t, lies
+ * beyond the near plane (p_z > near_z), within max_dist of the camera centre
+ * (|p| <= max_dist) and projects onto the image widened by `margin` pixels
+ * (-margin <= u <= W - 1 + margin, likewise v, pixels sampled at integer
+ * coordinates). The decisions are taken in binary64 from the binary32
+ * inputs in this order, with no fused operations:
+ *   p_k = ((R_k0 mu_0 + R_k1 mu_1) + R_k2 mu_2) + t_k,
+ *   d2 = (p_0 p_0 + p_1 p_1) + p_2 p_2 <= max_dist^2,
+ *   rz = 1 / p_z, u = fx (p_x rz) + cx, v = fy (p_y rz) + cy;
+ * a non-finite mean is never a candidate.
+ * means: device [3][n] float; viewmat: device float[12] world-to-camera
+ * [R|t]; intr: host struct. indices: device int32 with room for n entries,
+ * receiving the candidates' indices in ascending (map) order; count: device
+ * int64 receiving their number. workspace: device scratch of
+ * ms_select_workspace_bytes(n) bytes. n in [0, 2^31 - 1]. Errors:
+ * MS_ERR_INVALID_ARG (null or overlapping arrays, sizes, non-finite or
+ * negative near_z, max_dist, margin, fx, fy <= 0), MS_ERR_WORKSPACE;
+ * nothing is enqueued then. Enqueued on `stream`. */
+size_t ms_select_workspace_bytes(int64_t n);
+int32_t ms_select_candidates(const float* means, int64_t n, const float* viewmat, const ms_intrinsics* intr,
+                             float near_z, float max_dist, float margin, int32_t* indices, int64_t* count,
+                             void* workspace, size_t ws_bytes, void* stream);
+
 /* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
  * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
  * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]

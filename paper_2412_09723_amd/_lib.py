@@ -29,7 +29,8 @@ MS_FLAG_BWD_BF16X3 = 64
 EXPORTED = [
     "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes",
     "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
-    "ms_l1_loss_grad", "ms_ssim_loss_grad", "ms_prune_workspace_bytes", "ms_prune", "ms_prune_noalloc", "ms_pose_adam_step",
+    "ms_l1_loss_grad", "ms_ssim_loss_grad", "ms_prune_workspace_bytes", "ms_prune", "ms_prune_noalloc", "ms_select_workspace_bytes", "ms_select_candidates",
+    "ms_pose_adam_step",
     "ms_profiler_create", "ms_profiler_destroy", "ms_profiler_attach", "ms_profiler_read",
     "ms_batch_workspace_bytes", "ms_forward_batch", "ms_backward_batch", "ms_batch_read_stats",
 ]
@@ -120,6 +121,11 @@ def load():
     lib.ms_prune.restype = ctypes.c_int32
     lib.ms_prune_noalloc.argtypes = [ctypes.POINTER(MsMap), F, F, F, ctypes.POINTER(MsMap), P, P]
     lib.ms_prune_noalloc.restype = ctypes.c_int32
+    lib.ms_select_workspace_bytes.argtypes = [ctypes.c_int64]
+    lib.ms_select_workspace_bytes.restype = ctypes.c_size_t
+    lib.ms_select_candidates.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(MsIntrinsics), F, F, F, P, P, P,
+                                         ctypes.c_size_t, P]
+    lib.ms_select_candidates.restype = ctypes.c_int32
     lib.ms_pose_adam_step.argtypes = [P, P, P, F, F, F, F, P]
     lib.ms_pose_adam_step.restype = ctypes.c_int32
     lib.ms_profiler_create.argtypes = [ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]

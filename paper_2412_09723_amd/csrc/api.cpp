@@ -1,6 +1,7 @@
 // Host side of the C ABI: argument validation, workspace planning and the
 // launch sequence of the forward and backward passes. Allocates nothing;
 // every launch goes to the caller's stream.
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -671,6 +672,11 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
 size_t ms_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
 
 namespace {
+bool means_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
 // Host checks shared by ms_prune and ms_prune_noalloc.
 int32_t check_prune(const ms_map* in, float tau_o, float tau_s, float tau_e, const ms_map* out, const int64_t* kept) {
   int32_t s = check_map(in);
@@ -723,6 +729,44 @@ int32_t ms_prune_noalloc(const ms_map* in, float tau_o, float tau_s, float tau_e
   if (e != hipSuccess) return hip_fail(e, "prune scratch address");
   e = launch_prune(*in, *out, tau_o, tau_s, tau_e, kept, ws, st);
   if (e != hipSuccess) return hip_fail(e, "prune");
+  return MS_OK;
+}
+
+size_t ms_select_workspace_bytes(int64_t n) { return n < 0 ? 0 : select_workspace_bytes(n); }
+
+int32_t ms_select_candidates(const float* means, int64_t n, const float* viewmat, const ms_intrinsics* intr,
+                             float near_z, float max_dist, float margin, int32_t* indices, int64_t* count,
+                             void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(MS_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 1]", (long long)n);
+  if ((n > 0 && (!means || !indices)) || !viewmat || !intr || !count) return fail(MS_ERR_INVALID_ARG, "null argument");
+  if (intr->width < 1 || intr->width > 16384 || intr->height < 1 || intr->height > 16384)
+    return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", intr->width, intr->height);
+  if (!std::isfinite(intr->fx) || !std::isfinite(intr->fy) || !std::isfinite(intr->cx) || !std::isfinite(intr->cy) ||
+      !(intr->fx > 0.f) || !(intr->fy > 0.f))
+    return fail(MS_ERR_INVALID_ARG, "intrinsics must be finite with fx, fy > 0");
+  if (!std::isfinite(near_z) || !(near_z > 0.f)) return fail(MS_ERR_INVALID_ARG, "near_z must be finite and > 0");
+  if (!std::isfinite(max_dist) || max_dist < 0.f) return fail(MS_ERR_INVALID_ARG, "max_dist must be finite and >= 0");
+  if (!std::isfinite(margin) || margin < 0.f) return fail(MS_ERR_INVALID_ARG, "margin must be finite and >= 0");
+  if (n > 0 && (means_overlap(indices, (size_t)n * sizeof(int32_t), means, (size_t)n * 3 * sizeof(float))))
+    return fail(MS_ERR_INVALID_ARG, "indices overlap the means");
+  if (!workspace) return fail(MS_ERR_WORKSPACE, "null workspace");
+  if (ws_bytes < select_workspace_bytes(n)) return fail(MS_ERR_WORKSPACE, "workspace too small");
+  SelectArgs a;
+  a.means = means;
+  a.n = n;
+  a.viewmat = viewmat;
+  a.fx = (double)intr->fx;
+  a.fy = (double)intr->fy;
+  a.cx = (double)intr->cx;
+  a.cy = (double)intr->cy;
+  a.near = (double)near_z;
+  a.dmax2 = (double)max_dist * (double)max_dist;
+  a.xmin = -(double)margin;
+  a.xmax = (double)(intr->width - 1) + (double)margin;
+  a.ymin = -(double)margin;
+  a.ymax = (double)(intr->height - 1) + (double)margin;
+  hipError_t e = launch_select(a, indices, count, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "candidate selection");
   return MS_OK;
 }
 

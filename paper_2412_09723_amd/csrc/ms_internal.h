@@ -227,6 +227,18 @@ struct StageScope {
 };
 
 size_t prune_workspace_bytes(int64_t n);
+// One workgroup: bcount[b] (nblocks counts) becomes the exclusive offset of
+// block b, *total the sum.
+hipError_t launch_block_offsets(uint32_t* bcount, int64_t nblocks, int64_t* total, hipStream_t st);
+
+struct SelectArgs {
+  const float* means;      // [3][n]
+  int64_t n;
+  const float* viewmat;    // device [12]
+  double fx, fy, cx, cy, near, dmax2, xmin, xmax, ymin, ymax;
+};
+size_t select_workspace_bytes(int64_t n);
+hipError_t launch_select(const SelectArgs& a, int32_t* idx, int64_t* count, void* ws, hipStream_t st);
 constexpr int64_t kPruneNoAllocMaxN = int64_t(1) << 26;   // largest map of ms_prune_noalloc
 hipError_t prune_scratch(uint32_t** out);
 hipError_t launch_prune(const ms_map& in, const ms_map& out, float tau_o, float tau_s, float tau_e, int64_t* kept,

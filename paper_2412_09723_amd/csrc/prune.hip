@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(kPruneThreads) k_prune_count(PruneArgs A, uint
 }
 
 // In place: bcount[b] becomes the exclusive offset of block b; *kept the total.
+// (Also the middle pass of the candidate selection's compaction.)
 __global__ void __launch_bounds__(kPruneScanThreads) k_prune_scan(uint32_t* __restrict__ bcount, int64_t nblocks,
                                                                   int64_t* __restrict__ kept) {
   __shared__ int64_t wsum[kPruneScanThreads / 64];
@@ -180,6 +181,11 @@ hipError_t prune_scratch(uint32_t** out) {
   }
   *out = g_scratch_ptr[dev];
   return hipSuccess;
+}
+
+hipError_t launch_block_offsets(uint32_t* bcount, int64_t nblocks, int64_t* total, hipStream_t st) {
+  hipLaunchKernelGGL(k_prune_scan, dim3(1), dim3(kPruneScanThreads), 0, st, bcount, nblocks, total);
+  return hipGetLastError();
 }
 
 size_t prune_workspace_bytes(int64_t n) {

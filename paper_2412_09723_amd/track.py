@@ -128,3 +128,35 @@ def prune_map(m: dict, tau_o: float = 0.005, tau_s: float = 0.25, tau_e: float =
     k = int(kept.item())
     return {key: (bufs[key][:rows[key] * k].view(rows[key], k) if key != "opacity" else bufs[key][:k])
             for key in keys}
+
+
+def select_candidates(means: torch.Tensor, viewmat: torch.Tensor, intr, near_z: float = 0.2, max_dist: float = 3.0,
+                      margin: float = 0.0, sync: bool = True):
+    """Candidate selection of Sec. 3.4 ("1) Selection") through
+    ms_select_candidates: indices (int32, map order) of the Gaussians whose
+    mean is in the camera's field of view and within max_dist of its pose.
+    means: contiguous float32 [3, N] on the device; viewmat: float32 [12] on
+    the same device. With sync (one host read of the count) returns the index
+    tensor trimmed to the count; otherwise (indices [N], count [1] int64),
+    both on the device."""
+    from ._lib import MsIntrinsics
+    if means.dim() != 2 or means.shape[0] != 3 or means.dtype != torch.float32 or not means.is_contiguous():
+        raise ValueError("means must be a contiguous float32 [3, N] tensor")
+    if not means.is_cuda or viewmat.device != means.device or viewmat.dtype != torch.float32 or viewmat.numel() != 12:
+        raise ValueError("means and a float32 [12] viewmat must be on one device")
+    n = means.shape[1]
+    dev = means.device
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = _lib.load()
+    ws = torch.empty(max(int(lib.ms_select_workspace_bytes(n)), 256), dtype=torch.uint8, device=dev)
+    c_intr = MsIntrinsics(int(intr.width), int(intr.height), float(intr.fx), float(intr.fy), float(intr.cx),
+                          float(intr.cy))
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    check(lib.ms_select_candidates(ctypes.c_void_p(means.data_ptr()), n, ctypes.c_void_p(viewmat.data_ptr()),
+                                   ref(c_intr), float(near_z), float(max_dist), float(margin),
+                                   ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(count.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream))
+    if not sync:
+        return idx, count
+    return idx[:int(count.item())]

@@ -249,3 +249,28 @@ def test_prune_noalloc_rejects_bad_arguments(lib):
     assert call(src=MsMap(big, *[getattr(m, f) for f in fields]),
                 dst=MsMap(big, *[getattr(out, f) for f in fields])) == _lib.MS_ERR_INVALID_ARG
     assert "static scratch" in lib.ms_last_error().decode()
+
+
+def test_select_rejects_bad_arguments(lib):
+    from paper_2412_09723_amd._lib import MsIntrinsics as I
+    good = I(160, 120, 150.0, 150.0, 80.0, 60.0)
+
+    def call(means=FAKE, n=4096, vm=FAKE + 0x100000, intr=good, near=0.2, dmax=3.0, margin=0.0,
+             idx=FAKE + 0x200000, cnt=FAKE + 0x300000, ws=FAKE + 0x400000, wsb=1 << 20):
+        return lib.ms_select_candidates(ctypes.c_void_p(means), n, ctypes.c_void_p(vm),
+                                        ref(intr) if intr is not None else None, near, dmax, margin,
+                                        ctypes.c_void_p(idx), ctypes.c_void_p(cnt), ctypes.c_void_p(ws), wsb, None)
+    assert call(means=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(vm=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(intr=None) == _lib.MS_ERR_INVALID_ARG
+    assert call(cnt=0) == _lib.MS_ERR_INVALID_ARG
+    assert call(n=-1) == _lib.MS_ERR_INVALID_ARG
+    assert call(n=1 << 31) == _lib.MS_ERR_INVALID_ARG
+    assert call(intr=I(0, 120, 150.0, 150.0, 80.0, 60.0)) == _lib.MS_ERR_INVALID_ARG
+    assert call(intr=I(160, 120, -150.0, 150.0, 80.0, 60.0)) == _lib.MS_ERR_INVALID_ARG
+    assert call(near=0.0) == _lib.MS_ERR_INVALID_ARG
+    assert call(dmax=-1.0) == _lib.MS_ERR_INVALID_ARG
+    assert call(margin=float("nan")) == _lib.MS_ERR_INVALID_ARG
+    assert call(idx=FAKE + 64) == _lib.MS_ERR_INVALID_ARG          # indices over the means
+    assert call(ws=0) == _lib.MS_ERR_WORKSPACE
+    assert call(wsb=lib.ms_select_workspace_bytes(4096) - 1) == _lib.MS_ERR_WORKSPACE
