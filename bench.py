@@ -408,6 +408,33 @@ def ssim_bench(pred, target, calls: int = 50):
             "alu_TFLOP_s": round(SSIM_FLOPS_PER_VALUE * values / ms / 1e9, 2), "loss": float(loss.cpu()[0])}
 
 
+def pair_loss_bench(rgb_i, rgb_j, depth_i, depth_j, calls: int = 50):
+    """Eq. 7 on one pair of rendered views (ms_pair_loss_grad: L1 colour,
+    SSIM and L1 depth terms, gradients to both views, one launch) on two
+    1200x680 renders, timed with HIP events on the stream it runs on."""
+    import torch
+    from paper_2412_09723_amd.track import pair_loss_grad
+    grads = (torch.empty_like(rgb_i), torch.empty_like(rgb_j), torch.empty_like(depth_i), torch.empty_like(depth_j))
+    loss = torch.zeros(1, dtype=torch.float32, device=rgb_i.device)
+    for _ in range(5):
+        pair_loss_grad(rgb_i, rgb_j, depth_i, depth_j, grads=grads, loss=loss)
+    st = torch.cuda.current_stream(rgb_i.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(calls):
+        pair_loss_grad(rgb_i, rgb_j, depth_i, depth_j, grads=grads, loss=loss)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    C, H, W = rgb_i.shape
+    nbytes = 2 * (C + 1) * H * W * 4 * 2   # read both views' colour and depth, write their gradients
+    return {"workload": f"Eq. 7 on one pair of rendered views (0.8 L1 + 0.2 (1 - SSIM) + 0.1 depth L1, "
+                        f"gradients to both), {C}x{H}x{W} colour and {H}x{W} depth each",
+            "ms_per_call": round(ms, 4), "Mpix_s": round(H * W / ms / 1e3, 1), "hbm_bytes_per_call": nbytes,
+            "hbm_TB_s": round(nbytes / ms / 1e9, 3), "loss": float(loss.cpu()[0])}
+
+
 def ssim_cpu_baseline(pred, target):
     """The binary64 SSIM oracle (unchanged) on the same frame, once."""
     from oracle import ssim
@@ -688,6 +715,8 @@ def main():
     if not args.no_ssim:
         ssim_frames = (tracker.out[0].clone(), target[0].clone())
         out["ssim_loss"] = ssim_bench(*ssim_frames)
+        out["pair_loss"] = pair_loss_bench(tracker.out[0].clone(), target[0].clone(), tracker.out[1].clone(),
+                                           target[1].clone())
     if not args.no_batch:
         del tracker, job, obs_job_state
         torch.cuda.empty_cache()

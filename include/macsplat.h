@@ -215,6 +215,20 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
                     void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* grad_out,
                     const ms_grads* grads, void* stream);
 
+/* ms_backward for the L1 loss of Eq. 7's L1 terms as a per-agent tracking
+ * loss, w_rgb mean|rgb - rgb*| + w_depth mean|D - D*| + w_sil mean|S - S*|,
+ * with its upstream gradient formed per pixel inside the compositing
+ * backward (sign(0) = 0) instead of read from gradient planes: the same
+ * result, bit for bit, as ms_l1_loss_grad followed by ms_backward, without
+ * the planes' round trip through memory. pred: the images the last
+ * ms_forward on this workspace wrote; target: the observed images (device,
+ * same layout). Other arguments, errors and stream behaviour as
+ * ms_backward. */
+int32_t ms_backward_l1(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                       void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* pred,
+                       const ms_images* target, float w_rgb, float w_depth, float w_sil, const ms_grads* grads,
+                       void* stream);
+
 /* Counters of the last forward (and backward) on a workspace, copied to
  * host memory out[7]: visible Gaussians, (Gaussian, bin tile) pairs,
  * pair-capacity overflow flag (0/1), bin tiles, composited (pixel, Gaussian)
@@ -325,6 +339,27 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
  * otherwise MS_ERR_INVALID_ARG and nothing is enqueued. Enqueued on `stream`. */
 int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channels, int32_t width, int32_t height,
                           float weight, float* grad, int32_t accumulate, float* loss, void* stream);
+
+/* The loss of Eq. 7 for one pair (i, j) of rendered views (the images of
+ * two agents' maps, or two maps, rendered at one pose), with the readings
+ * of the SSIM term above (the term is w_ssim (1 - SSIM)):
+ *   L = w_l1 mean|I_i - I_j| + w_ssim (1 - mean SSIM(I_i, I_j))
+ *       + w_geom mean|D_i - D_j|,
+ * means over 3 W H colour values and W H depths, sign(0) = 0, and its
+ * gradient with respect to all four rendered images (the paper's weights
+ * are 0.8, 0.2 and 0.1). One launch: the SSIM window sums of both images
+ * give dL/dI_i and dL/dI_j (SSIM is symmetric in its two images), the L1
+ * terms join them in the same pass, and further workgroups take the depth
+ * planes. rgb_*: device float [3][H][W]; depth_*: [H][W]; g_*: gradients of
+ * the same shapes, overlapping no input and each other; accumulate = 0
+ * overwrites them and *loss, 1 adds to them. loss: device float or NULL.
+ * Errors: MS_ERR_INVALID_ARG (null or overlapping arrays, sizes outside
+ * [1, 16384], non-finite weights); nothing is enqueued then. Enqueued on
+ * `stream`. */
+int32_t ms_pair_loss_grad(const float* rgb_i, const float* rgb_j, const float* depth_i, const float* depth_j,
+                          int32_t width, int32_t height, float w_l1, float w_ssim, float w_geom, float* g_rgb_i,
+                          float* g_rgb_j, float* g_depth_i, float* g_depth_j, int32_t accumulate, float* loss,
+                          void* stream);
 
 /* ----------------------------------------------------------------- map upkeep
  * Map pruning (App. C.1, Algorithm 1). A Gaussian is removed when its opacity

@@ -27,9 +27,9 @@ MS_FLAG_ACCUMULATE_MAP_GRADS = 32
 MS_FLAG_BWD_BF16X3 = 64
 
 EXPORTED = [
-    "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes",
+    "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes", "ms_backward_l1",
     "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
-    "ms_l1_loss_grad", "ms_ssim_loss_grad", "ms_prune_workspace_bytes", "ms_prune", "ms_prune_noalloc", "ms_select_workspace_bytes", "ms_select_candidates",
+    "ms_l1_loss_grad", "ms_ssim_loss_grad", "ms_pair_loss_grad", "ms_prune_workspace_bytes", "ms_prune", "ms_prune_noalloc", "ms_select_workspace_bytes", "ms_select_candidates",
     "ms_pose_adam_step",
     "ms_profiler_create", "ms_profiler_destroy", "ms_profiler_attach", "ms_profiler_read",
     "ms_batch_workspace_bytes", "ms_forward_batch", "ms_backward_batch", "ms_batch_read_stats",
@@ -106,6 +106,9 @@ def load():
     lib.ms_forward.restype = ctypes.c_int32
     lib.ms_backward.argtypes = [P, P, P, P, P, ctypes.c_size_t, ctypes.c_int64, P, P, P]
     lib.ms_backward.restype = ctypes.c_int32
+    lib.ms_backward_l1.argtypes = [P, P, P, P, P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, P, P]
+    lib.ms_backward_l1.restype = ctypes.c_int32
     lib.ms_read_stats.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int64, P, P]
     lib.ms_read_stats.restype = ctypes.c_int32
     lib.ms_state_view_get.argtypes = [P, ctypes.c_size_t, ctypes.c_int64, P, P, ctypes.c_int64, P]
@@ -115,6 +118,9 @@ def load():
     lib.ms_l1_loss_grad.restype = ctypes.c_int32
     lib.ms_ssim_loss_grad.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, F, P, ctypes.c_int32, P, P]
     lib.ms_ssim_loss_grad.restype = ctypes.c_int32
+    lib.ms_pair_loss_grad.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32, F, F, F, P, P, P, P,
+                                      ctypes.c_int32, P, P]
+    lib.ms_pair_loss_grad.restype = ctypes.c_int32
     lib.ms_prune_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.ms_prune_workspace_bytes.restype = ctypes.c_size_t
     lib.ms_prune.argtypes = [ctypes.POINTER(MsMap), F, F, F, ctypes.POINTER(MsMap), P, P, ctypes.c_size_t, P]

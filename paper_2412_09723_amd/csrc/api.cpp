@@ -483,6 +483,39 @@ int32_t ms_backward(const ms_map* map, const float* viewmat, const ms_intrinsics
   return run_backward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
 }
 
+int32_t ms_backward_l1(const ms_map* map, const float* viewmat, const ms_intrinsics* intr, const ms_options* opts,
+                       void* workspace, size_t ws_bytes, int64_t pair_capacity, const ms_images* pred,
+                       const ms_images* target, float w_rgb, float w_depth, float w_sil, const ms_grads* grads,
+                       void* stream) {
+  int32_t s = check_map(map);
+  if (s != MS_OK) return s;
+  s = check_common(intr, opts, map->n, pair_capacity);
+  if (s != MS_OK) return s;
+  if (!viewmat) return fail(MS_ERR_INVALID_ARG, "null viewmat");
+  if (!pred || !pred->rgb || !pred->depth || !pred->silhouette)
+    return fail(MS_ERR_INVALID_ARG, "null rendered image");
+  if (!std::isfinite(w_rgb) || !std::isfinite(w_depth) || !std::isfinite(w_sil))
+    return fail(MS_ERR_INVALID_ARG, "non-finite loss weight");
+  s = check_backward_job(*map, target, grads, opts->flags);   // target in the upstream's place
+  if (s != MS_OK) return s;
+  JobTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = 1;
+  t.job[0] = job_from_map(*map, viewmat, *intr);
+  set_backward_job(t.job[0], *target, *grads, opts->flags);
+  JobDesc& J = t.job[0];
+  J.rgb = pred->rgb;
+  J.depth = pred->depth;
+  J.sil = pred->silhouette;
+  // the scales of ms_l1_loss_grad, so that both paths form the same upstream
+  const int64_t P = (int64_t)intr->width * intr->height;
+  J.l1s[0] = w_rgb / (3.0f * (float)P);
+  J.l1s[1] = w_depth / (float)P;
+  J.l1s[2] = w_sil / (float)P;
+  J.flags |= kJobL1Upstream;
+  return run_backward(t, opts, workspace, ws_bytes, pair_capacity, (hipStream_t)stream);
+}
+
 size_t ms_batch_workspace_bytes(int32_t njobs, const ms_job* jobs, const ms_options* opts, int64_t pair_capacity) {
   if (!opts) return 0;
   if (njobs < 1 || njobs > kMaxJobs || !jobs) return 0;
@@ -624,6 +657,11 @@ int32_t ms_l1_loss_grad(const ms_images* pred, const ms_images* target, const ms
   return MS_OK;
 }
 
+namespace {
+void ssim_window(float out[11]);
+bool means_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
+}  // namespace
+
 int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channels, int32_t width, int32_t height,
                           float weight, float* grad, int32_t accumulate, float* loss, void* stream) {
   if (!pred || !target || !grad) return fail(MS_ERR_INVALID_ARG, "null argument");
@@ -643,6 +681,7 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
   }
   hipStream_t st = (hipStream_t)stream;
   SsimArgs a;
+  std::memset(&a, 0, sizeof(a));
   a.pred = pred;
   a.target = target;
   a.grad = grad;
@@ -653,14 +692,7 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
   a.accumulate = accumulate;
   a.weight = weight;
   a.dS = (float)(-(double)weight / ((double)channels * (double)width * (double)height));
-  // Gaussian window, standard deviation 1.5 px, normalised in binary64
-  double wsum = 0.0, w[11];
-  for (int k = 0; k < 11; k++) {
-    const double d = k - 5;
-    w[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
-    wsum += w[k];
-  }
-  for (int k = 0; k < 11; k++) a.w[k] = (float)(w[k] / wsum);
+  ssim_window(a.w);
   hipError_t e = hipSuccess;
   StageTimer tm(MS_STAGE_LOSS, st);
   if (loss && !accumulate) e = launch_zero_scalar(loss, st);
@@ -669,9 +701,71 @@ int32_t ms_ssim_loss_grad(const float* pred, const float* target, int32_t channe
   return MS_OK;
 }
 
+int32_t ms_pair_loss_grad(const float* rgb_i, const float* rgb_j, const float* depth_i, const float* depth_j,
+                          int32_t width, int32_t height, float w_l1, float w_ssim, float w_geom, float* g_rgb_i,
+                          float* g_rgb_j, float* g_depth_i, float* g_depth_j, int32_t accumulate, float* loss,
+                          void* stream) {
+  if (!rgb_i || !rgb_j || !depth_i || !depth_j || !g_rgb_i || !g_rgb_j || !g_depth_i || !g_depth_j)
+    return fail(MS_ERR_INVALID_ARG, "null argument");
+  if (width < 1 || width > 16384 || height < 1 || height > 16384)
+    return fail(MS_ERR_INVALID_ARG, "image size %dx%d outside [1, 16384]", width, height);
+  if (!std::isfinite(w_l1) || !std::isfinite(w_ssim) || !std::isfinite(w_geom))
+    return fail(MS_ERR_INVALID_ARG, "non-finite loss weight");
+  if (accumulate != 0 && accumulate != 1) return fail(MS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  const size_t P = (size_t)width * (size_t)height;
+  const void* ins[4] = {rgb_i, rgb_j, depth_i, depth_j};
+  const size_t inb[4] = {3 * P * 4, 3 * P * 4, P * 4, P * 4};
+  const void* outs[4] = {g_rgb_i, g_rgb_j, g_depth_i, g_depth_j};
+  for (int o = 0; o < 4; o++) {
+    for (int i = 0; i < 4; i++)   // the window reads neighbouring pixels of every input
+      if (means_overlap(outs[o], inb[o], ins[i], inb[i])) return fail(MS_ERR_INVALID_ARG, "gradient overlaps an input");
+    for (int q = o + 1; q < 4; q++)
+      if (means_overlap(outs[o], inb[o], outs[q], inb[q])) return fail(MS_ERR_INVALID_ARG, "gradients overlap");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  SsimArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pred = rgb_i;
+  a.target = rgb_j;
+  a.grad = g_rgb_i;
+  a.grad_y = g_rgb_j;
+  a.loss = loss;
+  a.C = 3;
+  a.W = width;
+  a.H = height;
+  a.accumulate = accumulate;
+  a.weight = w_ssim;
+  a.dS = (float)(-(double)w_ssim / (3.0 * (double)P));
+  a.sl1 = (float)((double)w_l1 / (3.0 * (double)P));
+  a.dx = depth_i;
+  a.dy = depth_j;
+  a.gdx = g_depth_i;
+  a.gdy = g_depth_j;
+  a.sgeom = (float)((double)w_geom / (double)P);
+  ssim_window(a.w);
+  hipError_t e = hipSuccess;
+  StageTimer tm(MS_STAGE_LOSS, st);
+  if (loss && !accumulate) e = launch_zero_scalar(loss, st);
+  if (e == hipSuccess) e = launch_ssim_grad(a, st);
+  if (e != hipSuccess) return hip_fail(e, "pair loss");
+  return MS_OK;
+}
+
 size_t ms_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
 
 namespace {
+// Gaussian window of the SSIM statistics, standard deviation 1.5 px,
+// normalised in binary64.
+void ssim_window(float out[11]) {
+  double wsum = 0.0, w[11];
+  for (int k = 0; k < 11; k++) {
+    const double d = k - 5;
+    w[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    wsum += w[k];
+  }
+  for (int k = 0; k < 11; k++) out[k] = (float)(w[k] / wsum);
+}
+
 bool means_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
   return a0 < b0 + bbytes && b0 < a0 + abytes;

@@ -485,9 +485,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   const int tile_id = (int)blockIdx.x - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  const float* __restrict__ g_rgb = J.g_rgb;
-  const float* __restrict__ g_depth = J.g_depth;
-  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   if (counters[C_OVERFLOW] != 0) return;
@@ -499,11 +496,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GS = 0.f, Tf = 1.f;
   uint32_t L = 0u;
   if (inside) {
-    G0 = g_rgb[pix];
-    G1 = g_rgb[P + pix];
-    G2 = g_rgb[2 * P + pix];
-    GD = g_depth[pix];
-    GS = g_sil[pix];
+    load_upstream(J, pix, P, G0, G1, G2, GD, GS);
     Tf = tfinal[J.pix0 + pix];
     L = last[J.pix0 + pix];
   }
@@ -600,9 +593,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   const int tile_id = (int)blockIdx.x - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  const float* __restrict__ g_rgb = J.g_rgb;
-  const float* __restrict__ g_depth = J.g_depth;
-  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   if (counters_rw[C_OVERFLOW] != 0) return;
@@ -613,11 +603,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GS = 0.f, Tf = 1.f;
   uint32_t L = 0u;
   if (inside) {
-    G0 = g_rgb[pix];
-    G1 = g_rgb[P + pix];
-    G2 = g_rgb[2 * P + pix];
-    GD = g_depth[pix];
-    GS = g_sil[pix];
+    load_upstream(J, pix, P, G0, G1, G2, GD, GS);
     Tf = tfinal[J.pix0 + pix];
     L = last[J.pix0 + pix];
   }
@@ -743,9 +729,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   const int tile_id = (int)blockIdx.x - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  const float* __restrict__ g_rgb = J.g_rgb;
-  const float* __restrict__ g_depth = J.g_depth;
-  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (counters_rw[C_OVERFLOW] != 0) return;   // uniform over the launch
   // Sums of the block's waves for the same Gaussian meet in LDS, indexed by
@@ -769,11 +752,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GS = 0.f, Tf = 1.f;
   uint32_t L = 0u;
   if (inside) {
-    G0 = g_rgb[pix];
-    G1 = g_rgb[P + pix];
-    G2 = g_rgb[2 * P + pix];
-    GD = g_depth[pix];
-    GS = g_sil[pix];
+    load_upstream(J, pix, P, G0, G1, G2, GD, GS);
     Tf = tfinal[J.pix0 + pix];
     L = last[J.pix0 + pix];
   }
@@ -1055,9 +1034,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   const int tile_id = (int)blockIdx.x - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  const float* __restrict__ g_rgb = J.g_rgb;
-  const float* __restrict__ g_depth = J.g_depth;
-  const float* __restrict__ g_sil = J.g_sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (counters_rw[C_OVERFLOW] != 0) return;   // uniform over the launch
   // sums of the block's waves for one Gaussian meet in LDS, indexed by list
@@ -1080,11 +1056,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GS = 0.f, Tf = 1.f;
   uint32_t L = 0u;
   if (inside) {
-    G0 = g_rgb[pix];
-    G1 = g_rgb[P + pix];
-    G2 = g_rgb[2 * P + pix];
-    GD = g_depth[pix];
-    GS = g_sil[pix];
+    load_upstream(J, pix, P, G0, G1, G2, GD, GS);
     Tf = tfinal[J.pix0 + pix];
     L = last[J.pix0 + pix];
   }

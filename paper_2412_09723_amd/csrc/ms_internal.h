@@ -84,12 +84,40 @@ struct JobDesc {
   int tile0, tiles, tx;      // compositing tiles
   int bin0, bins, bx;        // bins
   int block0, blocks;        // projection blocks of 256 Gaussians (block0 a multiple of kAdjSlots / 256)
-  uint32_t flags;            // MS_FLAG_POSE_GRAD_ONLY / MS_FLAG_NO_POSE_GRAD for this job
+  uint32_t flags;            // MS_FLAG_POSE_GRAD_ONLY / MS_FLAG_NO_POSE_GRAD for this job, kJobL1Upstream
+  float l1s[3];              // kJobL1Upstream: the L1 gradient's scale of the rgb, depth, silhouette planes
 };
 struct JobTable {
   int njobs, pad;
   JobDesc job[kMaxJobs];
 };
+
+// Job flag (internal): the backward's upstream gradient is the L1 loss
+// gradient scale * sign(pred - target), formed per pixel from the rendered
+// images (rgb, depth, sil: the prediction) and the target planes, which then
+// sit in g_rgb, g_depth, g_sil.
+constexpr uint32_t kJobL1Upstream = 1u << 30;
+
+// Gradient of scale * |d| with sign(0) = 0.
+__host__ __device__ inline float l1_sign(float d, float sc) { return d > 0.f ? sc : (d < 0.f ? -sc : 0.f); }
+
+// The upstream gradient of pixel `pix` of job J (P = W H).
+__device__ inline void load_upstream(const JobDesc& J, int64_t pix, int64_t P, float& G0, float& G1, float& G2,
+                                     float& GD, float& GS) {
+  if (J.flags & kJobL1Upstream) {
+    G0 = l1_sign(J.rgb[pix] - J.g_rgb[pix], J.l1s[0]);
+    G1 = l1_sign(J.rgb[P + pix] - J.g_rgb[P + pix], J.l1s[0]);
+    G2 = l1_sign(J.rgb[2 * P + pix] - J.g_rgb[2 * P + pix], J.l1s[0]);
+    GD = l1_sign(J.depth[pix] - J.g_depth[pix], J.l1s[1]);
+    GS = l1_sign(J.sil[pix] - J.g_sil[pix], J.l1s[2]);
+  } else {
+    G0 = J.g_rgb[pix];
+    G1 = J.g_rgb[P + pix];
+    G2 = J.g_rgb[2 * P + pix];
+    GD = J.g_depth[pix];
+    GS = J.g_sil[pix];
+  }
+}
 
 // Job owning global tile `t` (tile ranges ascend with the job index).
 __device__ inline int job_of_tile(const JobDesc* __restrict__ jobs, int njobs, int t) {
@@ -204,13 +232,19 @@ hipError_t launch_zero_scalar(float* p, hipStream_t st);
 // and *loss += weight (1 - mean S) when loss is not null. w: the 11 window
 // weights; dS = -weight / (C W H).
 struct SsimArgs {
-  const float* pred;
-  const float* target;
-  float* grad;
+  const float* pred;       // x [C][H][W]
+  const float* target;     // y
+  float* grad;             // dL/dx
   float* loss;
   int C, W, H, accumulate;
-  float weight, dS;
-  float w[11];
+  float weight, dS;        // SSIM weight; dL/dS = -weight / (C W H)
+  float w[11];             // window taps
+  // pair form (Eq. 7 for two rendered views): grad_y != NULL
+  float* grad_y;           // dL/dy
+  float sl1;               // L1 scale of the channels: w_l1 / (C W H)
+  const float *dx, *dy;    // depth planes [H][W]
+  float *gdx, *gdy;        // their gradients
+  float sgeom;             // w_geom / (W H)
 };
 hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st);
 // Map pruning (prune.hip): scratch bytes for n Gaussians, and the three

@@ -34,14 +34,39 @@ constexpr int kRunGrad = 4;    // the two passes over a, b, c: 42 x 8 and 32 x 8
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
-// region 1: x, y (2 x 52 x 52), later a, b, c (3 x 42 x 42)
-constexpr int kR1 = 2 * kSsimIn * kSsimIn;
-// region 2: five row-sum planes (5 x 52 x 42), later three (3 x 42 x 32)
+// region 1: x, y (2 x 52 x 52), later a, b, c (3 x 42 x 42) and, in the
+// pair form, a_y (4 x 42 x 42)
+template <bool kPair>
+constexpr int ssim_r1() {
+  return kPair ? 4 * kSsimStat * kSsimStat : 2 * kSsimIn * kSsimIn;
+}
+static_assert(4 * kSsimStat * kSsimStat >= 2 * kSsimIn * kSsimIn, "x, y fit the pair form's region 1");
+// region 2: five row-sum planes (5 x 52 x 42), later three or four (x 42 x 32)
 constexpr int kR2 = 5 * kSsimIn * kSsimStat;
-static_assert(3 * kSsimStat * kSsimStat <= kR1, "a, b, c fit region 1");
-static_assert(3 * kSsimStat * kSsimTile <= kR2, "their row sums fit region 2");
+static_assert(3 * kSsimStat * kSsimStat <= 2 * kSsimIn * kSsimIn, "a, b, c fit region 1");
+static_assert(4 * kSsimStat * kSsimTile <= kR2, "their row sums fit region 2");
 
+// Pair form, depth part: the L1 term of the two depth planes on one 32x32
+// tile (no window); returns the tile's share of the loss from thread 0.
+__device__ inline float depth_l1_tile(const SsimArgs& A, int X0, int Y0, int t) {
+  float acc = 0.f;
+  for (int i = t; i < kSsimTile * kSsimTile; i += kSsimThreads) {
+    const int gx = X0 + (i % kSsimTile), gy = Y0 + i / kSsimTile;
+    if (gx >= A.W || gy >= A.H) continue;
+    const int64_t q = (int64_t)gy * A.W + gx;
+    const float d = A.dx[q] - A.dy[q];
+    const float g = l1_sign(d, A.sgeom);
+    A.gdx[q] = A.accumulate ? A.gdx[q] + g : g;
+    A.gdy[q] = A.accumulate ? A.gdy[q] - g : -g;
+    acc += fabsf(d) * A.sgeom;
+  }
+  return acc;
+}
+
+template <bool kPair>
 __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
+  constexpr int kR1 = ssim_r1<kPair>();
+  constexpr int kPlanes = kPair ? 4 : 3;   // a (a_x), b, c, and a_y
   __shared__ float r1[kR1];
   __shared__ float r2[kR2];
   __shared__ float red[kSsimThreads / 64];
@@ -51,9 +76,23 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
   // workgroups go to the eight XCDs in turn: give each XCD a contiguous run
   // of tiles so that neighbouring tiles' halos meet in one L2
   const int gx = (W + kSsimTile - 1) / kSsimTile, gy = (H + kSsimTile - 1) / kSsimTile;
-  const int total = gx * gy * A.C, per = (total + 7) / 8;
+  const int total = gx * gy * (A.C + (kPair ? 1 : 0)), per = (total + 7) / 8;
   const int tile = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
   if (tile >= total) return;
+  if (kPair && tile >= gx * gy * A.C) {   // block-uniform: a depth tile
+    const int rem = tile - gx * gy * A.C, by = rem / gx, bx = rem - by * gx;
+    float acc = depth_l1_tile(A, bx * kSsimTile, by * kSsimTile, t);
+    if (!A.loss) return;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      float s = 0.f;
+      for (int w = 0; w < kSsimThreads / 64; w++) s += red[w];
+      unsafeAtomicAdd(A.loss, s);
+    }
+    return;
+  }
   const int bz = tile / (gx * gy), rem = tile - bz * gx * gy, by = rem / gx, bx = rem - by * gx;
   const int X0 = bx * kSsimTile, Y0 = by * kSsimTile;
   const float* __restrict__ x = A.pred + (int64_t)bz * P;
@@ -117,6 +156,7 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
   float* pa = r1;
   float* pb = r1 + kP2;
   float* pc = r1 + 2 * kP2;
+  float* pay = r1 + 3 * kP2;   // pair form only
   float ssum = 0.f;
   {
     constexpr int kRun = kRunStat, kGroups = kSsimStat / kRun, kLen = kRun + 2 * kSsimRad;
@@ -141,7 +181,7 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
 #pragma unroll
       for (int o = 0; o < kRun; o++) {
         const int r = r0 + o, gy = Y0 - kSsimRad + r;
-        float va = 0.f, vb = 0.f, vc = 0.f;
+        float va = 0.f, vb = 0.f, vc = 0.f, vay = 0.f;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
           const float mx = st[0][o], my = st[1][o];
           const float a1 = 2.f * mx * my + kC1;
@@ -157,12 +197,15 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
           va = ds * (2.f * my * (ra1 - ra2) + 2.f * mx * (rb2 - rb1));
           vb = -ds * rb2;
           vc = 2.f * ds * ra2;
+          // S is symmetric in x and y: dS/dmy swaps their roles
+          if (kPair) vay = ds * (2.f * mx * (ra1 - ra2) + 2.f * my * (rb2 - rb1));
           if (own_col && r >= kSsimRad && r < kSsimRad + kSsimTile) ssum += sv;
         }
         const int i = r * kSsimStat + c;
         pa[i] = va;
         pb[i] = vb;
         pc[i] = vc;
+        if (kPair) pay[i] = vay;
       }
     }
   }
@@ -173,41 +216,38 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
     constexpr int kRun = kRunGrad, kGroups = kSsimTile / kRun, kLen = kRun + 2 * kSsimRad;
     for (int it = t; it < kSsimStat * kGroups; it += kSsimThreads) {
       const int r = it / kGroups, c0 = (it - r * kGroups) * kRun;
-      float va[kLen], vb[kLen], vc[kLen];
+      float v[kPlanes][kLen];
 #pragma unroll
       for (int j = 0; j < kLen; j++) {
         const int i = r * kSsimStat + c0 + j;
-        va[j] = pa[i];
-        vb[j] = pb[i];
-        vc[j] = pc[i];
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) v[q][j] = r1[q * kP2 + i];
       }
 #pragma unroll
       for (int o = 0; o < kRun; o++) {
-        float sa = 0.f, sb = 0.f, sc = 0.f;
-#pragma unroll
-        for (int k = 0; k < kSsimTaps; k++) {
-          sa = __builtin_fmaf(g[k], va[o + k], sa);
-          sb = __builtin_fmaf(g[k], vb[o + k], sb);
-          sc = __builtin_fmaf(g[k], vc[o + k], sc);
-        }
         const int i = r * kSsimTile + c0 + o;
-        r2[i] = sa;
-        r2[kP3 + i] = sb;
-        r2[2 * kP3 + i] = sc;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+          float sq = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSsimTaps; k++) sq = __builtin_fmaf(g[k], v[q][o + k], sq);
+          r2[q * kP3 + i] = sq;
+        }
       }
     }
   }
   __syncthreads();
   // 4. column sums on the tile and the gradient
+  float l1sum = 0.f;
   {
     constexpr int kRun = kRunGrad, kGroups = kSsimTile / kRun, kLen = kRun + 2 * kSsimRad;
     for (int it = t; it < kSsimTile * kGroups; it += kSsimThreads) {
       const int c = it % kSsimTile, r0 = (it / kSsimTile) * kRun;
       const int gx = X0 + c;
       if (gx >= W) continue;
-      float sum[3][kRun];
+      float sum[kPlanes][kRun];
 #pragma unroll
-      for (int q = 0; q < 3; q++) {
+      for (int q = 0; q < kPlanes; q++) {
         float v[kLen];
 #pragma unroll
         for (int j = 0; j < kLen; j++) v[j] = r2[q * kP3 + (r0 + j) * kSsimTile + c];
@@ -224,12 +264,25 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
         const int gy = Y0 + r0 + o;
         if (gy >= H) break;
         const int64_t q = (int64_t)gy * W + gx;
-        const float v = sum[0][o] + 2.f * x[q] * sum[1][o] + y[q] * sum[2][o];
-        grad[q] = A.accumulate ? grad[q] + v : v;
+        const float xq = x[q], yq = y[q];
+        const float v = sum[0][o] + 2.f * xq * sum[1][o] + yq * sum[2][o];
+        if (kPair) {
+          // the L1 term of the pair, and dL/dy by the same window sums
+          const float d = xq - yq;
+          const float l1 = l1_sign(d, A.sl1);
+          const float vy = sum[3][o] + 2.f * yq * sum[1][o] + xq * sum[2][o];
+          float* __restrict__ grad_y = A.grad_y + (int64_t)bz * P;
+          grad[q] = A.accumulate ? grad[q] + (v + l1) : v + l1;
+          grad_y[q] = A.accumulate ? grad_y[q] + (vy - l1) : vy - l1;
+          l1sum += fabsf(d) * A.sl1;
+        } else {
+          grad[q] = A.accumulate ? grad[q] + v : v;
+        }
       }
     }
   }
   if (!A.loss) return;
+  ssum = A.dS * ssum + l1sum;   // this thread's share of the loss
   for (int off = 32; off > 0; off >>= 1) ssum += __shfl_xor(ssum, off, 64);
   if ((t & 63) == 0) red[t >> 6] = ssum;
   __syncthreads();
@@ -238,7 +291,7 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
     for (int w = 0; w < kSsimThreads / 64; w++) s += red[w];
     // weight * (1 - mean S): the constant once, from the first workgroup
     const bool first = bx == 0 && by == 0 && bz == 0;
-    unsafeAtomicAdd(A.loss, A.dS * s + (first ? A.weight : 0.f));
+    unsafeAtomicAdd(A.loss, s + (first ? A.weight : 0.f));
   }
 }
 
@@ -246,10 +299,15 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_grad(SsimArgs A) {
 
 hipError_t launch_ssim_grad(const SsimArgs& a, hipStream_t st) {
   if (a.W <= 0 || a.H <= 0 || a.C <= 0) return hipSuccess;
-  // one workgroup per (tile, channel), rounded up to a multiple of the eight XCDs
-  const int total = ((a.W + kSsimTile - 1) / kSsimTile) * ((a.H + kSsimTile - 1) / kSsimTile) * a.C;
+  // one workgroup per (tile, channel) -- and per depth tile in the pair form
+  // -- rounded up to a multiple of the eight XCDs
+  const bool pair = a.grad_y != nullptr;
+  const int total = ((a.W + kSsimTile - 1) / kSsimTile) * ((a.H + kSsimTile - 1) / kSsimTile) * (a.C + (pair ? 1 : 0));
   const dim3 grid((unsigned)((total + 7) / 8 * 8));
-  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSsimThreads), 0, st, a);
+  if (pair)
+    hipLaunchKernelGGL(k_ssim_grad<true>, grid, dim3(kSsimThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_ssim_grad<false>, grid, dim3(kSsimThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -22,7 +22,6 @@ struct L1Planes {
   int64_t end[3];   // cumulative flat end of each plane
 };
 
-__device__ inline float l1_sign(float d, float sc) { return d > 0.f ? sc : (d < 0.f ? -sc : 0.f); }
 
 // VEC: every plane length is a multiple of 4 and every plane 16-byte
 // aligned, so j counts groups of four floats (L.end in groups).

@@ -192,6 +192,35 @@ class Job:
                               ref(gg), _stream_ptr(dev)))
         return g
 
+    def backward_l1(self, pred: tuple, target: tuple, w_rgb: float = 1.0, w_depth: float = 0.5, w_sil: float = 0.0,
+                    map_grads: bool = True, pose_grads: bool = True, out: dict | None = None) -> dict:
+        """Backward of the L1 loss w_rgb mean|rgb - rgb*| + w_depth mean|D - D*|
+        + w_sil mean|S - S*| between the images of the last forward (`pred`,
+        as it returned them) and `target`, with the loss gradient formed
+        inside the compositing backward (ms_backward_l1): the same gradients,
+        bit for bit, as ms_l1_loss_grad then backward()."""
+        if self._gen is None or getattr(self.ws, "_ms_generation", None) != self._gen:
+            raise RuntimeError("backward_l1() needs this Job's forward state, and another forward has run in its "
+                               "workspace since (or none has run)")
+        dev = self.m["means"].device
+        flags = (0 if map_grads else _lib.MS_FLAG_POSE_GRAD_ONLY) | (0 if pose_grads else _lib.MS_FLAG_NO_POSE_GRAD)
+        g = out if out is not None else {}
+        if map_grads and out is None:
+            for k in ("means", "scales", "quats", "opacity", "colors"):
+                g[k] = torch.empty_like(self.m[k])
+        if pose_grads and out is None:
+            g["viewmat"] = torch.empty(12, dtype=torch.float32, device=dev)
+            g["twist"] = torch.empty(6, dtype=torch.float32, device=dev)
+        pi = MsImages(pred[0].data_ptr(), pred[1].data_ptr(), pred[2].data_ptr())
+        ti = MsImages(target[0].data_ptr(), target[1].data_ptr(), target[2].data_ptr())
+        gg = MsGrads(*[g[k].data_ptr() if k in g else 0
+                       for k in ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist")])
+        lib = _lib.load()
+        check(lib.ms_backward_l1(ref(self.c_map), _ptr(self.viewmat), ref(self.c_intr),
+                                 ref(opts_struct(self.opts, flags)), _ptr(self.ws), self.ws_bytes, self.cap, ref(pi),
+                                 ref(ti), float(w_rgb), float(w_depth), float(w_sil), ref(gg), _stream_ptr(dev)))
+        return g
+
     # -- inspection ---------------------------------------------------------
     def stats(self) -> dict:
         out = (ctypes.c_int64 * 7)()

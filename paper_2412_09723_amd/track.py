@@ -48,15 +48,19 @@ class Tracker:
         self._out_c, self._tgt_c, self._grad_c = _imgs(self.out), _imgs(target), _imgs(self.grad)
 
     def iteration(self, with_loss: bool = False):
-        """One iteration; with_loss also accumulates the loss value into
-        self.loss (an extra reduction)."""
+        """One iteration. The L1 loss gradient is formed inside the compositing
+        backward (no gradient planes); with_loss instead runs the separate
+        loss kernel, which also accumulates the loss value into self.loss."""
         lib = _lib.load()
         stream = ctypes.c_void_p(torch.cuda.current_stream(self.viewmat.device).cuda_stream)
         self.job.forward(out=self.out)
-        check(lib.ms_l1_loss_grad(ref(self._out_c), ref(self._tgt_c), ref(self.c_intr), self.w[0], self.w[1],
-                                  self.w[2], ref(self._grad_c),
-                                  ctypes.c_void_p(self.loss.data_ptr() if with_loss else 0), stream))
-        self.job.backward(*self.grad, map_grads=self.map_grads, pose_grads=True, out=self.g)
+        if with_loss:
+            check(lib.ms_l1_loss_grad(ref(self._out_c), ref(self._tgt_c), ref(self.c_intr), self.w[0], self.w[1],
+                                      self.w[2], ref(self._grad_c), ctypes.c_void_p(self.loss.data_ptr()), stream))
+            self.job.backward(*self.grad, map_grads=self.map_grads, pose_grads=True, out=self.g)
+        else:
+            self.job.backward_l1(self.out, self.target, *self.w, map_grads=self.map_grads, pose_grads=True,
+                                 out=self.g)
         check(lib.ms_pose_adam_step(ctypes.c_void_p(self.viewmat.data_ptr()),
                                     ctypes.c_void_p(self.g["twist"].data_ptr()),
                                     ctypes.c_void_p(self.adam.data_ptr()), self.lr, 0.9, 0.999, 1e-8, stream))
@@ -160,3 +164,40 @@ def select_candidates(means: torch.Tensor, viewmat: torch.Tensor, intr, near_z: 
     if not sync:
         return idx, count
     return idx[:int(count.item())]
+
+
+def pair_loss_grad(rgb_i: torch.Tensor, rgb_j: torch.Tensor, depth_i: torch.Tensor, depth_j: torch.Tensor,
+                   w_l1: float = 0.8, w_ssim: float = 0.2, w_geom: float = 0.1, grads: tuple | None = None,
+                   accumulate: bool = False, loss: torch.Tensor | None = None):
+    """Eq. 7 for one pair of rendered views through ms_pair_loss_grad:
+    w_l1 mean|I_i - I_j| + w_ssim (1 - mean SSIM(I_i, I_j)) + w_geom mean|D_i - D_j|
+    (the paper's weights by default) and its gradient with respect to all
+    four images. rgb_*: contiguous float32 [3, H, W], depth_*: [H, W], on one
+    device. grads: (g_rgb_i, g_rgb_j, g_depth_i, g_depth_j), written or added
+    to; loss: a one-element device tensor. Returns the four gradients."""
+    ins = (rgb_i, rgb_j, depth_i, depth_j)
+    if rgb_i.dim() != 3 or rgb_i.shape[0] != 3 or rgb_j.shape != rgb_i.shape or \
+            depth_i.shape != rgb_i.shape[1:] or depth_j.shape != rgb_i.shape[1:]:
+        raise ValueError("rgb_* must be [3, H, W] and depth_* [H, W] of one size")
+    dev = rgb_i.device
+    for t in ins:
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != dev or not t.is_cuda:
+            raise ValueError("inputs must be contiguous float32 tensors on one GPU")
+    if grads is None:
+        if accumulate:
+            raise ValueError("accumulate needs gradient tensors")
+        grads = (torch.empty_like(rgb_i), torch.empty_like(rgb_j), torch.empty_like(depth_i),
+                 torch.empty_like(depth_j))
+    for g, t in zip(grads, ins):
+        if g.shape != t.shape or g.dtype != torch.float32 or not g.is_contiguous() or g.device != dev:
+            raise ValueError("gradients must be contiguous float32 tensors shaped like the inputs, on their device")
+    if loss is not None and (loss.dtype != torch.float32 or loss.numel() < 1 or loss.device != dev):
+        raise ValueError("loss must be a float32 tensor on the inputs' device")
+    H, W = rgb_i.shape[1:]
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    lib = _lib.load()
+    check(lib.ms_pair_loss_grad(*[p(t) for t in ins], int(W), int(H), float(w_l1), float(w_ssim), float(w_geom),
+                                *[p(g) for g in grads], int(bool(accumulate)),
+                                ctypes.c_void_p(loss.data_ptr() if loss is not None else 0),
+                                ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)))
+    return grads
