@@ -21,6 +21,8 @@ rotation), and Eq. 4's Mahalanobis distance when the sources are points
       y_k = ((R_k0 x_0 + R_k1 x_1) + R_k2 x_2) + t_k,
       d = y - mu_l (per component), d2 = (d_0 d_0 + d_1 d_1) + d_2 d_2,
       accepted iff d2 <= fl32(d_max * d_max);
+  - a source whose transformed point, or a target whose mean, has a
+    non-finite coordinate takes no part;
   - covariances of Gaussians given by scales and unit quaternions:
     S = R_q diag(s^2) R_q^T;
   - one iteration: correspondences at the current T, then the Gauss-Newton
@@ -68,17 +70,24 @@ def transform32(T, x):
 
 def correspond(T, src, tgt, d_max=0.02):
     """Target index per source ([n] int64, -1 when none within d_max)."""
-    y = transform32(T, src)
+    with np.errstate(invalid="ignore", over="ignore"):
+        y = transform32(T, src)
     mu = np.asarray(tgt, np.float32)
     dmax2 = np.float32(np.float32(d_max) * np.float32(d_max))
-    tree = cKDTree(mu.T.astype(np.float64))
-    # binary64 superset of the binary32 test; the pinned distance decides
-    cand = tree.query_ball_point(y.T.astype(np.float64), r=float(d_max) * (1 + 1e-4) + 1e-6)
     out = np.full(y.shape[1], -1, np.int64)
-    for k, c in enumerate(cand):
+    # a non-finite target mean is never a neighbour, a non-finite transformed
+    # source has none
+    live = np.flatnonzero(np.all(np.isfinite(mu), axis=0))
+    qk = np.flatnonzero(np.all(np.isfinite(y), axis=0))
+    if live.size == 0 or qk.size == 0:
+        return out
+    tree = cKDTree(mu[:, live].T.astype(np.float64))
+    # binary64 superset of the binary32 test; the pinned distance decides
+    cand = tree.query_ball_point(y[:, qk].T.astype(np.float64), r=float(d_max) * (1 + 1e-4) + 1e-6)
+    for k, c in zip(qk, cand):
         if not c:
             continue
-        c = np.asarray(sorted(c), np.int64)
+        c = live[np.asarray(sorted(c), np.int64)]
         d = (y[:, k:k + 1] - mu[:, c]).astype(np.float32)
         d2 = ((d[0] * d[0]).astype(np.float32) + (d[1] * d[1]).astype(np.float32)).astype(np.float32)
         d2 = (d2 + (d[2] * d[2]).astype(np.float32)).astype(np.float32)

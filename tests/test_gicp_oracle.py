@@ -133,3 +133,21 @@ def test_correspondences_against_brute_force():
     sr = np.array([[-0.5, -after, 0.5], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]], np.float32)
     # exactly d_max from target 0: in; just beyond: none; 0.5 from both: the smaller index
     assert G.correspond(I, sr, tg, 0.5).tolist() == [0, -1, 0]
+
+
+def test_non_finite_inputs_take_no_part():
+    rng = np.random.default_rng(4)
+    tgt = rng.uniform(0, 0.2, (3, 500)).astype(np.float32)
+    src = rng.uniform(0, 0.2, (3, 300)).astype(np.float32)
+    I = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], np.float32)
+    t2, s2 = tgt.copy(), src.copy()
+    t2[:, 11] = np.nan
+    s2[:, 3] = np.inf
+    got = G.correspond(I, s2, t2, 0.02)
+    assert got[3] == -1 and 11 not in got
+    # the rest as if target 11 were absent
+    t3 = tgt.copy()
+    t3[:, 11] = 1e6
+    want = G.correspond(I, src, t3, 0.02)
+    want[3] = -1
+    assert np.array_equal(got, want)
