@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--no-views", action="store_true", help="skip the one-map multi-view mapping measurement")
     ap.add_argument("--no-prune", action="store_true", help="skip the map-pruning measurement")
     ap.add_argument("--no-alt", action="store_true", help="skip the bf16x3-backward comparison step")
+    ap.add_argument("--no-gicp", action="store_true", help="skip the Generalized-ICP alignment measurement")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
     ap.add_argument("--serve-sweep", default="2,4,8,16", help="rate multipliers of the sweep (stops at saturation)")
@@ -374,6 +375,68 @@ def select_bench(m: dict, vm, intr, calls: int = 20, max_dist: float = 3.0):
                         f"{n // 1000}k-Gaussian room map at the tracking pose",
             "ms_per_call": round(ms, 4), "selected": k, "n": n, "algorithmic_bytes": algo,
             "hbm_TB_s": round(algo / ms / 1e9, 3), "hbm_frac_of_8TB_s": round(algo / ms / 1e9 / 8.0, 3)}
+
+
+def gicp_bench(n_src: int = 200_000, iters: int = 10, reps: int = 5, cpu_sample: int = 20_000, cpu: bool = True):
+    """Generalized-ICP alignment of observed points to the room map: n_src
+    points (visible surface means with 3 mm jitter, camera frame) against
+    the 1M-Gaussian map's means and covariances, correspondences within
+    0.02 m, `iters` Gauss-Newton iterations on the device per alignment.
+    Timed with HIP events on the stream it runs on; the oracle's one
+    iteration on a bounded sample of the sources gives the CPU rate."""
+    import numpy as np
+    import torch
+    from paper_2412_09723_amd import scenes
+    from paper_2412_09723_amd.align import GeneralizedICP
+    sc, src, Tt, T0 = scenes.gicp_scene(n_src)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tgt = {"means": dev(sc.means), "scales": dev(sc.scales), "quats": dev(sc.quats)}
+    s = {"means": dev(src)}
+    g = GeneralizedICP(src.shape[1], sc.n)
+    st = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    g.build(tgt)
+    T = dev(T0)
+    g.align(s, tgt, T, iters=2)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        g.build(tgt)
+    e1.record(st)
+    Ts = [dev(T0) for _ in range(reps)]
+    for Ti in Ts:
+        _, hist = g.align(s, tgt, Ti, iters=iters, history=True)
+    e2.record(st)
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1) / reps
+    iter_ms = e1.elapsed_time(e2) / (reps * iters)
+    h = hist.cpu().numpy()
+    n = src.shape[1]
+    # per iteration: the source means read twice, the correspondence written
+    # and read, the matched target's mean, scales and quaternion read
+    nbytes = n * (12 + 4 + 12 + 4) + int(h[-1, 28]) * 40
+    out = {"workload": f"Generalized-ICP: {n // 1000}k observed points (camera frame) against the {sc.n // 1000}k-"
+                       f"Gaussian room map, correspondences within 0.02 m, {iters} iterations from 5 mm / 0.3 deg",
+           "build_ms": round(build_ms, 4), "ms_per_iteration": round(iter_ms, 4),
+           "points_per_s": round(n / (iter_ms * 1e-3), 1), "correspondences_last": int(h[-1, 28]),
+           "cost_first_last": [float(h[0, 27]), float(h[-1, 27])],
+           "pose_error_m": {"initial": float(np.abs(T0 - Tt).max()),
+                            "final": float(np.abs(Ts[-1].cpu().numpy() - Tt).max())},
+           "algorithmic_bytes_per_iteration": nbytes,
+           "hbm_TB_s": round(nbytes / (iter_ms * 1e-3) / 1e12, 3)}
+    if cpu:
+        from oracle import gicp as G
+        tcov = G.quat_cov(sc.scales, sc.quats)
+        sub = src[:, :cpu_sample]
+        t0 = time.perf_counter()
+        corr = G.correspond(T0, sub, sc.means, 0.02)
+        H, gv, cost, cnt = G.normal_equations(T0, sub, None, sc.means, tcov, corr)
+        G.gn_update(T0, H, gv)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(cpu_sample / el, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one iteration on {cpu_sample} of the points ({el:.2f} s, numpy and "
+                                         "scipy's k-d tree)"}
+    return out
 
 
 SSIM_FLOPS_PER_VALUE = 390   # separable window sums: 5 statistics x 2 x 11 FMAs + 3 partials x 2 x 11 FMAs, + ~40
@@ -717,6 +780,8 @@ def main():
         out["ssim_loss"] = ssim_bench(*ssim_frames)
         out["pair_loss"] = pair_loss_bench(tracker.out[0].clone(), target[0].clone(), tracker.out[1].clone(),
                                            target[1].clone())
+    if not args.no_gicp:
+        out["gicp"] = gicp_bench(cpu=not args.no_cpu)
     if not args.no_batch:
         del tracker, job, obs_job_state
         torch.cuda.empty_cache()

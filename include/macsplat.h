@@ -423,6 +423,64 @@ int32_t ms_select_candidates(const float* means, int64_t n, const float* viewmat
                              float near_z, float max_dist, float margin, int32_t* indices, int64_t* count,
                              void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- alignment
+ * Generalized-ICP alignment (Sec. 3.4 "3) Alignment", Eqs. 3-4; Sec. 3.5
+ * "3) Alignment", Eq. 6). A rigid transform T = [R|t] (device float[12],
+ * row-major, binary32) takes source Gaussians x_k (observed points, or
+ * another map's Gaussians) onto target Gaussians y_l (the map, or the
+ * candidates of ms_select_candidates), minimising
+ *   E(T) = sum_(k,l) r^T (R S_k R^T + S_l + eps I)^-1 r,   r = T x_k - y_l,
+ * with S = R_q diag(s^2) R_q^T from a Gaussian's scales and quaternion (zero
+ * for a map without scales: points, which gives Eq. 4's Mahalanobis
+ * distance under the map covariance). Eq. 6 as printed adds S_k unrotated;
+ * here it is rotated by T (Generalized-ICP's form).
+ * Correspondences: each source takes the nearest target mean within d_max
+ * (the paper's point-selection distance, 0.02 m), inclusive, ties to the
+ * smaller target index, decided in binary32 in this order without fused
+ * operations: y_i = ((R_i0 x_0 + R_i1 x_1) + R_i2 x_2) + t_i;
+ * d = y - mu; d2 = (d_0 d_0 + d_1 d_1) + d_2 d_2 <= fl(d_max d_max).
+ * An iteration: correspondences at T, the Gauss-Newton normal equations in
+ * binary64 (J = [I | -[T x]_x] for the left twist xi = (rho, phi),
+ * H = sum J^T M J, g = sum J^T M r with M = (R S_k R^T + S_l + eps I)^-1 at
+ * T), xi = -(H + lam I)^-1 g with lam = 1e-12 trace(H) / 6, and
+ * T <- exp(xi^) T stored in binary32; with fewer than 6 correspondences T
+ * stays. Sums are returned as 29 doubles: H's upper triangle row by row
+ * (21), g (6), the cost E, the number of correspondences.
+ * The target grid is built once (ms_gicp_build) and serves every call
+ * after it on the same workspace. Maps: device [3][n] means; scales [3][n]
+ * and quats [4][n] both given or both NULL (points); opacity and colors are
+ * not read. Coordinates must be finite to take part (others are skipped)
+ * and below 1e6 m in magnitude. Every call is enqueued on `stream`; errors
+ * (MS_ERR_INVALID_ARG: null or inconsistent arrays, sizes above the
+ * configuration, non-finite or non-positive d_max, negative eps;
+ * MS_ERR_WORKSPACE) enqueue nothing. */
+typedef struct {
+  int64_t max_src, max_tgt;   /* largest source and target counts the workspace serves */
+  float d_max;                /* correspondence distance, metres, > 0 */
+  float eps;                  /* covariance regularisation, m^2, >= 0 (1e-6 suggested) */
+} ms_gicp_config;
+
+size_t ms_gicp_workspace_bytes(const ms_gicp_config* cfg);
+/* Hashed grid of the target means: all of `tgt` (tgt_idx NULL, m = tgt->n)
+ * or its m Gaussians listed in tgt_idx (device int32, e.g. the candidates of
+ * ms_select_candidates). m <= cfg->max_tgt. */
+int32_t ms_gicp_build(const ms_gicp_config* cfg, const ms_map* tgt, const int32_t* tgt_idx, int64_t m,
+                      void* workspace, size_t ws_bytes, void* stream);
+/* Correspondences at T: corr (device int32 [src->n]) receives each source's
+ * target map index, or -1. */
+int32_t ms_gicp_correspond(const ms_gicp_config* cfg, const ms_map* src, const float* T, int32_t* corr,
+                           void* workspace, size_t ws_bytes, void* stream);
+/* Normal equations at T for the correspondences corr (device int32
+ * [src->n], target map indices or -1): out, device double[29]. */
+int32_t ms_gicp_normal_equations(const ms_gicp_config* cfg, const ms_map* src, const ms_map* tgt, const float* T,
+                                 const int32_t* corr, double* out, void* workspace, size_t ws_bytes, void* stream);
+/* `iters` iterations from T, updating T in place on the device (no host
+ * synchronisation). corr: device int32 [src->n] receiving the last
+ * iteration's correspondences, or NULL. hist: device double[iters][29]
+ * receiving each iteration's sums, or NULL. */
+int32_t ms_gicp_align(const ms_gicp_config* cfg, const ms_map* src, const ms_map* tgt, float* T, int32_t iters,
+                      int32_t* corr, double* hist, void* workspace, size_t ws_bytes, void* stream);
+
 /* One Adam step on the pose's left twist (Sec. 3.1: poses in SE(3)).
  * viewmat: device float[12] [R|t], updated in place to exp(-step^) [R|t]
  * with step = lr * mhat / (sqrt(vhat) + eps); twist_grad: device float[6]
@@ -454,7 +512,8 @@ enum {
   /* helpers, timed in their own calls */
   MS_STAGE_LOSS = 9,           /* ms_l1_loss_grad, ms_ssim_loss_grad */
   MS_STAGE_POSE_STEP = 10,     /* ms_pose_adam_step */
-  MS_STAGE_COUNT = 11
+  MS_STAGE_GICP = 11,          /* ms_gicp_* */
+  MS_STAGE_COUNT = 12
 };
 typedef struct ms_profiler ms_profiler;
 int32_t ms_profiler_create(uint32_t stage_mask, int32_t capacity, ms_profiler** out);

@@ -30,6 +30,7 @@ EXPORTED = [
     "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes", "ms_backward_l1",
     "ms_forward", "ms_backward", "ms_read_stats", "ms_state_view_get",
     "ms_l1_loss_grad", "ms_ssim_loss_grad", "ms_pair_loss_grad", "ms_prune_workspace_bytes", "ms_prune", "ms_prune_noalloc", "ms_select_workspace_bytes", "ms_select_candidates",
+    "ms_gicp_workspace_bytes", "ms_gicp_build", "ms_gicp_correspond", "ms_gicp_normal_equations", "ms_gicp_align",
     "ms_pose_adam_step",
     "ms_profiler_create", "ms_profiler_destroy", "ms_profiler_attach", "ms_profiler_read",
     "ms_batch_workspace_bytes", "ms_forward_batch", "ms_backward_batch", "ms_batch_read_stats",
@@ -37,7 +38,7 @@ EXPORTED = [
 MS_MAX_BATCH = 12
 
 STAGES = ["project", "bin", "composite", "composite_bwd", "project_bwd", "bin_count", "bin_emit", "bin_sort",
-          "pose", "loss", "pose_step"]
+          "pose", "loss", "pose_step", "gicp"]
 
 
 class MsIntrinsics(ctypes.Structure):
@@ -63,6 +64,11 @@ class MsGrads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
                 ("opacity", ctypes.c_void_p), ("colors", ctypes.c_void_p), ("viewmat", ctypes.c_void_p),
                 ("twist", ctypes.c_void_p)]
+
+
+class MsGicpConfig(ctypes.Structure):
+    _fields_ = [("max_src", ctypes.c_int64), ("max_tgt", ctypes.c_int64), ("d_max", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class MsJob(ctypes.Structure):
@@ -132,6 +138,16 @@ def load():
     lib.ms_select_candidates.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(MsIntrinsics), F, F, F, P, P, P,
                                          ctypes.c_size_t, P]
     lib.ms_select_candidates.restype = ctypes.c_int32
+    lib.ms_gicp_workspace_bytes.argtypes = [P]
+    lib.ms_gicp_workspace_bytes.restype = ctypes.c_size_t
+    lib.ms_gicp_build.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_size_t, P]
+    lib.ms_gicp_build.restype = ctypes.c_int32
+    lib.ms_gicp_correspond.argtypes = [P, P, P, P, P, ctypes.c_size_t, P]
+    lib.ms_gicp_correspond.restype = ctypes.c_int32
+    lib.ms_gicp_normal_equations.argtypes = [P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    lib.ms_gicp_normal_equations.restype = ctypes.c_int32
+    lib.ms_gicp_align.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    lib.ms_gicp_align.restype = ctypes.c_int32
     lib.ms_pose_adam_step.argtypes = [P, P, P, F, F, F, F, P]
     lib.ms_pose_adam_step.restype = ctypes.c_int32
     lib.ms_profiler_create.argtypes = [ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmacsplat.so")
-SOURCES = ["api.cpp", "project.hip", "bin.hip", "composite.hip", "track.hip", "ssim.hip", "prune.hip", "select.hip"]
+SOURCES = ["api.cpp", "project.hip", "bin.hip", "composite.hip", "track.hip", "ssim.hip", "prune.hip", "select.hip", "gicp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

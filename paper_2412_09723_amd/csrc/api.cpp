@@ -864,6 +864,115 @@ int32_t ms_select_candidates(const float* means, int64_t n, const float* viewmat
   return MS_OK;
 }
 
+namespace {
+int32_t check_gicp_cfg(const ms_gicp_config* c) {
+  if (!c) return fail(MS_ERR_INVALID_ARG, "null configuration");
+  if (c->max_src < 0 || c->max_tgt < 0 || c->max_src > INT32_MAX || c->max_tgt > INT32_MAX)
+    return fail(MS_ERR_INVALID_ARG, "counts outside [0, 2^31 - 1]");
+  if (!std::isfinite(c->d_max) || !(c->d_max > 0.f)) return fail(MS_ERR_INVALID_ARG, "d_max must be finite and > 0");
+  if (!std::isfinite(c->eps) || c->eps < 0.f) return fail(MS_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  return MS_OK;
+}
+
+// A map of means with optional (scales, quats); opacity and colors unused.
+int32_t check_gicp_map(const ms_map* m, int64_t limit, const char* what) {
+  if (!m) return fail(MS_ERR_INVALID_ARG, "null %s map", what);
+  if (m->n < 0 || m->n > limit)
+    return fail(MS_ERR_INVALID_ARG, "%s count %lld outside [0, %lld]", what, (long long)m->n, (long long)limit);
+  if (m->n > 0 && !m->means) return fail(MS_ERR_INVALID_ARG, "null %s means", what);
+  if ((m->scales == nullptr) != (m->quats == nullptr))
+    return fail(MS_ERR_INVALID_ARG, "%s scales and quats must both be given or both be NULL", what);
+  return MS_OK;
+}
+
+int32_t check_gicp_ws(const GicpPlan& p, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(MS_ERR_WORKSPACE, "null workspace");
+  if (((uintptr_t)ws & 255) != 0) return fail(MS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < p.bytes) return fail(MS_ERR_WORKSPACE, "workspace too small");
+  return MS_OK;
+}
+}  // namespace
+
+size_t ms_gicp_workspace_bytes(const ms_gicp_config* cfg) {
+  if (!cfg || cfg->max_src < 0 || cfg->max_tgt < 0 || !(cfg->d_max > 0.f)) return 0;
+  return gicp_plan(cfg->max_src, cfg->max_tgt, cfg->d_max).bytes;
+}
+
+int32_t ms_gicp_build(const ms_gicp_config* cfg, const ms_map* tgt, const int32_t* tgt_idx, int64_t m,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_gicp_cfg(cfg);
+  if (s == MS_OK) s = check_gicp_map(tgt, INT32_MAX, "target");
+  if (s != MS_OK) return s;
+  if (m < 0 || m > cfg->max_tgt) return fail(MS_ERR_INVALID_ARG, "m = %lld outside [0, max_tgt]", (long long)m);
+  if (!tgt_idx && m != tgt->n) return fail(MS_ERR_INVALID_ARG, "without an index list m must equal the map's n");
+  if (tgt_idx && m > 0 && tgt->n == 0) return fail(MS_ERR_INVALID_ARG, "indices into an empty map");
+  const GicpPlan p = gicp_plan(cfg->max_src, cfg->max_tgt, cfg->d_max);
+  s = check_gicp_ws(p, workspace, ws_bytes);
+  if (s != MS_OK) return s;
+  StageTimer tm(MS_STAGE_GICP, (hipStream_t)stream);
+  hipError_t e = gicp_build(p, tgt->means, tgt->n, tgt_idx, m, (char*)workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "alignment grid");
+  return MS_OK;
+}
+
+int32_t ms_gicp_correspond(const ms_gicp_config* cfg, const ms_map* src, const float* T, int32_t* corr,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_gicp_cfg(cfg);
+  if (s == MS_OK) s = check_gicp_map(src, cfg->max_src, "source");
+  if (s != MS_OK) return s;
+  if (!T || (src->n > 0 && !corr)) return fail(MS_ERR_INVALID_ARG, "null pose or correspondence array");
+  const GicpPlan p = gicp_plan(cfg->max_src, cfg->max_tgt, cfg->d_max);
+  s = check_gicp_ws(p, workspace, ws_bytes);
+  if (s != MS_OK) return s;
+  StageTimer tm(MS_STAGE_GICP, (hipStream_t)stream);
+  hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, corr, (char*)workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "correspondences");
+  return MS_OK;
+}
+
+int32_t ms_gicp_normal_equations(const ms_gicp_config* cfg, const ms_map* src, const ms_map* tgt, const float* T,
+                                 const int32_t* corr, double* out, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_gicp_cfg(cfg);
+  if (s == MS_OK) s = check_gicp_map(src, cfg->max_src, "source");
+  if (s == MS_OK) s = check_gicp_map(tgt, INT32_MAX, "target");
+  if (s != MS_OK) return s;
+  if (!T || !out || (src->n > 0 && !corr)) return fail(MS_ERR_INVALID_ARG, "null pose, output or correspondences");
+  const GicpPlan p = gicp_plan(cfg->max_src, cfg->max_tgt, cfg->d_max);
+  s = check_gicp_ws(p, workspace, ws_bytes);
+  if (s != MS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  StageTimer tm(MS_STAGE_GICP, st);
+  hipError_t e = gicp_normal(p, *src, *tgt, T, corr, cfg->eps, (char*)workspace, st);
+  if (e == hipSuccess) e = gicp_solve(p, src->n, nullptr, out, nullptr, (char*)workspace, st, false);
+  if (e != hipSuccess) return hip_fail(e, "normal equations");
+  return MS_OK;
+}
+
+int32_t ms_gicp_align(const ms_gicp_config* cfg, const ms_map* src, const ms_map* tgt, float* T, int32_t iters,
+                      int32_t* corr, double* hist, void* workspace, size_t ws_bytes, void* stream) {
+  int32_t s = check_gicp_cfg(cfg);
+  if (s == MS_OK) s = check_gicp_map(src, cfg->max_src, "source");
+  if (s == MS_OK) s = check_gicp_map(tgt, INT32_MAX, "target");
+  if (s != MS_OK) return s;
+  if (!T) return fail(MS_ERR_INVALID_ARG, "null pose");
+  if (iters < 0 || iters > 1000) return fail(MS_ERR_INVALID_ARG, "iters = %d outside [0, 1000]", iters);
+  const GicpPlan p = gicp_plan(cfg->max_src, cfg->max_tgt, cfg->d_max);
+  s = check_gicp_ws(p, workspace, ws_bytes);
+  if (s != MS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  int32_t* c = corr ? corr : at<int32_t>(ws, p.corr);
+  StageTimer tm(MS_STAGE_GICP, st);
+  for (int it = 0; it < iters; it++) {
+    hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, c, ws, st);
+    if (e == hipSuccess) e = gicp_normal(p, *src, *tgt, T, c, cfg->eps, ws, st);
+    if (e == hipSuccess)
+      e = gicp_solve(p, src->n, T, at<double>(ws, p.out), hist ? hist + 29 * (int64_t)it : nullptr, ws, st, true);
+    if (e != hipSuccess) return hip_fail(e, "alignment iteration");
+  }
+  return MS_OK;
+}
+
 int32_t ms_pose_adam_step(float* viewmat, const float* twist_grad, float* state, float lr, float beta1, float beta2,
                           float eps, void* stream) {
   if (!viewmat || !twist_grad || !state) return fail(MS_ERR_INVALID_ARG, "null argument");

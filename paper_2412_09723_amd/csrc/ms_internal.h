@@ -265,6 +265,22 @@ size_t prune_workspace_bytes(int64_t n);
 // block b, *total the sum.
 hipError_t launch_block_offsets(uint32_t* bcount, int64_t nblocks, int64_t* total, hipStream_t st);
 
+// Generalized-ICP workspace plan (gicp.hip): byte offsets of its regions.
+struct GicpPlan {
+  int64_t nbuckets, max_src, max_tgt, nblocks;
+  double cell;
+  size_t bcount, fillpos, bstart, bsum, total, entries, corr, partial, out, bytes;
+};
+GicpPlan gicp_plan(int64_t max_src, int64_t max_tgt, float d_max);
+hipError_t gicp_build(const GicpPlan& p, const float* mu, int64_t n, const int32_t* idx, int64_t m, char* ws,
+                      hipStream_t st);
+hipError_t gicp_correspond(const GicpPlan& p, const float* src, int64_t n, const float* T, float d_max,
+                           int32_t* corr, char* ws, hipStream_t st);
+hipError_t gicp_normal(const GicpPlan& p, const ms_map& src, const ms_map& tgt, const float* T, const int32_t* corr,
+                       float eps, char* ws, hipStream_t st);
+hipError_t gicp_solve(const GicpPlan& p, int64_t n_src, float* T, double* out, double* hist, char* ws, hipStream_t st,
+                      bool update);
+
 struct SelectArgs {
   const float* means;      // [3][n]
   int64_t n;

@@ -287,3 +287,34 @@ def poisson_trace(n_agents: int, rate_per_agent: float, duration_s: float, seed:
             k += 1
     events.sort()
     return events
+
+
+def gicp_scene(n_src: int = 200_000, seed: int = 0, noise: float = 0.003, deg: float = 0.3, metres: float = 0.005,
+               max_dist: float = 4.0):
+    """Inputs of the alignment workload: the room map of `room_view`, and
+    n_src observed points -- means of the map's visible surface Gaussians
+    (in front of the camera, within max_dist) with N(0, noise) jitter,
+    expressed in the camera frame. Returns (scene, src_means [3, n_src]
+    float32 camera frame, T_true [12] camera-to-world float32, T0 [12]: T_true
+    moved by `metres` along a random direction and `deg` degrees about a
+    random axis, as an initial estimate)."""
+    sc = room_view()
+    rng = np.random.default_rng(7000 + seed)
+    V = sc.viewmat.astype(np.float64).reshape(3, 4)
+    R, t = V[:, :3], V[:, 3]
+    n_surf = int(0.7 * sc.n)                              # the planar part of the room generator
+    p = R @ sc.means[:, :n_surf].astype(np.float64) + t[:, None]
+    ok = np.flatnonzero((p[2] > 0.3) & (np.linalg.norm(p, axis=0) < max_dist) &
+                        (np.abs(p[0] / p[2]) < 1.0) & (np.abs(p[1] / p[2]) < 0.6))
+    pick = rng.choice(ok, size=min(n_src, ok.size), replace=False)
+    src = p[:, pick] + rng.normal(0.0, noise, (3, pick.size))
+    Tw = np.concatenate([R.T, (-R.T @ t)[:, None]], axis=1)   # camera to world
+    ax = rng.standard_normal(3)
+    ax /= np.linalg.norm(ax)
+    dr = rng.standard_normal(3)
+    dr /= np.linalg.norm(dr)
+    th = np.deg2rad(deg)
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    Rd = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K)
+    T0 = np.concatenate([Rd @ Tw[:, :3], (Rd @ Tw[:, 3] + metres * dr)[:, None]], axis=1)
+    return (sc, src.astype(np.float32), Tw.reshape(12).astype(np.float32), T0.reshape(12).astype(np.float32))

@@ -274,3 +274,36 @@ def test_select_rejects_bad_arguments(lib):
     assert call(idx=FAKE + 64) == _lib.MS_ERR_INVALID_ARG          # indices over the means
     assert call(ws=0) == _lib.MS_ERR_WORKSPACE
     assert call(wsb=lib.ms_select_workspace_bytes(4096) - 1) == _lib.MS_ERR_WORKSPACE
+
+
+def test_gicp_rejects_bad_arguments(lib):
+    from paper_2412_09723_amd._lib import MsGicpConfig
+    cfg = MsGicpConfig(1000, 2000, 0.02, 1e-6)
+    nb = lib.ms_gicp_workspace_bytes(ref(cfg))
+    assert nb > 0
+    assert lib.ms_gicp_workspace_bytes(ref(MsGicpConfig(1000, 2000, 0.0, 1e-6))) == 0
+    pts = MsMap(1000, FAKE, 0, 0, 0, 0)
+    tgt = MsMap(2000, FAKE + 0x100000, FAKE + 0x200000, FAKE + 0x300000, 0, 0)
+    ws = ctypes.c_void_p(FAKE + 0x1000000)
+    T = ctypes.c_void_p(FAKE + 0x400000)
+    st = None
+
+    def build(c=cfg, t=tgt, idx=None, m=2000, w=ws, wb=nb):
+        return lib.ms_gicp_build(ref(c), ref(t), ctypes.c_void_p(idx or 0), m, w, wb, st)
+    assert build(c=MsGicpConfig(1000, 2000, float("nan"), 1e-6)) == _lib.MS_ERR_INVALID_ARG
+    assert build(c=MsGicpConfig(1000, 2000, 0.02, -1.0)) == _lib.MS_ERR_INVALID_ARG
+    assert build(m=2001, t=MsMap(2001, tgt.means, tgt.scales, tgt.quats, 0, 0)) == _lib.MS_ERR_INVALID_ARG
+    assert build(m=1999) == _lib.MS_ERR_INVALID_ARG                     # m != n without an index list
+    assert build(t=MsMap(2000, tgt.means, tgt.scales, 0, 0, 0)) == _lib.MS_ERR_INVALID_ARG   # scales without quats
+    assert build(w=ctypes.c_void_p(0)) == _lib.MS_ERR_WORKSPACE
+    assert build(w=ctypes.c_void_p(FAKE + 0x1000010)) == _lib.MS_ERR_WORKSPACE   # misaligned
+    assert build(wb=nb - 1) == _lib.MS_ERR_WORKSPACE
+    corr = ctypes.c_void_p(FAKE + 0x500000)
+    assert lib.ms_gicp_correspond(ref(cfg), ref(MsMap(1001, FAKE, 0, 0, 0, 0)), T, corr, ws, nb, st) == \
+        _lib.MS_ERR_INVALID_ARG                                          # more sources than configured
+    assert lib.ms_gicp_correspond(ref(cfg), ref(pts), ctypes.c_void_p(0), corr, ws, nb, st) == _lib.MS_ERR_INVALID_ARG
+    out = ctypes.c_void_p(FAKE + 0x600000)
+    assert lib.ms_gicp_normal_equations(ref(cfg), ref(pts), ref(tgt), T, corr, ctypes.c_void_p(0), ws, nb, st) == \
+        _lib.MS_ERR_INVALID_ARG
+    assert lib.ms_gicp_align(ref(cfg), ref(pts), ref(tgt), T, -1, corr, None, ws, nb, st) == _lib.MS_ERR_INVALID_ARG
+    assert lib.ms_gicp_align(ref(cfg), ref(pts), ref(tgt), T, 1001, corr, None, ws, nb, st) == _lib.MS_ERR_INVALID_ARG
