@@ -50,6 +50,11 @@ def kernel_names(args) -> dict:
     fwd = f"k_composite_fwd_s<{t}>" if args.fwd_records == "scalar" else f"k_composite_fwd<{t}, {wb}>"
     bwd = {"mfma": f"k_composite_bwd_f<{t}>", "mfma_bf16x3": f"k_composite_bwd_m<{t}>",
            "lds": f"k_composite_bwd<{t}, {wb}>", "scalar": f"k_composite_bwd_s<{t}>"}[args.bwd_records]
+    if args.schedule != "grid":   # persistent launches, each after the single-workgroup queue sort
+        if args.fwd_records == "lds":
+            fwd = "k_tile_order + " + fwd.replace("<", "_q<", 1)
+        if args.bwd_records.startswith("mfma"):
+            bwd = "k_tile_order + " + bwd.replace("<", "_q<", 1)
     return {"project": "k_project_fwd", "bin_count": "k_unit_count + k_unit_scan", "bin_emit": "k_unit_emit",
             "bin_sort": "k_bin_sort", "composite": fwd, "composite_bwd": bwd, "project_bwd": "k_project_bwd",
             "pose": "k_pose_final", "loss": "k_l1_grad", "pose_step": "k_pose_adam"}
@@ -115,7 +120,10 @@ def parse():
     ap.add_argument("--no-ssim", action="store_true", help="skip the SSIM loss measurement")
     ap.add_argument("--no-views", action="store_true", help="skip the one-map multi-view mapping measurement")
     ap.add_argument("--no-prune", action="store_true", help="skip the map-pruning measurement")
-    ap.add_argument("--no-alt", action="store_true", help="skip the bf16x3-backward comparison step")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the comparison steps (bf16x3 backward, persistent tile-queue schedules)")
+    ap.add_argument("--schedule", choices=("grid", "queue", "xcd_queue"), default="grid",
+                    help="compositing launch: one workgroup per tile, or persistent over a tile queue")
     ap.add_argument("--no-gicp", action="store_true", help="skip the Generalized-ICP alignment measurement")
     ap.add_argument("--serve-duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals at the base rate (30 jobs/s per agent)")
@@ -559,14 +567,23 @@ def batch_bench(rounds: int):
 
     ms_plain = timed(autotune._PlainStep(maps, vms, intrs, ups, plain.options))
     ms_batch = timed(autotune._BatchStep(maps, vms, intrs, ups, batched.options))
+    # the compositing schedules at the batch's tile and wave batch
+    sched = {}
+    for s in autotune.SCHEDULES:
+        step = autotune._BatchStep(maps, vms, intrs, ups, dataclasses.replace(batched.options, schedule=s))
+        sched[s] = round(timed(step), 4)
+        step.release()
+        torch.cuda.empty_cache()
     px = sum(i.pixels for i in intrs)
-    opt = lambda o: {"tile": o.tile, "wave_batch": o.wave_batch, "bin_tile": o.bin_tile, "bwd": o.bwd_records}
+    opt = lambda o: {"tile": o.tile, "wave_batch": o.wave_batch, "bin_tile": o.bin_tile, "bwd": o.bwd_records,
+                     "schedule": o.schedule}
     return {"workload": "4 agents, room maps of 200k/600k/1.2M/2M Gaussians, 1200x680 each, one forward+backward "
                         "of every agent per round",
             "rounds": rounds, "plain_ms_per_round": round(ms_plain, 4), "batched_ms_per_round": round(ms_batch, 4),
             "plain_Mpix_s": round(px / ms_plain / 1e3, 2), "batched_Mpix_s": round(px / ms_batch / 1e3, 2),
             "speedup": round(ms_plain / ms_batch, 3), "plain_options": opt(plain.options),
-            "batched_options": opt(batched.options), "autotune_ms": {"plain": plain.table, "batched": batched.table}}
+            "batched_options": opt(batched.options), "batched_ms_by_schedule": sched,
+            "autotune_ms": {"plain": plain.table, "batched": batched.table}}
 
 
 def serve_bench(duration: float, sweep: list, sweep_duration: float, budget_gb: float, small_gb: float):
@@ -654,7 +671,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     m = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), colors=t(sc.colors))
     opts = raster.RenderOptions(tile=args.tile, wave_batch=args.wave_batch, fwd_records=args.fwd_records,
-                                bwd_records=args.bwd_records, bin_tile=args.bin_tile)
+                                bwd_records=args.bwd_records, bin_tile=args.bin_tile, schedule=args.schedule)
     # observed frame: render from the pose perturbed by 2 cm / 1 degree
     vm_obs = t(scenes.perturb_pose(sc.viewmat, scenes.rng_for(1, 0, salt=3)))
     obs_job = raster.Job(m, vm_obs, sc.intr, raster.RenderOptions(tile=args.tile, wave_batch=args.wave_batch,
@@ -739,7 +756,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "tracking step: 10 x (RGB-D forward + L1 loss grad + full backward + pose Adam), "
                                f"1M-Gaussian 6x4x3 m room, 1200x680, tile {args.tile}, wave batch {args.wave_batch}, "
-                               f"bin tile {args.bin_tile or args.tile}, {args.fwd_records}/{args.bwd_records} records"
+                               f"bin tile {args.bin_tile or args.tile}, {args.fwd_records}/{args.bwd_records} records, "
+                               f"{args.schedule} compositing schedule"
                                + (", pose-only gradients" if args.pose_only else ""),
                    "gaussians": sc.n, "width": W, "height": H, "iterations_per_step": args.iters},
         "arithmetic": ARITHMETIC[args.bwd_records],
@@ -749,28 +767,37 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
-    if not args.no_alt and args.bwd_records == "mfma":
-        # the same step with the backward's products on bf16 high/low parts
-        alt_opts = dataclasses.replace(opts, bwd_records="mfma_bf16x3")
+    def alt_step(alt_opts, steps=5):
+        """The same tracking step with other options: ms per step and the
+        compositing stages' average launch times."""
         alt = Tracker(m, t(sc.viewmat), target, sc.intr, alt_opts, lr=1e-3, w_depth=0.5,
                       map_grads=not args.pose_only)
         for _ in range(2):
             alt.step(args.iters)
-        aprof = _lib.Profiler(stages=("composite_bwd",))
+        aprof = _lib.Profiler(stages=("composite", "composite_bwd"))
         torch.cuda.synchronize()
         with aprof:
             ta = time.perf_counter()
-            for _ in range(5):
+            for _ in range(steps):
                 alt.step(args.iters)
             torch.cuda.synchronize()
             tb = time.perf_counter()
-        ab = aprof.read()["composite_bwd"]
+        r = aprof.read()
         aprof.close()
-        a_ms = (tb - ta) * 1e3 / 5
-        out["bwd_bf16x3"] = {"arithmetic": ARITHMETIC["mfma_bf16x3"], "kernel": "k_composite_bwd_m<16>",
-                             "Mpix_s": round(px / (a_ms / 1e3) / 1e6, 2), "ms_per_step": round(a_ms, 3),
-                             "composite_bwd_ms": round(ab[0] / max(ab[1], 1), 4)}
         del alt
+        a_ms = (tb - ta) * 1e3 / steps
+        return {"Mpix_s": round(px / (a_ms / 1e3) / 1e6, 2), "ms_per_step": round(a_ms, 3),
+                "composite_ms": round(r["composite"][0] / max(r["composite"][1], 1), 4),
+                "composite_bwd_ms": round(r["composite_bwd"][0] / max(r["composite_bwd"][1], 1), 4)}
+
+    if not args.no_alt and args.bwd_records == "mfma":
+        # the same step with the backward's products on bf16 high/low parts
+        a = alt_step(dataclasses.replace(opts, bwd_records="mfma_bf16x3"))
+        out["bwd_bf16x3"] = {"arithmetic": ARITHMETIC["mfma_bf16x3"], "kernel": "k_composite_bwd_m<16>", **a}
+    if not args.no_alt:
+        # compositing launched per tile against the persistent tile-queue schedules
+        out["schedules"] = {s: alt_step(dataclasses.replace(opts, schedule=s))
+                            for s in ("grid", "queue", "xcd_queue")}
     if not args.no_prune:
         out["prune"] = prune_bench(m)
         out["select"] = select_bench(m, t(sc.viewmat), sc.intr)

@@ -105,7 +105,7 @@
 extern "C" {
 #endif
 
-#define MS_ABI_VERSION 4
+#define MS_ABI_VERSION 5
 
 typedef enum {
   MS_OK = 0,
@@ -140,6 +140,16 @@ typedef struct {
                                        (hi*hi + hi*lo + lo*hi, about 16 significant bits per term,
                                        fp32 accumulation; v_mfma_f32_16x16x32_bf16). Faster, less
                                        precise; not the default */
+#define MS_FLAG_TILE_QUEUE 128u     /* compositing (the LDS-staged forward and the MFMA backward) as a
+                                       persistent launch: as many workgroups as the device holds at once
+                                       take tiles from a queue sorted by expected work, longest first (the
+                                       bin's list length for the forward, the forward's per-sub-block list
+                                       depth for the backward). Same results as the one-workgroup-per-tile
+                                       grid up to float summation order. The scalar-record kernels and the
+                                       LDS backward ignore it */
+#define MS_FLAG_XCD_QUEUES 256u     /* with MS_FLAG_TILE_QUEUE: eight queues, one per XCD, dealt the
+                                       sorted tiles round-robin; a workgroup drains its own XCD's queue
+                                       first, then the others in turn */
 
 /* Launch options. tile: edge in pixels of the screen tile one compositing
  * workgroup owns, 8 | 16 | 32. bin_tile: edge of the tiles whose
@@ -307,6 +317,13 @@ typedef struct {
                                (kind 1: zero outside a backward pass) */
   int32_t pair_rank_bits;   /* 0: separate arrays; > 0: each pair is one word tile << bits | rank */
   int32_t list_kind;
+  uint32_t* tile_order;     /* [tiles] compositing tiles in the order of the last persistent launch's
+                               queue (MS_FLAG_TILE_QUEUE), longest expected work first */
+  uint32_t* tile_cost;      /* [tiles][tile_waves] per 8x8 sub-block of each compositing tile (row-major
+                               in the tile): the deepest list position + 1 any of its pixels composited
+                               in the last LDS-staged forward, 0 for none */
+  int32_t tiles;            /* compositing tiles (tile edge opts->tile) */
+  int32_t tile_waves;       /* (tile / 8)^2 */
 } ms_state_view;
 
 /* Record layout (16 x 32-bit words per visible Gaussian):

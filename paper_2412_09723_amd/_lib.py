@@ -25,6 +25,8 @@ MS_FLAG_SCALAR_BWD = 8
 MS_FLAG_MFMA_BWD = 16
 MS_FLAG_ACCUMULATE_MAP_GRADS = 32
 MS_FLAG_BWD_BF16X3 = 64
+MS_FLAG_TILE_QUEUE = 128
+MS_FLAG_XCD_QUEUES = 256
 
 EXPORTED = [
     "ms_abi_version", "ms_status_string", "ms_last_error", "ms_workspace_bytes", "ms_backward_l1",
@@ -80,7 +82,9 @@ class MsStateView(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in (
         "depth_key", "sorted_index", "rank_of", "pair_tile", "pair_rank", "tile_range", "records",
         "tfinal", "last", "counters", "grad2d")] + [("pair_rank_bits", ctypes.c_int32),
-                                                     ("list_kind", ctypes.c_int32)]
+                                                     ("list_kind", ctypes.c_int32),
+                                                     ("tile_order", ctypes.c_void_p), ("tile_cost", ctypes.c_void_p),
+                                                     ("tiles", ctypes.c_int32), ("tile_waves", ctypes.c_int32)]
 
 
 _lib = None

@@ -21,6 +21,7 @@ from . import raster
 
 TILES = (8, 16, 32)
 WAVE_BATCHES = (32, 64, 128)
+SCHEDULES = ("grid", "queue", "xcd_queue")
 
 
 def shape_key(ns, intrs) -> str:
@@ -32,19 +33,24 @@ def shape_key(ns, intrs) -> str:
 class TuneResult:
     options: raster.RenderOptions
     ms: float
-    table: dict          # "tile/wave_batch" -> median ms of one forward + backward of all jobs
+    table: dict          # "tile/wave_batch" (grid launches) and "tile/wave_batch/schedule" (the other
+                         # compositing schedules at the best tile and batch) -> median ms of one
+                         # forward + backward of all jobs
 
 
 class Autotuner:
-    """Chooses RenderOptions (tile, wave_batch) for a set of jobs.
+    """Chooses RenderOptions (tile, wave_batch, compositing schedule) for a
+    set of jobs: every (tile, wave_batch) pair with one workgroup per tile,
+    then the persistent tile-queue schedules at the best pair.
 
     `base` supplies every other option (bin tile, record paths, near plane);
     the bin tile is raised to the tile edge where it is smaller."""
 
     def __init__(self, base: raster.RenderOptions = raster.RenderOptions(), tiles=TILES,
-                 wave_batches=WAVE_BATCHES, reps: int = 3, cache_path: str | None = None):
+                 wave_batches=WAVE_BATCHES, reps: int = 3, cache_path: str | None = None, schedules=SCHEDULES):
         self.base = base
         self.candidates = [(t, w) for t in tiles for w in wave_batches]
+        self.schedules = [s for s in schedules if s != "grid"]
         self.reps = reps
         self.cache_path = cache_path
         self.cache: dict[str, dict] = {}
@@ -52,9 +58,10 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
-    def _options(self, tile: int, wb: int) -> raster.RenderOptions:
+    def _options(self, tile: int, wb: int, schedule: str = "grid") -> raster.RenderOptions:
         bin_tile = self.base.bin_tile if self.base.bin_tile == 0 else max(self.base.bin_tile, tile)
-        return dataclasses.replace(self.base, tile=tile, wave_batch=wb, bin_tile=bin_tile, check=True)
+        return dataclasses.replace(self.base, tile=tile, wave_batch=wb, bin_tile=bin_tile, check=True,
+                                   schedule=schedule)
 
     @staticmethod
     def _time(step, reps: int) -> float:
@@ -85,24 +92,32 @@ class Autotuner:
     def _tune(self, key: str, make) -> TuneResult:
         if key in self.cache:
             c = self.cache[key]
-            return TuneResult(self._options(c["tile"], c["wave_batch"]), c["ms"], c["table"])
+            return TuneResult(self._options(c["tile"], c["wave_batch"], c.get("schedule", "grid")), c["ms"],
+                              c["table"])
         table = {}
         best = None
-        for tile, wb in self.candidates:
-            opts = self._options(tile, wb)
-            step = make(opts)
+
+        def trial(tile, wb, schedule, name):
+            nonlocal best
+            step = make(self._options(tile, wb, schedule))
             ms = self._time(step, self.reps)
             step.release()
-            table[f"{tile}/{wb}"] = round(ms, 4)
+            table[name] = round(ms, 4)
             if best is None or ms < best[0]:
-                best = (ms, tile, wb)
+                best = (ms, tile, wb, schedule)
             torch.cuda.empty_cache()
-        ms, tile, wb = best
-        self.cache[key] = dict(tile=tile, wave_batch=wb, ms=ms, table=table)
+
+        for tile, wb in self.candidates:
+            trial(tile, wb, "grid", f"{tile}/{wb}")
+        _, tile, wb, _ = best
+        for schedule in self.schedules:
+            trial(tile, wb, schedule, f"{tile}/{wb}/{schedule}")
+        ms, tile, wb, schedule = best
+        self.cache[key] = dict(tile=tile, wave_batch=wb, schedule=schedule, ms=ms, table=table)
         if self.cache_path:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1)
-        return TuneResult(self._options(tile, wb), ms, table)
+        return TuneResult(self._options(tile, wb, schedule), ms, table)
 
 
 class _BatchStep:

@@ -230,6 +230,9 @@ bool make_plan(JobTable& t, int tile, int bin, int64_t cap, Plan& p) {
   p.pval2 = p.packed ? p.pkey2 : take(4 * cc);
   p.tfinal = take(4 * (size_t)p.pixels);
   p.last = take(4 * (size_t)p.pixels);
+  p.order = take(4 * (size_t)p.tiles);
+  p.qctr = take(512);   // eight claim counters on lines of their own
+  p.wcost = take(4 * (size_t)p.tiles * (size_t)((tile / 8) * (tile / 8)));
   p.g2d = take(4 * (size_t)kGradFields * nn);
   p.pose_part = take(8 * 12 * (size_t)p.pose_blocks);
   p.jobs = take(sizeof(JobTable));
@@ -628,6 +631,10 @@ int32_t ms_state_view_get(void* workspace, size_t ws_bytes, int64_t n, const ms_
   v->counters = at<uint64_t>(ws, p.counters);
   v->grad2d = at<float>(ws, p.g2d);
   v->pair_rank_bits = p.packed ? p.rank_bits : 0;
+  v->tile_order = at<uint32_t>(ws, p.order);
+  v->tile_cost = at<uint32_t>(ws, p.wcost);
+  v->tiles = p.tiles;
+  v->tile_waves = (p.tile / 8) * (p.tile / 8);
   return MS_OK;
 }
 

@@ -200,6 +200,256 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------- tile queue
+// Persistent compositing: the launch holds as many workgroups G as fit on
+// the device at once (G <= tiles), and each takes tiles from a queue until
+// it is empty. The queue is a permutation of the tiles sorted by expected
+// work, longest first (k_tile_order), so that the long tiles of a batch's
+// large maps start at once rather than after the short ones, and the launch
+// ends on short tiles. Workgroup g starts on queue position g without a
+// claim; only the positions from G on are handed out by atomic claims.
+//
+// With nq = 8 the positions are dealt to eight queues, one per XCD (the
+// hardware sends workgroup i to XCD i mod 8), in runs of kDeal consecutive
+// positions (consecutive positions are tiles of one bin, which read the
+// same list); a workgroup drains its own XCD's queue first and then takes
+// from the others in turn, so no single counter is hit by every workgroup.
+struct TileQueue {
+  const uint32_t* order;   // tile ids, longest expected work first
+  uint32_t* ctr;           // nq claim counters, kQueueStride words apart (zeroed by k_tile_order)
+  int n;                   // tiles
+  int nq;                  // queues: 1, or 8
+  int grid;                // workgroups of the launch
+};
+constexpr int kQueueStride = 16;   // words: one 64-byte line per counter
+constexpr int kMaxQueues = 8;
+constexpr int kDeal = 8;           // consecutive positions dealt to one queue
+
+// Number of the positions below `count` that queue q holds, and the
+// position of its slot s (slots in position order).
+__device__ inline int queue_count(int nq, int q, int count) {
+  const int run = kDeal * nq;
+  const int full = count / run, rem = count - full * run;
+  return full * kDeal + min(max(rem - q * kDeal, 0), kDeal);
+}
+__device__ inline int queue_size(const TileQueue& tq, int q) { return queue_count(tq.nq, q, tq.n); }
+__device__ inline int queue_position(const TileQueue& tq, int q, int s) {
+  return ((s / kDeal) * tq.nq + q) * kDeal + s % kDeal;
+}
+// Slots of queue q taken without a claim: its positions below G.
+__device__ inline int queue_static(const TileQueue& tq, int q) { return queue_count(tq.nq, q, tq.grid); }
+
+// Issues a claim on queue q, unless a plain read already shows it exhausted
+// (then returns 0xFFFFFFFF).
+__device__ inline uint32_t queue_claim(const TileQueue& tq, int q) {
+  uint32_t* c = tq.ctr + kQueueStride * q;
+  const uint32_t seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((int)seen + queue_static(tq, q) >= queue_size(tq, q)) return 0xFFFFFFFFu;
+  return atomicAdd(c, 1u);
+}
+
+// Position of the claim `s` on queue q, moving on to the next queue while
+// the current one is exhausted; n when every queue is. `tries` counts the
+// queues given up so far (the caller keeps q and tries across calls).
+__device__ inline int queue_resolve(const TileQueue& tq, uint32_t s, int& q, int& tries) {
+  for (;;) {
+    if (tries >= tq.nq) return tq.n;
+    if (s != 0xFFFFFFFFu) {
+      const int slot = (int)s + queue_static(tq, q);
+      if (slot < queue_size(tq, q)) return queue_position(tq, q, slot);
+    }
+    tries++;
+    q = q + 1 == tq.nq ? 0 : q + 1;
+    if (tries < tq.nq) s = queue_claim(tq, q);
+  }
+}
+
+// Runs body(b) for the tiles this workgroup takes from the queue. Thread 0
+// claims one tile ahead, and reads the next tile's id one tile ahead: the
+// claim for the tile after next and the id of the next are in flight while
+// the current tile is composited, so their latency overlaps the tile's own
+// first loads. Every thread of the workgroup runs each body and the barrier
+// after it.
+template <class F>
+__device__ inline void for_queued_tiles(const TileQueue& tq, F&& body) {
+  __shared__ int next[2];
+  const int g = (int)blockIdx.x;
+  int q = g % tq.nq, tries = 0;   // the home queue: this workgroup's XCD
+  uint32_t claim = 0xFFFFFFFFu;
+  if (threadIdx.x == 0) {
+    claim = queue_claim(tq, q);
+    next[0] = (int)tq.order[g];   // the static first position (g < G <= n)
+  }
+  __syncthreads();
+  for (int it = 0;; it ^= 1) {
+    const int b = next[it];
+    if (b < 0) break;   // uniform
+    int nb = -1;
+    if (threadIdx.x == 0) {
+      const int i = queue_resolve(tq, claim, q, tries);
+      if (i < tq.n) {
+        nb = (int)tq.order[i];
+        claim = queue_claim(tq, q);
+      }
+    }
+    body(b);
+    if (threadIdx.x == 0) next[it ^ 1] = nb;
+    __syncthreads();
+  }
+}
+
+// Expected-work class: 0 for none, else 1 + 4 floor(log2 c) plus the two
+// bits below the leading one (quarter-octave classes, at most 128).
+__device__ inline int cost_class(uint32_t c) {
+  if (c == 0u) return 0;
+  const int l = 31 - __builtin_clz(c);
+  const uint32_t f = l >= 2 ? (c >> (l - 2)) & 3u : (c << (2 - l)) & 3u;
+  return 1 + 4 * l + (int)f;
+}
+
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderPer = 4;       // bins per thread per pass
+constexpr int kCostClasses = 192;  // three per lane of the scanning wave (129 used)
+constexpr int kOrderLdsBins = 4096;   // bins whose backward costs are summed in LDS
+
+// Sorts the tiles by expected work, longest first, into `order`, and zeroes
+// the queue counters. The unit of the sort is the bin: its tiles read the
+// same list, so they stay together, row-major, in the queue. One workgroup:
+// a histogram of the bins' cost classes weighted by their tile counts, in
+// LDS, an exclusive scan of it from the top class down, and a scatter in
+// which each bin reserves its run of positions (the order of the bins
+// within a class is arbitrary). The expected work of a bin is its list
+// length for the forward (nw = 0), and for the backward the sum over its
+// tiles of the per-wave list depths the forward left in wcost (nw waves per
+// tile).
+__global__ void __launch_bounds__(kOrderThreads)
+    k_tile_order(const uint32_t* __restrict__ trange, const uint32_t* __restrict__ wcost, int nw,
+                 const JobDesc* __restrict__ jobs, int njobs, int bshift, int nbins, uint32_t* __restrict__ order,
+                 uint32_t* __restrict__ qctr) {
+  __shared__ uint32_t hist[kCostClasses];
+  __shared__ int jt[kMaxJobs][6];   // bin0, bins per row, tile0, tiles per row, tile rows
+  __shared__ uint32_t bcost[kOrderLdsBins];   // backward: per-bin sums of the tiles' list depths
+  const bool lds_sum = nw > 0 && nbins <= kOrderLdsBins;
+  for (int i = threadIdx.x; i < kCostClasses; i += kOrderThreads) hist[i] = 0u;
+  if (lds_sum)
+    for (int i = threadIdx.x; i < nbins; i += kOrderThreads) bcost[i] = 0u;
+  if (threadIdx.x < kMaxQueues) qctr[kQueueStride * threadIdx.x] = 0u;
+  if ((int)threadIdx.x < njobs) {
+    const JobDesc& J = jobs[threadIdx.x];
+    jt[threadIdx.x][0] = J.bin0;
+    jt[threadIdx.x][1] = J.bx;
+    jt[threadIdx.x][2] = J.tile0;
+    jt[threadIdx.x][3] = J.tx;
+    jt[threadIdx.x][4] = J.tx > 0 ? J.tiles / J.tx : 0;
+  }
+  __syncthreads();
+  // the bin's tiles: columns [x0, x1) and rows [y0, y1) of its job's tile
+  // grid, whose first tile is t0 and which has tx tiles per row
+  struct BinTiles {
+    int t0, tx, x0, x1, y0, y1;
+  };
+  auto tiles_of = [&](int g) -> BinTiles {
+    int j = 0;
+    for (int k = 1; k < njobs; k++)
+      if (g >= jt[k][0]) j = k;
+    const int lb = g - jt[j][0];
+    const int bxi = lb % jt[j][1], byi = lb / jt[j][1];
+    BinTiles r;
+    r.t0 = jt[j][2];
+    r.tx = jt[j][3];
+    r.x0 = bxi << bshift;
+    r.x1 = min((bxi + 1) << bshift, jt[j][3]);
+    r.y0 = byi << bshift;
+    r.y1 = min((byi + 1) << bshift, jt[j][4]);
+    return r;
+  };
+  if (lds_sum) {   // tile-parallel sums of the list depths into the bins (few bins)
+    int ntiles = 0;
+    for (int k = 0; k < njobs; k++) ntiles = max(ntiles, jt[k][2] + jt[k][3] * jt[k][4]);
+    for (int t = threadIdx.x; t < ntiles; t += kOrderThreads) {
+      int j = 0;
+      for (int k = 1; k < njobs; k++)
+        if (t >= jt[k][2]) j = k;
+      const int id = t - jt[j][2];
+      const int tx = id % jt[j][3], ty = id / jt[j][3];
+      uint32_t c = 0u;
+      for (int w = 0; w < nw; w++) c += wcost[(int64_t)t * nw + w];
+      if (c != 0u) atomicAdd(&bcost[jt[j][0] + (tx >> bshift) + (ty >> bshift) * jt[j][1]], c);
+    }
+    __syncthreads();
+  }
+  // class index counted from the top class down (longest first)
+  auto rank_of = [&](int g, const BinTiles& bt) -> int {
+    uint32_t c = 0u;
+    if (nw == 0) {
+      c = trange[2 * g + 1] - trange[2 * g];
+    } else if (lds_sum) {
+      c = bcost[g];
+    } else {
+      for (int y = bt.y0; y < bt.y1; y++)
+        for (int x = bt.x0; x < bt.x1; x++) {
+          const int64_t t = bt.t0 + (int64_t)y * bt.tx + x;
+          for (int w = 0; w < nw; w++) c += wcost[t * nw + w];
+        }
+    }
+    return 128 - cost_class(c);
+  };
+  for (int g0 = 0; g0 < nbins; g0 += kOrderThreads * kOrderPer) {
+#pragma unroll
+    for (int u = 0; u < kOrderPer; u++) {
+      const int g = g0 + u * kOrderThreads + (int)threadIdx.x;
+      if (g < nbins) {
+        const BinTiles bt = tiles_of(g);
+        atomicAdd(&hist[rank_of(g, bt)], (uint32_t)((bt.x1 - bt.x0) * (bt.y1 - bt.y0)));
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int l = (int)threadIdx.x;
+    const uint32_t a = hist[3 * l], b = hist[3 * l + 1], c = hist[3 * l + 2];
+    uint32_t incl = a + b + c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
+      if (l >= off) incl += o;
+    }
+    const uint32_t excl = incl - (a + b + c);
+    hist[3 * l] = excl;
+    hist[3 * l + 1] = excl + a;
+    hist[3 * l + 2] = excl + a + b;
+  }
+  __syncthreads();
+  for (int g0 = 0; g0 < nbins; g0 += kOrderThreads * kOrderPer) {
+#pragma unroll
+    for (int u = 0; u < kOrderPer; u++) {
+      const int g = g0 + u * kOrderThreads + (int)threadIdx.x;
+      if (g < nbins) {
+        const BinTiles bt = tiles_of(g);
+        const uint32_t m = (uint32_t)((bt.x1 - bt.x0) * (bt.y1 - bt.y0));
+        uint32_t pos = atomicAdd(&hist[rank_of(g, bt)], m);
+        for (int y = bt.y0; y < bt.y1; y++)
+          for (int x = bt.x0; x < bt.x1; x++) order[pos++] = (uint32_t)(bt.t0 + y * bt.tx + x);
+      }
+    }
+  }
+}
+
 constexpr int kFwdGroup = 4;   // entries evaluated together in the forward
 #ifndef MS_FWD_WAVES
 #define MS_FWD_WAVES 8
@@ -208,25 +458,39 @@ constexpr int kFwdGroup = 4;   // entries evaluated together in the forward
 #define MS_BWDM_WAVES 4
 #endif
 
+#define MS_FWD_PARAMS                                                                                          \
+  const uint4 *__restrict__ rec, const uint32_t *__restrict__ pval, uint32_t rank_mask,                        \
+      const uint32_t *__restrict__ trange, uint64_t *__restrict__ counters_rw, const JobDesc *__restrict__ jobs, \
+      int njobs, int bshift, float *__restrict__ tfinal, uint32_t *__restrict__ last, uint32_t *__restrict__ wcost
+#define MS_FWD_ARGS rec, pval, rank_mask, trange, counters_rw, jobs, njobs, bshift, tfinal, last, wcost
+
+// Forward of compositing tile b. Each wave also leaves in wcost[b NW + wave]
+// the deepest list position any of its pixels composited (0 for none): the
+// length of the list walk the backward will make for its sub-block.
 template <int TILE, int WB>
-__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
-    k_composite_fwd(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                    const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobDesc* __restrict__ jobs, int njobs, int bshift,
-                    float* __restrict__ tfinal, uint32_t* __restrict__ last) {
+__device__ __forceinline__ void fwd_tile(int b, MS_FWD_PARAMS) {
+  // the thread index, opaque to the compiler: in the persistent loop this
+  // keeps the values derived from it from being hoisted and held live
+  // across tiles
+  int tid = (int)threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   __shared__ Staged stage[NW][WB];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, b)];
   const int W = J.W, H = J.H;
-  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tile_id = b - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
   float* __restrict__ rgb = J.rgb;
   float* __restrict__ depth = J.depth;
   float* __restrict__ sil = J.sil;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
-  if (X0 >= W || Y0 >= H) return;   // whole sub-block outside the image (wave-uniform)
+  if (X0 >= W || Y0 >= H) {   // whole sub-block outside the image (wave-uniform)
+    if (lane == 0) wcost[b * NW + wave] = 0u;
+    return;
+  }
   const int xl = lane & 7, yl = lane >> 3;
   const int x = X0 + xl, y = Y0 + yl;
   const bool inside = x < W && y < H;
@@ -290,13 +554,15 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
       if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
     }
   }
+  const uint32_t deepest = wave_max_u32(lastpos);
+  if (lane == 0) wcost[b * NW + wave] = deepest;
   // work counters: one atomic per wave
   uint32_t wsum = ncomp;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += (uint32_t)__shfl_xor((int)wsum, off, 64);
   if (lane == 0) {
-    work_add(counters_rw, blockIdx.x * NW + wave, W_COMPOSITED, wsum);
-    work_add(counters_rw, blockIdx.x * NW + wave, W_STAGED, staged);
+    work_add(counters_rw, b * NW + wave, W_COMPOSITED, wsum);
+    work_add(counters_rw, b * NW + wave, W_STAGED, staged);
   }
   if (!inside) return;
   const int64_t P = (int64_t)W * H;
@@ -316,6 +582,19 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
   sil[pix] = 1.f - T;
   tfinal[J.pix0 + pix] = T;
   last[J.pix0 + pix] = lastpos;
+}
+
+template <int TILE, int WB>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES) k_composite_fwd(MS_FWD_PARAMS) {
+  fwd_tile<TILE, WB>((int)blockIdx.x, MS_FWD_ARGS);
+}
+
+// Persistent form: as many workgroups as fit on the device at once, each
+// taking tiles from the queue until it is empty.
+template <int TILE, int WB>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_FWD_WAVES)
+    k_composite_fwd_q(MS_FWD_PARAMS, const TileQueue tq) {
+  for_queued_tiles(tq, [&](int b) { fwd_tile<TILE, WB>(b, MS_FWD_ARGS); });
 }
 
 // Scalar-record variant of the forward. The 64-byte record of the Gaussian
@@ -454,21 +733,6 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   sil[pix] = 1.f - T;
   tfinal[J.pix0 + pix] = T;
   last[J.pix0 + pix] = lastpos;
-}
-
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
-    v = o > v ? o : v;
-  }
-  return v;
 }
 
 template <int TILE, int WB>
@@ -697,6 +961,19 @@ constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
 #define MS_BWD_CHUNK 48
 #endif
 constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per staging round
+#define MS_BWD_PARAMS                                                                                     \
+  const uint4 *__restrict__ rec, const uint32_t *__restrict__ pval, uint32_t rank_mask,                   \
+      const uint32_t *__restrict__ trange, uint64_t *__restrict__ counters_rw, const JobTable &tbl,       \
+      JobTable *__restrict__ tbl_dst, int bshift, const float *__restrict__ tfinal,                       \
+      const uint32_t *__restrict__ last, float *__restrict__ g2d
+#define MS_BWD_ARGS rec, pval, rank_mask, trange, counters_rw, tbl, tbl_dst, bshift, tfinal, last, g2d
+// kernels take the job table by value
+#define MS_BWD_KPARAMS                                                                                    \
+  const uint4 *__restrict__ rec, const uint32_t *__restrict__ pval, uint32_t rank_mask,                   \
+      const uint32_t *__restrict__ trange, uint64_t *__restrict__ counters_rw, const JobTable tbl,        \
+      JobTable *__restrict__ tbl_dst, int bshift, const float *__restrict__ tfinal,                       \
+      const uint32_t *__restrict__ last, float *__restrict__ g2d
+
 constexpr int kBwdStep = 4;                    // entries whose alphas are evaluated together
 #ifndef MS_ACC_ROWS
 #define MS_ACC_ROWS 256
@@ -704,29 +981,30 @@ constexpr int kBwdStep = 4;                    // entries whose alphas are evalu
 constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
 
 template <int TILE>
-__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
-    k_composite_bwd_m(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobTable tbl,
-                      JobTable* __restrict__ tbl_dst, int bshift, const float* __restrict__ tfinal,
-                      const uint32_t* __restrict__ last, float* __restrict__ g2d) {
+__device__ __forceinline__ void bwd_m_tile(int b, MS_BWD_PARAMS) {
+  // the thread index, opaque to the compiler: in the persistent loop this
+  // keeps the values derived from it from being hoisted and held live
+  // across tiles
+  int tid = (int)threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   // the job table arrives by value; the first workgroup leaves a copy in the
   // workspace for the projection adjoint
   const JobDesc* jobs = tbl.job;
   const int njobs = tbl.njobs;
-  if (blockIdx.x == 0) {
+  if (b == 0) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&tbl);
     uint32_t* d = reinterpret_cast<uint32_t*>(tbl_dst);
-    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
+    for (int i = tid; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
   }
   __shared__ __attribute__((aligned(16))) float lds[NW * kWaveLds];
   __shared__ Staged stage[NW][kBwdChunk];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, b)];
   const int W = J.W, H = J.H;
-  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tile_id = b - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
@@ -738,7 +1016,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   constexpr int kAcc = NW > 1 ? kAccRows : 0;
   __shared__ float acc[kAcc > 0 ? kAcc * kGradFields : 1];
   if (kAcc > 0) {
-    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
+    for (int i = tid; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
     __syncthreads();
   }
   if (X0 < W && Y0 < H) {   // wave-uniform: sub-blocks wholly outside the image do nothing
@@ -952,12 +1230,12 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     if (rows > 0) flush(rows);
     hi = lo;
   }
-  if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
+  if (lane == 0) work_add(counters_rw, b * NW + wave, W_REDUCED, reduced);
   }
   if (kAcc > 0) {
     __syncthreads();
     const uint32_t start = trange[2 * bin_id];
-    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) {
+    for (int i = tid; i < kAcc * kGradFields; i += 64 * NW) {
       const float v = acc[i];
       if (v != 0.f) {   // only rows of list entries some wave packed
         const int pos = i / kGradFields, fi = i - pos * kGradFields;
@@ -966,6 +1244,17 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       }
     }
   }
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES) k_composite_bwd_m(MS_BWD_KPARAMS) {
+  bwd_m_tile<TILE>((int)blockIdx.x, MS_BWD_ARGS);
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
+    k_composite_bwd_m_q(MS_BWD_KPARAMS, const TileQueue tq) {
+  for_queued_tiles(tq, [&](int b) { bwd_m_tile<TILE>(b, MS_BWD_ARGS); });
 }
 
 // Backward with the per-Gaussian reduction over the wave's 64 pixels on the
@@ -1011,27 +1300,28 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
 constexpr int kGrpF = 8;                       // Gaussians per product (two columns each)
 
 template <int TILE>
-__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
-    k_composite_bwd_f(const uint4* __restrict__ rec, const uint32_t* __restrict__ pval, uint32_t rank_mask,
-                      const uint32_t* __restrict__ trange, uint64_t* __restrict__ counters_rw, const JobTable tbl,
-                      JobTable* __restrict__ tbl_dst, int bshift, const float* __restrict__ tfinal,
-                      const uint32_t* __restrict__ last, float* __restrict__ g2d) {
+__device__ __forceinline__ void bwd_f_tile(int b, MS_BWD_PARAMS) {
+  // the thread index, opaque to the compiler: in the persistent loop this
+  // keeps the values derived from it from being hoisted and held live
+  // across tiles
+  int tid = (int)threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
   constexpr int SB = TILE / 8;
   constexpr int NW = SB * SB;
   const JobDesc* jobs = tbl.job;
   const int njobs = tbl.njobs;
-  if (blockIdx.x == 0) {   // leave the job table for the projection adjoint
+  if (b == 0) {   // leave the job table for the projection adjoint
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&tbl);
     uint32_t* d = reinterpret_cast<uint32_t*>(tbl_dst);
-    for (int i = threadIdx.x; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
+    for (int i = tid; i < (int)(sizeof(JobTable) / 4); i += 64 * NW) d[i] = src[i];
   }
   __shared__ __attribute__((aligned(16))) float lds[NW * kWaveLds];
   __shared__ Staged stage[NW][kBwdChunk];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const JobDesc& J = jobs[job_of_tile(jobs, njobs, (int)blockIdx.x)];
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const JobDesc& J = jobs[job_of_tile(jobs, njobs, b)];
   const int W = J.W, H = J.H;
-  const int tile_id = (int)blockIdx.x - J.tile0;
+  const int tile_id = b - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
@@ -1042,7 +1332,7 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
   constexpr int kAcc = NW > 1 ? kAccRows : 0;
   __shared__ float acc[kAcc > 0 ? kAcc * kGradFields : 1];
   if (kAcc > 0) {
-    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
+    for (int i = tid; i < kAcc * kGradFields; i += 64 * NW) acc[i] = 0.f;
     __syncthreads();
   }
   if (X0 < W && Y0 < H) {   // wave-uniform: sub-blocks wholly outside the image do nothing
@@ -1255,12 +1545,12 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
     if (rows > 0) flush(rows);
     hi = lo;
   }
-  if (lane == 0) work_add(counters_rw, blockIdx.x * NW + wave, W_REDUCED, reduced);
+  if (lane == 0) work_add(counters_rw, b * NW + wave, W_REDUCED, reduced);
   }
   if (kAcc > 0) {
     __syncthreads();
     const uint32_t start = trange[2 * bin_id];
-    for (int i = threadIdx.x; i < kAcc * kGradFields; i += 64 * NW) {
+    for (int i = tid; i < kAcc * kGradFields; i += 64 * NW) {
       const float v = acc[i];
       if (v != 0.f) {   // only rows of list entries some wave packed
         const int pos = i / kGradFields, fi = i - pos * kGradFields;
@@ -1269,6 +1559,17 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
       }
     }
   }
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES) k_composite_bwd_f(MS_BWD_KPARAMS) {
+  bwd_f_tile<TILE>((int)blockIdx.x, MS_BWD_ARGS);
+}
+
+template <int TILE>
+__global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8), MS_BWDM_WAVES)
+    k_composite_bwd_f_q(MS_BWD_KPARAMS, const TileQueue tq) {
+  for_queued_tiles(tq, [&](int b) { bwd_f_tile<TILE>(b, MS_BWD_ARGS); });
 }
 
 template <int TILE>
@@ -1307,7 +1608,71 @@ hipError_t fwd_one(const Plan& p, char* ws, hipStream_t st) {
   hipLaunchKernelGGL((k_composite_fwd<TILE, WB>), dim3(p.tiles), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
                      at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
                      at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
-                     at<uint32_t>(ws, p.last));
+                     at<uint32_t>(ws, p.last), at<uint32_t>(ws, p.wcost));
+  return hipGetLastError();
+}
+
+// Workgroups of `kernel` (`threads` each) resident on the current device at
+// once, at most `tiles`; 0 when the runtime cannot say.
+int queue_grid(const void* kernel, int threads, int tiles) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+  const int64_t g = (int64_t)cus * per_cu;
+  return (int)(g < tiles ? g : tiles);
+}
+
+// The queue of a persistent launch over the plan's tiles, sorted for the
+// forward (nw = 0) or the backward (nw waves per tile).
+hipError_t launch_order(const Plan& p, int nw, int nq, int grid, char* ws, hipStream_t st, TileQueue& tq) {
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, at<uint32_t>(ws, p.trange),
+                     at<uint32_t>(ws, p.wcost), nw, at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, p.bins,
+                     at<uint32_t>(ws, p.order), at<uint32_t>(ws, p.qctr));
+  tq.order = at<uint32_t>(ws, p.order);
+  tq.ctr = at<uint32_t>(ws, p.qctr);
+  tq.n = p.tiles;
+  tq.nq = nq;
+  tq.grid = grid;
+  return hipGetLastError();
+}
+
+template <int TILE, int WB>
+hipError_t fwd_queue(const Plan& p, int nq, char* ws, hipStream_t st) {
+  constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
+  const int grid = queue_grid(reinterpret_cast<const void*>(&k_composite_fwd_q<TILE, WB>), threads, p.tiles);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  TileQueue tq;
+  hipError_t e = launch_order(p, 0, nq, grid, ws, st, tq);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_composite_fwd_q<TILE, WB>), dim3(grid), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
+                     at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange), at<uint64_t>(ws, p.counters),
+                     at<JobTable>(ws, p.jobs)->job, p.njobs, p.bshift, at<float>(ws, p.tfinal),
+                     at<uint32_t>(ws, p.last), at<uint32_t>(ws, p.wcost), tq);
+  return hipGetLastError();
+}
+
+// The MFMA backward (fp32 or bf16x3 products) as a persistent launch.
+template <int TILE, bool kBf16x3>
+hipError_t bwd_queue(const Plan& p, int nq, const JobTable& t, char* ws, hipStream_t st) {
+  constexpr int threads = 64 * (TILE / 8) * (TILE / 8);
+  const void* k = kBf16x3 ? reinterpret_cast<const void*>(&k_composite_bwd_m_q<TILE>)
+                          : reinterpret_cast<const void*>(&k_composite_bwd_f_q<TILE>);
+  const int grid = queue_grid(k, threads, p.tiles);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  TileQueue tq;
+  hipError_t e = launch_order(p, (TILE / 8) * (TILE / 8), nq, grid, ws, st, tq);
+  if (e != hipSuccess) return e;
+  if (kBf16x3)
+    hipLaunchKernelGGL((k_composite_bwd_m_q<TILE>), dim3(grid), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
+                       at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange),
+                       at<uint64_t>(ws, p.counters), t, at<JobTable>(ws, p.jobs), p.bshift, at<float>(ws, p.tfinal),
+                       at<uint32_t>(ws, p.last), at<float>(ws, p.g2d), tq);
+  else
+    hipLaunchKernelGGL((k_composite_bwd_f_q<TILE>), dim3(grid), dim3(threads), 0, st, at<uint4>(ws, rec_slots(p)),
+                       at<uint32_t>(ws, p.pval), rank_mask(p), at<uint32_t>(ws, p.trange),
+                       at<uint64_t>(ws, p.counters), t, at<JobTable>(ws, p.jobs), p.bshift, at<float>(ws, p.tfinal),
+                       at<uint32_t>(ws, p.last), at<float>(ws, p.g2d), tq);
   return hipGetLastError();
 }
 
@@ -1357,12 +1722,29 @@ hipError_t launch_composite_fwd(const Plan& p, int wave_batch, uint32_t flags, c
       default: return hipErrorInvalidValue;
     }
   }
+  if (flags & MS_FLAG_TILE_QUEUE) {
+    const int nq = (flags & MS_FLAG_XCD_QUEUES) ? kMaxQueues : 1;
+    MS_DISPATCH(fwd_queue, p, nq, ws, st)
+  }
   MS_DISPATCH(fwd_one, p, ws, st)
 }
 
 hipError_t launch_composite_bwd(const Plan& p, int wave_batch, uint32_t flags, const JobTable& t, char* ws,
                                 hipStream_t st) {
   if (p.tiles == 0) return hipSuccess;
+  if ((flags & MS_FLAG_MFMA_BWD) && (flags & MS_FLAG_TILE_QUEUE)) {
+    const int nq = (flags & MS_FLAG_XCD_QUEUES) ? kMaxQueues : 1;
+    const bool x3 = (flags & MS_FLAG_BWD_BF16X3) != 0;
+    switch (p.tile * 2 + (x3 ? 1 : 0)) {
+      case 16: return bwd_queue<8, false>(p, nq, t, ws, st);
+      case 17: return bwd_queue<8, true>(p, nq, t, ws, st);
+      case 32: return bwd_queue<16, false>(p, nq, t, ws, st);
+      case 33: return bwd_queue<16, true>(p, nq, t, ws, st);
+      case 64: return bwd_queue<32, false>(p, nq, t, ws, st);
+      case 65: return bwd_queue<32, true>(p, nq, t, ws, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if ((flags & MS_FLAG_MFMA_BWD) && (flags & MS_FLAG_BWD_BF16X3)) {
     switch (p.tile) {
       case 8: return bwd_mfma<8>(p, t, ws, st);

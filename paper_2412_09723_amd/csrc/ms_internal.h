@@ -170,6 +170,8 @@ struct Plan {
   size_t counters, tickets, digit_hist, lookback, gcnt, trange, ctrl_end;
   size_t jobs;           // device JobTable
   size_t key, rec_i, g2d, pose_part, tfinal, last, pkey, pval, pkey2, pval2;
+  // persistent compositing: tile queue, its claim counters, per-wave list depths of the forward
+  size_t order, qctr, wcost;
   // per-bin path
   size_t gbin, ucnt, uvis;
   // global depth sort path

@@ -33,6 +33,9 @@ class RenderOptions:
                                          # matrix cores in binary32), "mfma_bf16x3" (the same product from
                                          # bf16 high/low parts), "lds" or "scalar" (wave reductions)
     grow: bool = True                    # with check: enlarge the pair capacity and redo on overflow
+    schedule: str = "grid"               # compositing launch: "grid" (one workgroup per tile), "queue"
+                                         # (persistent workgroups taking tiles longest-first from one
+                                         # queue) or "xcd_queue" (eight queues, one per XCD)
 
 
 def default_capacity(n: int, width: int, height: int, tile: int) -> int:
@@ -62,6 +65,12 @@ def opts_struct(opts: RenderOptions, flags: int = 0) -> MsOptions:
         flags |= _lib.MS_FLAG_MFMA_BWD
     if opts.bwd_records == "mfma_bf16x3":
         flags |= _lib.MS_FLAG_BWD_BF16X3
+    if opts.schedule not in ("grid", "queue", "xcd_queue"):
+        raise ValueError(f"schedule {opts.schedule!r} not in ('grid', 'queue', 'xcd_queue')")
+    if opts.schedule in ("queue", "xcd_queue"):
+        flags |= _lib.MS_FLAG_TILE_QUEUE
+    if opts.schedule == "xcd_queue":
+        flags |= _lib.MS_FLAG_XCD_QUEUES
     return MsOptions(int(opts.tile), int(opts.wave_batch), float(opts.near_z), int(flags), int(opts.bin_tile))
 
 
@@ -269,6 +278,9 @@ class Job:
             counters=view(v.counters, 8, torch.int64),
             grad2d=view(v.grad2d, 10 * n, torch.float32).view(n, 10),
             pair_rank_bits=int(v.pair_rank_bits),
+            tile_order=view(v.tile_order, int(v.tiles), torch.int32),
+            tile_cost=view(v.tile_cost, int(v.tiles) * int(v.tile_waves), torch.int32).view(int(v.tiles),
+                                                                                           int(v.tile_waves)),
         )
 
 

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.ms_abi_version() == 4
+    assert lib.ms_abi_version() == 5
     for code in range(6):
         assert lib.ms_status_string(code)
     assert lib.ms_status_string(99) == b"unknown status"

@@ -123,15 +123,16 @@ def test_batch_per_job_gradient_flags():
 
 def test_batch_config3_full_size():
     """Four agents' room maps of 200k, 600k, 1.2M and 2M Gaussians at
-    1200x680 in one batch, against each rendered alone and the oracle on the
-    smallest."""
+    1200x680 in one batch, against each rendered alone, and the smallest's
+    images and gradients against the oracle."""
     _log("four_agent_rooms batch: 200k/600k/1.2M/2M at 1200x680")
     scs = scenes.four_agent_rooms()
     devs = [to_dev(sc) for sc in scs]
     opts = raster.RenderOptions(check=True)
     batch = raster.BatchJob([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], opts)
     outs = batch.forward()
-    ups = [_dev(scenes.upstream_grads(sc.intr, scenes.rng_for(3, j, salt=2), 0.5, 0.0)) for j, sc in enumerate(scs)]
+    ups_np = [scenes.upstream_grads(sc.intr, scenes.rng_for(3, j, salt=2), 0.5, 0.0) for j, sc in enumerate(scs)]
+    ups = [_dev(u) for u in ups_np]
     gbs = batch.backward(ups)
     torch.cuda.synchronize()
     _log(f"  batch stats {batch.stats()}")
@@ -144,7 +145,9 @@ def test_batch_config3_full_size():
         torch.cuda.synchronize()
         check_reordered_grads(gbs[j], ga, KEYS + ("viewmat", "twist"))
         del alone, ga
+    # the 200k map's images and gradients from the batch against the oracle
     check_images(outs[0], oracle.forward(scs[0]))
+    check_grads(gbs[0], oracle.backward(scs[0], *ups_np[0]))
 
 
 def test_autotuner_picks_a_measured_candidate():
@@ -154,9 +157,10 @@ def test_autotuner_picks_a_measured_candidate():
     ups = [_dev(_upstream(sc, j)) for j, sc in enumerate(scs)]
     tuner = autotune.Autotuner(reps=1)
     res = tuner.tune_batch([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], ups)
-    assert len(res.table) == 9
+    assert len(res.table) == 9 + len(autotune.SCHEDULES) - 1
     assert abs(res.ms - min(res.table.values())) < 1e-3
     assert res.options.tile in autotune.TILES and res.options.wave_batch in autotune.WAVE_BATCHES
+    assert res.options.schedule in autotune.SCHEDULES
     assert res.options.bin_tile >= res.options.tile
     again = tuner.tune_batch([m for m, _ in devs], [vm for _, vm in devs], [sc.intr for sc in scs], ups)
     assert again.options == res.options         # cached
