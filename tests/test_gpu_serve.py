@@ -81,6 +81,27 @@ def test_served_results_equal_alone(agents):
                                                                    sc.colors, vm, sc.intr)))
 
 
+def test_served_equal_alone_at_full_size():
+    """Serving at full size: a 1200x680 agent with a 1.2M-Gaussian map
+    served together with two 640x480 agents (300k and 150k Gaussians); every
+    served result against the same request run alone."""
+    scs = [scenes.room_view(n=1_200_000, agent=5, intr=scenes.ROOM_INTR, stream=4),
+           scenes.room_view(n=300_000, agent=1, intr=scenes.VGA_INTR, stream=4),
+           scenes.room_view(n=150_000, agent=2, intr=scenes.VGA_INTR, stream=4)]
+    ags = serve.make_agents(scs, steps=32)
+    reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags), 1500.0, 0.04, seed=15))
+    _log(f"full-size serving: {len(reqs)} requests over agents of {[a.n for a in ags]} Gaussians")
+    opts = raster.RenderOptions()
+    done, failed, info = serve.serve(ags, reqs, opts, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert not failed and len(done) == len(reqs)
+    s = serve.summarize(done, info["wall_s"])
+    _log(f"  {s}")
+    mixed = [d for d in done if d.batch > 1]
+    assert mixed and any(reqs[d.rid].agent == 0 for d in mixed)   # the 1.2M agent shared rounds
+    _check_same_as_alone(ags, reqs, done, opts)
+
+
 def test_plain_baseline_equals_alone(agents):
     scs, ags = agents
     reqs = serve.requests_from_trace(scenes.poisson_trace(len(ags), 60.0, 0.2, seed=12))
