@@ -483,9 +483,9 @@ __device__ __forceinline__ void fwd_tile(int b, MS_FWD_PARAMS) {
   const int tile_id = b - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  float* __restrict__ rgb = J.rgb;
-  float* __restrict__ depth = J.depth;
-  float* __restrict__ sil = J.sil;
+  const auto rgb = global_ptr(J.rgb);
+  const auto depth = global_ptr(J.depth);
+  const auto sil = global_ptr(J.sil);
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) {   // whole sub-block outside the image (wave-uniform)
     if (lane == 0) wcost[b * NW + wave] = 0u;
@@ -660,9 +660,9 @@ __global__ void __launch_bounds__(64 * (TILE / 8) * (TILE / 8))
   const int tile_id = (int)blockIdx.x - J.tile0;
   const int tx = tile_id % J.tx, ty = tile_id / J.tx;
   const int bin_id = J.bin0 + (tx >> bshift) + (ty >> bshift) * J.bx;
-  float* __restrict__ rgb = J.rgb;
-  float* __restrict__ depth = J.depth;
-  float* __restrict__ sil = J.sil;
+  const auto rgb = global_ptr(J.rgb);
+  const auto depth = global_ptr(J.depth);
+  const auto sil = global_ptr(J.sil);
   const int X0 = tx * TILE + (wave % SB) * 8, Y0 = ty * TILE + (wave / SB) * 8;
   if (X0 >= W || Y0 >= H) return;
   const int x = X0 + (lane & 7), y = Y0 + (lane >> 3);

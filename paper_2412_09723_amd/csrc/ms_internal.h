@@ -98,24 +98,37 @@ struct JobTable {
 // sit in g_rgb, g_depth, g_sil.
 constexpr uint32_t kJobL1Upstream = 1u << 30;
 
+// Global-address-space view of a device pointer read from a job table in
+// memory. The compiler cannot tell where such a pointer points and would
+// access it with flat instructions, which also count against the LDS wait
+// counter, so every LDS wait would wait for them as well.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* global_ptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Gradient of scale * |d| with sign(0) = 0.
 __host__ __device__ inline float l1_sign(float d, float sc) { return d > 0.f ? sc : (d < 0.f ? -sc : 0.f); }
 
 // The upstream gradient of pixel `pix` of job J (P = W H).
 __device__ inline void load_upstream(const JobDesc& J, int64_t pix, int64_t P, float& G0, float& G1, float& G2,
                                      float& GD, float& GS) {
+  const auto g_rgb = global_ptr(J.g_rgb);
+  const auto g_depth = global_ptr(J.g_depth);
+  const auto g_sil = global_ptr(J.g_sil);
   if (J.flags & kJobL1Upstream) {
-    G0 = l1_sign(J.rgb[pix] - J.g_rgb[pix], J.l1s[0]);
-    G1 = l1_sign(J.rgb[P + pix] - J.g_rgb[P + pix], J.l1s[0]);
-    G2 = l1_sign(J.rgb[2 * P + pix] - J.g_rgb[2 * P + pix], J.l1s[0]);
-    GD = l1_sign(J.depth[pix] - J.g_depth[pix], J.l1s[1]);
-    GS = l1_sign(J.sil[pix] - J.g_sil[pix], J.l1s[2]);
+    const auto rgb = global_ptr(J.rgb);
+    G0 = l1_sign(rgb[pix] - g_rgb[pix], J.l1s[0]);
+    G1 = l1_sign(rgb[P + pix] - g_rgb[P + pix], J.l1s[0]);
+    G2 = l1_sign(rgb[2 * P + pix] - g_rgb[2 * P + pix], J.l1s[0]);
+    GD = l1_sign(global_ptr(J.depth)[pix] - g_depth[pix], J.l1s[1]);
+    GS = l1_sign(global_ptr(J.sil)[pix] - g_sil[pix], J.l1s[2]);
   } else {
-    G0 = J.g_rgb[pix];
-    G1 = J.g_rgb[P + pix];
-    G2 = J.g_rgb[2 * P + pix];
-    GD = J.g_depth[pix];
-    GS = J.g_sil[pix];
+    G0 = g_rgb[pix];
+    G1 = g_rgb[P + pix];
+    G2 = g_rgb[2 * P + pix];
+    GD = g_depth[pix];
+    GS = g_sil[pix];
   }
 }
 

@@ -43,7 +43,8 @@ struct Pose {
   double R[3][3], t[3];
 };
 
-__device__ inline void load_pose(const float* vm, Pose& P) {
+template <class PtrT>
+__device__ inline void load_pose(PtrT vm, Pose& P) {
 #pragma unroll
   for (int i = 0; i < 3; i++) {
 #pragma unroll
@@ -288,15 +289,17 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)vm[u], 0u))] =
           u * 256 + (int)threadIdx.x;
   __syncthreads();
-  const float* __restrict__ means = J.means;
-  const float* __restrict__ scales = J.scales;
-  const float* __restrict__ quats = J.quats;
-  const float* __restrict__ opac = J.opacity;
+  const auto means = global_ptr(J.means);
+  const auto scales = global_ptr(J.scales);
+  const auto quats = global_ptr(J.quats);
+  const auto opac = global_ptr(J.opacity);
   struct {
     int W, H;
     float fx, fy;
   } cam = {J.W, J.H, J.fx, J.fy};
-  const float* viewmat = J.viewmat;
+  const auto viewmat = global_ptr(J.viewmat);
+  const auto gm_out = global_ptr(J.gm), gs_out = global_ptr(J.gs), gq_out = global_ptr(J.gq),
+             go_out = global_ptr(J.go), gc_out = global_ptr(J.gc);
   const bool map_grads = !(J.flags & MS_FLAG_POSE_GRAD_ONLY);
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool accumulate = (J.flags & MS_FLAG_ACCUMULATE_MAP_GRADS) != 0;   // several views of one map
@@ -307,12 +310,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       const int64_t li = li0 + u * 256 + threadIdx.x;
       if (li < n && !own_vis[u]) {
         for (int k = 0; k < 3; k++) {
-          J.gm[k * n + li] = 0.f;
-          J.gs[k * n + li] = 0.f;
-          J.gc[k * n + li] = 0.f;
+          gm_out[k * n + li] = 0.f;
+          gs_out[k * n + li] = 0.f;
+          gc_out[k * n + li] = 0.f;
         }
-        for (int k = 0; k < 4; k++) J.gq[k * n + li] = 0.f;
-        J.go[li] = 0.f;
+        for (int k = 0; k < 4; k++) gq_out[k * n + li] = 0.f;
+        go_out[li] = 0.f;
       }
     }
   }
@@ -465,20 +468,20 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     }
     if (map_grads && accumulate) {
       for (int k = 0; k < 3; k++) {
-        unsafeAtomicAdd(J.gm + k * n + li, gm[k]);
-        unsafeAtomicAdd(J.gs + k * n + li, gs[k]);
-        unsafeAtomicAdd(J.gc + k * n + li, gc[k]);
+        __builtin_amdgcn_global_atomic_fadd_f32(gm_out + k * n + li, gm[k]);
+        __builtin_amdgcn_global_atomic_fadd_f32(gs_out + k * n + li, gs[k]);
+        __builtin_amdgcn_global_atomic_fadd_f32(gc_out + k * n + li, gc[k]);
       }
-      for (int k = 0; k < 4; k++) unsafeAtomicAdd(J.gq + k * n + li, gq[k]);
-      unsafeAtomicAdd(J.go + li, go);
+      for (int k = 0; k < 4; k++) __builtin_amdgcn_global_atomic_fadd_f32(gq_out + k * n + li, gq[k]);
+      __builtin_amdgcn_global_atomic_fadd_f32(go_out + li, go);
     } else if (map_grads) {
       for (int k = 0; k < 3; k++) {
-        J.gm[k * n + li] = gm[k];
-        J.gs[k * n + li] = gs[k];
-        J.gc[k * n + li] = gc[k];
+        gm_out[k * n + li] = gm[k];
+        gs_out[k * n + li] = gs[k];
+        gc_out[k * n + li] = gc[k];
       }
-      for (int k = 0; k < 4; k++) J.gq[k * n + li] = gq[k];
-      J.go[li] = go;
+      for (int k = 0; k < 4; k++) gq_out[k * n + li] = gq[k];
+      go_out[li] = go;
     }
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
@@ -517,9 +520,9 @@ __global__ void __launch_bounds__(kPoseThreads) k_pose_final(const JobDesc* __re
   __shared__ double tot[12];
   const JobDesc& J = jobs[blockIdx.x];
   if (J.flags & MS_FLAG_NO_POSE_GRAD) return;   // uniform over the block
-  const float* viewmat = J.viewmat;
-  float* gview = J.gview;
-  float* gtwist = J.gtwist;
+  const auto viewmat = global_ptr(J.viewmat);
+  const auto gview = global_ptr(J.gview);
+  const auto gtwist = global_ptr(J.gtwist);
   const int nblocks = (int)((J.n + kAdjSlots - 1) / kAdjSlots);   // adjoint blocks of this job
   part += (int64_t)(J.block0 / (kAdjSlots / 256)) * 12;
   // thread t folds partials t, t + 256, ...; then 16 sums of 16 threads and
