@@ -11,8 +11,8 @@ import pytest
 import torch
 
 import oracle
-from paper_2412_09723_amd import scenes
-from tests.gpu_util import check_grads, check_images, check_structure, run_job, to_dev
+from paper_2412_09723_amd import raster, scenes
+from tests.gpu_util import check_grads, check_images, check_reordered_grads, check_structure, run_job, to_dev
 from tests.helpers import make_scene
 
 pytestmark = pytest.mark.gpu
@@ -286,3 +286,34 @@ def test_long_bin_segment_with_depth_ties():
     g = job.backward(*_dev_grads(up))
     torch.cuda.synchronize()
     check_grads(g, oracle.backward(sc, *up))
+
+
+@pytest.mark.parametrize("bwd,schedule", [("mfma", "grid"), ("mfma", "queue"), ("mfma_bf16x3", "grid"),
+                                          ("lds", "grid"), ("scalar", "grid")])
+def test_stale_gradient_arrays_are_overwritten(bwd, schedule):
+    """Gradient arrays filled with stale values beforehand: every Gaussian's
+    gradient is written, the culled ones with exact zeros, the rest as in a
+    backward into fresh arrays, on every backward variant and schedule."""
+    _log(f"stale gradient arrays bwd={bwd} schedule={schedule}")
+    sc = scenes.small_frustum()
+    sc.means[2, :300] = -1.0                    # behind the camera: culled
+    sc.means[0, 300:400] *= 40.0                # far outside the guard band: culled
+    m, vm = to_dev(sc)
+    opts = raster.RenderOptions(check=True, bwd_records=bwd, fwd_records="scalar" if bwd == "scalar" else "lds",
+                                schedule=schedule)
+    job = raster.Job(m, vm, sc.intr, opts)
+    job.forward()
+    up = _dev_grads(_up(sc))
+    fresh = {k: v.clone() for k, v in job.backward(*up).items()}
+    stale = {k: torch.full_like(m[k], 7.0) for k in ("means", "scales", "quats", "opacity", "colors")}
+    stale["viewmat"] = torch.full((12,), 7.0, device="cuda")
+    stale["twist"] = torch.full((6,), 7.0, device="cuda")
+    got = job.backward(*up, out=stale)
+    torch.cuda.synchronize()
+    culled = job.state()["depth_key"].cpu().numpy().view(np.uint32)[:sc.n] == 0xFFFFFFFF
+    assert culled.sum() >= 350
+    for k in ("means", "scales", "quats", "opacity", "colors"):
+        a = got[k].cpu().numpy().reshape(-1, sc.n)
+        assert not a[:, culled].any(), k
+        assert np.isfinite(a).all() and (a != 7.0).any(), k
+    check_reordered_grads(got, fresh, ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist"))
