@@ -11,12 +11,12 @@
 //            k_gicp_bscan (bucket starts), k_gicp_fill -- a hashed uniform
 //            grid of the target means, cells of d_max (1 + 2^-10), bucket
 //            entries as float4 (x, y, z, target index);
-//   iterate: k_gicp_correspond (per source: the 27 neighbouring cells, the
+//   iterate: k_gicp_correspond (per source, on eight lanes: the 27 neighbouring cells, the
 //            nearest mean in the pinned binary32 distance, ties to the
 //            smaller index), k_gicp_normal (per correspondence in binary64:
 //            residual, (R S_k R^T + S_l + eps I)^-1, J = [I | -[T x]_x],
 //            J^T M J and J^T M r; per-block partial sums), k_gicp_solve (one
-//            workgroup: fixed-order fold of the partials, Cholesky solve of
+//            workgroup: fixed-order parallel fold of the partials, Cholesky solve of
 //            the 6x6 system, T <- exp(xi^) T, stored in binary32).
 // The correspondence decision is an integer taken in binary32 in this
 // order, without fused operations:
@@ -118,39 +118,61 @@ __device__ inline Pose32 load_pose32(const float* __restrict__ T) {
   return P;
 }
 
+// Eight lanes per source, each probing every eighth of the 27 neighbouring
+// cells; their nearest candidates meet by a butterfly. The order on
+// (distance, index) is total, so the nearest is the same whatever lane
+// finds it.
+constexpr int kProbeLanes = 8;
+
+__device__ inline bool closer(float dd, int32_t j, float bd, int32_t best) {
+  return j >= 0 && (best < 0 || dd < bd || (dd == bd && j < best));
+}
+
 __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __restrict__ src, int64_t n, const float* __restrict__ T,
                                                                double inv_cell, uint32_t mask, const uint32_t* __restrict__ bstart,
                                                                const float4* __restrict__ entries, float dmax2,
                                                                int32_t* __restrict__ corr) {
-  const int64_t k = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
-  if (k >= n) return;
-  const Pose32 P = load_pose32(T);
-  const float x0 = src[k], x1 = src[n + k], x2 = src[2 * n + k];
-  const float y0 = ((P.r[0] * x0 + P.r[1] * x1) + P.r[2] * x2) + P.r[3];
-  const float y1 = ((P.r[4] * x0 + P.r[5] * x1) + P.r[6] * x2) + P.r[7];
-  const float y2 = ((P.r[8] * x0 + P.r[9] * x1) + P.r[10] * x2) + P.r[11];
+  const int64_t g = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
+  const int64_t k = g / kProbeLanes;
+  const int sub = (int)(g % kProbeLanes);
+  const bool live = k < n;   // the lanes of one source are all live or all not (kGThreads % kProbeLanes == 0)
   int32_t best = -1;
   float bd = 0.f;
-  if (finite3(y0, y1, y2)) {
-    const int64_t cx = cell_of(y0, inv_cell), cy = cell_of(y1, inv_cell), cz = cell_of(y2, inv_cell);
-    for (int dz = -1; dz <= 1; dz++)
-      for (int dy = -1; dy <= 1; dy++)
-        for (int dx = -1; dx <= 1; dx++) {
-          const uint32_t b = cell_hash(cx + dx, cy + dy, cz + dz, mask);
-          const uint32_t e = bstart[b + 1];
-          for (uint32_t s = bstart[b]; s < e; s++) {
-            const float4 q = entries[s];
-            const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
-            const float dd = (d0 * d0 + d1 * d1) + d2 * d2;
-            const int32_t j = __float_as_int(q.w);
-            if (dd <= dmax2 && (best < 0 || dd < bd || (dd == bd && j < best))) {
-              best = j;
-              bd = dd;
-            }
+  if (live) {
+    const Pose32 P = load_pose32(T);
+    const float x0 = src[k], x1 = src[n + k], x2 = src[2 * n + k];
+    const float y0 = ((P.r[0] * x0 + P.r[1] * x1) + P.r[2] * x2) + P.r[3];
+    const float y1 = ((P.r[4] * x0 + P.r[5] * x1) + P.r[6] * x2) + P.r[7];
+    const float y2 = ((P.r[8] * x0 + P.r[9] * x1) + P.r[10] * x2) + P.r[11];
+    if (finite3(y0, y1, y2)) {
+      const int64_t cx = cell_of(y0, inv_cell), cy = cell_of(y1, inv_cell), cz = cell_of(y2, inv_cell);
+      for (int c = sub; c < 27; c += kProbeLanes) {
+        const int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
+        const uint32_t b = cell_hash(cx + dx, cy + dy, cz + dz, mask);
+        const uint32_t e = bstart[b + 1];
+        for (uint32_t s = bstart[b]; s < e; s++) {
+          const float4 q = entries[s];
+          const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
+          const float dd = (d0 * d0 + d1 * d1) + d2 * d2;
+          const int32_t j = __float_as_int(q.w);
+          if (dd <= dmax2 && closer(dd, j, bd, best)) {
+            best = j;
+            bd = dd;
           }
         }
+      }
+    }
   }
-  corr[k] = best;
+#pragma unroll
+  for (int off = 1; off < kProbeLanes; off <<= 1) {
+    const float od = __shfl_xor(bd, off, 64);
+    const int32_t oj = __shfl_xor(best, off, 64);
+    if (closer(od, oj, bd, best)) {
+      best = oj;
+      bd = od;
+    }
+  }
+  if (live && sub == 0) corr[k] = best;
 }
 
 // covariance R_q diag(s^2) R_q^T of Gaussian j in binary64 (upper triangle
@@ -259,11 +281,28 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_normal(const float* __restri
 // One workgroup: fold the partials in a fixed order, solve, update T.
 __global__ void __launch_bounds__(kGThreads) k_gicp_solve(const double* __restrict__ partial, int64_t nblocks, float* __restrict__ T,
                                                           double* __restrict__ out, double* __restrict__ hist) {
+  // fixed-order fold of the partials: thread t sums blocks t, t + 256, ...;
+  // each wave folds its lanes by a butterfly; the waves are added in order
+  __shared__ double wsum[kGThreads / 64][32];
   __shared__ double tot[32];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double acc[kSums];
+#pragma unroll
+  for (int i = 0; i < kSums; i++) acc[i] = 0.0;
+  for (int64_t b = t; b < nblocks; b += kGThreads)
+#pragma unroll
+    for (int i = 0; i < kSums; i++) acc[i] += partial[b * 32 + i];
+#pragma unroll
+  for (int i = 0; i < kSums; i++) {
+    double v = acc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[wave][i] = v;
+  }
+  __syncthreads();
   if (t < kSums) {
     double s = 0.0;
-    for (int64_t b = 0; b < nblocks; b++) s += partial[b * 32 + t];
+    for (int w = 0; w < kGThreads / 64; w++) s += wsum[w][t];
     tot[t] = s;
   }
   __syncthreads();
@@ -396,7 +435,8 @@ hipError_t gicp_correspond(const GicpPlan& p, const float* src, int64_t n, const
                            int32_t* corr, char* ws, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const float dmax2 = d_max * d_max;
-  hipLaunchKernelGGL(k_gicp_correspond, dim3((unsigned)((n + kGThreads - 1) / kGThreads)), dim3(kGThreads), 0, st, src, n, T,
+  static_assert(kGThreads % kProbeLanes == 0, "a source's lanes share one workgroup");
+  hipLaunchKernelGGL(k_gicp_correspond, dim3((unsigned)((n * kProbeLanes + kGThreads - 1) / kGThreads)), dim3(kGThreads), 0, st, src, n, T,
                      1.0 / p.cell, (uint32_t)(p.nbuckets - 1), at<uint32_t>(ws, p.bstart), at<float4>(ws, p.entries), dmax2,
                      corr);
   return hipGetLastError();
