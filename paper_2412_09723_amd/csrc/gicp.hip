@@ -146,20 +146,37 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __re
     const float y2 = ((P.r[8] * x0 + P.r[9] * x1) + P.r[10] * x2) + P.r[11];
     if (finite3(y0, y1, y2)) {
       const int64_t cx = cell_of(y0, inv_cell), cy = cell_of(y1, inv_cell), cz = cell_of(y2, inv_cell);
-      for (int c = sub; c < 27; c += kProbeLanes) {
-        const int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
-        const uint32_t b = cell_hash(cx + dx, cy + dy, cz + dz, mask);
-        const uint32_t e = bstart[b + 1];
-        for (uint32_t s = bstart[b]; s < e; s++) {
-          const float4 q = entries[s];
-          const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
-          const float dd = (d0 * d0 + d1 * d1) + d2 * d2;
-          const int32_t j = __float_as_int(q.w);
-          if (dd <= dmax2 && closer(dd, j, bd, best)) {
-            best = j;
-            bd = dd;
-          }
+      // the bucket ranges of this lane's cells, loaded together
+      constexpr int kCells = (27 + kProbeLanes - 1) / kProbeLanes;
+      uint32_t bs[kCells], be[kCells];
+#pragma unroll
+      for (int u = 0; u < kCells; u++) {
+        const int c = sub + u * kProbeLanes;
+        bs[u] = be[u] = 0u;
+        if (c < 27) {
+          const uint32_t b = cell_hash(cx + (c % 3 - 1), cy + ((c / 3) % 3 - 1), cz + (c / 9 - 1), mask);
+          bs[u] = bstart[b];
+          be[u] = bstart[b + 1];
         }
+      }
+      auto test = [&](const float4& q) {
+        const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
+        const float dd = (d0 * d0 + d1 * d1) + d2 * d2;
+        const int32_t j = __float_as_int(q.w);
+        if (dd <= dmax2 && closer(dd, j, bd, best)) {
+          best = j;
+          bd = dd;
+        }
+      };
+#pragma unroll
+      for (int u = 0; u < kCells; u++) {
+        uint32_t s = bs[u];
+        for (; s + 1 < be[u]; s += 2) {   // two entries in flight
+          const float4 qa = entries[s], qb = entries[s + 1];
+          test(qa);
+          test(qb);
+        }
+        if (s < be[u]) test(entries[s]);
       }
     }
   }

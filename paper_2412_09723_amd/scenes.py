@@ -294,10 +294,11 @@ def gicp_scene(n_src: int = 200_000, seed: int = 0, noise: float = 0.003, deg: f
     """Inputs of the alignment workload: the room map of `room_view`, and
     n_src observed points -- means of the map's visible surface Gaussians
     (in front of the camera, within max_dist) with N(0, noise) jitter,
-    expressed in the camera frame. Returns (scene, src_means [3, n_src]
-    float32 camera frame, T_true [12] camera-to-world float32, T0 [12]: T_true
-    moved by `metres` along a random direction and `deg` degrees about a
-    random axis, as an initial estimate)."""
+    expressed in the camera frame and listed in the raster order of the
+    pixels they project to, as a depth camera delivers them. Returns (scene,
+    src_means [3, n_src] float32 camera frame, T_true [12] camera-to-world
+    float32, T0 [12]: T_true moved by `metres` along a random direction and
+    `deg` degrees about a random axis, as an initial estimate)."""
     sc = room_view()
     rng = np.random.default_rng(7000 + seed)
     V = sc.viewmat.astype(np.float64).reshape(3, 4)
@@ -308,6 +309,10 @@ def gicp_scene(n_src: int = 200_000, seed: int = 0, noise: float = 0.003, deg: f
                         (np.abs(p[0] / p[2]) < 1.0) & (np.abs(p[1] / p[2]) < 0.6))
     pick = rng.choice(ok, size=min(n_src, ok.size), replace=False)
     src = p[:, pick] + rng.normal(0.0, noise, (3, pick.size))
+    it = sc.intr                                          # raster order: pixel row, then column
+    u = it.fx * src[0] / src[2] + it.cx
+    v = it.fy * src[1] / src[2] + it.cy
+    src = src[:, np.lexsort((u, np.floor(v)))]
     Tw = np.concatenate([R.T, (-R.T @ t)[:, None]], axis=1)   # camera to world
     ax = rng.standard_normal(3)
     ax /= np.linalg.norm(ax)
