@@ -767,11 +767,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_bwd_ms": round(fb_ms, 4),
     }
-    def alt_step(alt_opts, steps=5):
+    def alt_step(alt_opts, steps=5, map_grads=not args.pose_only):
         """The same tracking step with other options: ms per step and the
         compositing stages' average launch times."""
-        alt = Tracker(m, t(sc.viewmat), target, sc.intr, alt_opts, lr=1e-3, w_depth=0.5,
-                      map_grads=not args.pose_only)
+        alt = Tracker(m, t(sc.viewmat), target, sc.intr, alt_opts, lr=1e-3, w_depth=0.5, map_grads=map_grads)
         for _ in range(2):
             alt.step(args.iters)
         aprof = _lib.Profiler(stages=("composite", "composite_bwd"))
@@ -798,6 +797,12 @@ def main():
         # compositing launched per tile against the persistent tile-queue schedules
         out["schedules"] = {s: alt_step(dataclasses.replace(opts, schedule=s))
                             for s in ("grid", "queue", "xcd_queue")}
+        if not args.pose_only:
+            # the tracking step with the pose gradient only (the backward still
+            # forms every Gaussian's screen-space sums; the projection adjoint
+            # writes no map gradients)
+            out["pose_only"] = {"workload": "the same tracking step, backward to the pose only",
+                                **alt_step(opts, map_grads=False)}
     if not args.no_prune:
         out["prune"] = prune_bench(m)
         out["select"] = select_bench(m, t(sc.viewmat), sc.intr)
