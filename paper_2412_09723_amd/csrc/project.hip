@@ -247,6 +247,24 @@ __global__ void __launch_bounds__(256) k_project_fwd(const JobTable tbl, JobTabl
 
 #pragma clang fp contract(fast)
 
+// Reciprocal and reciprocal square root in binary64 for the adjoint: the
+// hardware estimates (relative error about 2^-22) refined by two Newton
+// steps, each of which squares the relative error, so the result is within a
+// few units in the last place. The adjoint's outputs are binary32, so it
+// needs neither correctly rounded quotients nor roots; each of these is a
+// handful of dependent instructions where a correctly rounded division is
+// about ten.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ inline double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  return __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+}
+
 __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__ jobs, int njobs,
                                                      const uint32_t* __restrict__ key,
                                                      const int32_t* __restrict__ rank_of,
@@ -304,21 +322,6 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool accumulate = (J.flags & MS_FLAG_ACCUMULATE_MAP_GRADS) != 0;   // several views of one map
   const bool overflow = counters[C_OVERFLOW] != 0;
-  if (map_grads && !accumulate) {
-#pragma unroll
-    for (int u = 0; u < kSub; u++) {
-      const int64_t li = li0 + u * 256 + threadIdx.x;
-      if (li < n && !own_vis[u]) {
-        for (int k = 0; k < 3; k++) {
-          gm_out[k * n + li] = 0.f;
-          gs_out[k * n + li] = 0.f;
-          gc_out[k * n + li] = 0.f;
-        }
-        for (int k = 0; k < 4; k++) gq_out[k * n + li] = 0.f;
-        go_out[li] = 0.f;
-      }
-    }
-  }
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
   for (int h = threadIdx.x; h < nvis; h += 256) {
     const int64_t li = li0 + s_list[h];   // index within the job
@@ -347,8 +350,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     double p[3];
     for (int a = 0; a < 3; a++) p[a] = P.R[a][0] * mu[0] + P.R[a][1] * mu[1] + P.R[a][2] * mu[2] + P.t[a];
     const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-    const double qnorm = sqrt(qn2);
-    const double iq = 1.0 / qnorm;   // reciprocals: the adjoint needs no correctly rounded quotients
+    const double iq = rsq64(qn2);   // qn2 > 0 for every visible Gaussian
     const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
     const double Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
                              {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) Wm[a][b] = P.R[a][0] * M[0][b] + P.R[a][1] * M[1][b] + P.R[a][2] * M[2][b];
     const double fx = cam.fx, fy = cam.fy;
-    const double Z = p[2], rz = 1.0 / Z;
+    const double Z = p[2], rz = rcp64(Z);   // Z > near plane > 0
     const double xn = p[0] * rz, yn = p[1] * rz;
     const double limx = kGuard * cam.W / fx, limy = kGuard * cam.H / fy;
     const int clx = xn < -limx ? -1 : (xn > limx ? 1 : 0);
@@ -374,9 +376,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     const double s0 = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + kDilation;
     const double s1 = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
     const double s2 = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + kDilation;
-    const double d = s0 * s2 - s1 * s1;
-    const double sqd = sqrt(d), sqs2 = sqrt(s2);
-    const double r_d = 1.0 / d, r_s2 = 1.0 / s2, r_sqd = 1.0 / sqd, r_sqs2 = 1.0 / sqs2;
+    const double d = s0 * s2 - s1 * s1;   // >= 0.09: both diagonals carry the dilation
+    const double r_sqd = rsq64(d), r_sqs2 = rsq64(s2);
+    const double sqs2 = s2 * r_sqs2, r_d = r_sqd * r_sqd, r_s2 = r_sqs2 * r_sqs2;
     const double l11 = sqs2 * r_sqd, l22 = r_sqs2;
     const double l12 = -s1 * (r_sqd * r_sqs2);
     const double a_ = kKappa * l11, b_ = kKappa * l12, c_ = kKappa * l22;
@@ -385,7 +387,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
     const double gu = -a_ * c2 * P1;
     const double gv = -(b_ * c2 * P1 + c_ * c2 * P2);
     const double gl11 = kKappa * c2 * P1x, gl12 = kKappa * c2 * P1y, gl22 = kKappa * c2 * P2y;
-    go = (float)(o > 0.0 ? E * (1.0 / o) : 0.0);   // opacity 0 composites nowhere (E = 0)
+    go = (float)(o > 0.0 ? E * rcp64(o) : 0.0);   // opacity 0 composites nowhere (E = 0)
     // Cholesky factors -> (S00, S01, S11)
     const double r_dsq = r_d * r_sqd * r_sqs2;   // 1 / (d sqrt(d s2))
     const double gS0 = gl11 * (-0.5 * l11 * s2 * r_d) + gl12 * (-0.5 * l12 * s2 * r_d);
@@ -482,6 +484,24 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       }
       for (int k = 0; k < 4; k++) gq_out[k * n + li] = gq[k];
       go_out[li] = go;
+    }
+  }
+  // The owners of invisible slots write zero gradients only now: the memory
+  // counter a wave waits on for a load also counts its earlier stores, so
+  // stores issued before the loads above would have delayed them.
+  if (map_grads && !accumulate) {
+#pragma unroll
+    for (int u = 0; u < kSub; u++) {
+      const int64_t li = li0 + u * 256 + threadIdx.x;
+      if (li < n && !own_vis[u]) {
+        for (int k = 0; k < 3; k++) {
+          gm_out[k * n + li] = 0.f;
+          gs_out[k * n + li] = 0.f;
+          gc_out[k * n + li] = 0.f;
+        }
+        for (int k = 0; k < 4; k++) gq_out[k * n + li] = 0.f;
+        go_out[li] = 0.f;
+      }
     }
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
