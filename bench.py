@@ -60,10 +60,31 @@ def kernel_names(args) -> dict:
             "pose": "k_pose_final", "loss": "k_l1_grad", "pose_step": "k_pose_adam"}
 
 
+# sources whose hash a counted-traffic entry of the streaming kernels must match
+STREAM_SOURCES = {"project": ("project.hip", "ms_internal.h"), "bin_count": ("bin.hip", "ms_internal.h"),
+                  "bin_emit": ("bin.hip", "ms_internal.h"), "bin_sort": ("bin.hip", "ms_internal.h"),
+                  "project_bwd": ("project.hip", "ms_internal.h")}
+
+
+def read_stream_traffic() -> dict:
+    """Counted HBM bytes per launch of the streaming kernels (rocprofv3
+    FETCH_SIZE / WRITE_SIZE, copy-calibrated) from the committed summary,
+    for the stages whose sources have not changed since."""
+    path = os.path.join(ROOT, "profiles", "streaming_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return {}
+    return {k: v for k, v in d.get("stages", {}).items()
+            if k in STREAM_SOURCES and v.get("source_hash") == kernel_source_hash(STREAM_SOURCES[k])}
+
+
 def kernel_table(stage_ms: dict, names: dict, N: int, Nv: int, K: int, P: int, pairs: int) -> dict:
     """Each kernel of the tracking iteration: live HIP-event time per launch
     (one profiled step) against its roofline. Streaming kernels carry their
-    algorithmic HBM bytes per launch, the compositing kernels their
+    algorithmic HBM bytes per launch and, where a counter summary of the
+    current source exists, the bytes the hardware counted (reads of scattered
+    visible Gaussians fetch whole lines), the compositing kernels their
     algorithmic flops."""
     bytes_of = {
         "project": (68 * N + 104 * Nv, "56 B of parameters read + 4 B depth key + 8 B pixel footprint written per "
@@ -77,6 +98,7 @@ def kernel_table(stage_ms: dict, names: dict, N: int, Nv: int, K: int, P: int, p
         "loss": (60 * P, "5 planes x (prediction, target read + gradient written) x 4 B per pixel"),
     }
     out = {}
+    counted = read_stream_traffic()
     pose_ms = stage_ms.get("pose", 0.0)
     for k, name in names.items():
         ms = stage_ms.get(k, 0.0)
@@ -89,6 +111,10 @@ def kernel_table(stage_ms: dict, names: dict, N: int, Nv: int, K: int, P: int, p
             nb, what = bytes_of[k]
             row.update(bytes=nb, bytes_are=what, GB_s=round(nb / (ms * 1e-3) / 1e9, 1),
                        hbm_frac=round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+            if k in counted:
+                cb = counted[k]["bytes_per_launch"]
+                row.update(counted_bytes=cb, counted_GB_s=round(cb / (ms * 1e-3) / 1e9, 1),
+                           counted_hbm_frac=round(cb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
         elif k in ("composite", "composite_bwd"):
             fl = FLOPS_PER_PAIR[k] * pairs
             row.update(flops=fl, TFLOP_s=round(fl / (ms * 1e-3) / 1e12, 2),

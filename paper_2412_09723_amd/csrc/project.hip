@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   // checked for visibility, and the visible Gaussians are packed in index
   // order onto the block's threads, so every wave runs the long binary64
   // path with nearly all lanes busy (a quarter of the slots are visible in a
-  // typical frame); the owners of invisible slots write zero gradients.
+  // typical frame); each slot's owner writes the zero gradients of an
+  // invisible Gaussian (and, through LDS, those computed for a visible one).
   const int64_t li0 = ((int64_t)blockIdx.x * kSub - J.block0) * 256;   // block's first index within the job
   bool own_vis[kSub];
   uint64_t vm[kSub];
@@ -322,6 +323,16 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool accumulate = (J.flags & MS_FLAG_ACCUMULATE_MAP_GRADS) != 0;   // several views of one map
   const bool overflow = counters[C_OVERFLOW] != 0;
+  // The pose reduction's LDS, before that reduction, carries the gradients
+  // of the visible Gaussians from the threads that computed them to the
+  // slots' owners, so that every store of a gradient plane covers whole
+  // lines (64 consecutive slots) instead of scattered parts of them. Blocks
+  // with more visible Gaussians than threads (several compute rounds) store
+  // from the computing threads instead.
+  __shared__ double pr[12][256];
+  float* xg = reinterpret_cast<float*>(&pr[0][0]);   // [14][256]: gm 3, gs 3, gc 3, gq 4, go
+  static_assert(14 * 256 <= 2 * 12 * 256, "gradient exchange fits the pose reduction's LDS");
+  const bool exchange = map_grads && !accumulate && nvis <= 256;   // uniform
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
   for (int h = threadIdx.x; h < nvis; h += 256) {
     const int64_t li = li0 + s_list[h];   // index within the job
@@ -476,6 +487,14 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       }
       for (int k = 0; k < 4; k++) __builtin_amdgcn_global_atomic_fadd_f32(gq_out + k * n + li, gq[k]);
       __builtin_amdgcn_global_atomic_fadd_f32(go_out + li, go);
+    } else if (exchange) {
+      for (int k = 0; k < 3; k++) {
+        xg[k * 256 + h] = gm[k];
+        xg[(3 + k) * 256 + h] = gs[k];
+        xg[(6 + k) * 256 + h] = gc[k];
+      }
+      for (int k = 0; k < 4; k++) xg[(9 + k) * 256 + h] = gq[k];
+      xg[13 * 256 + h] = go;
     } else if (map_grads) {
       for (int k = 0; k < 3; k++) {
         gm_out[k * n + li] = gm[k];
@@ -486,10 +505,30 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       go_out[li] = go;
     }
   }
+  if (exchange) {   // every slot's owner stores its gradients (zero for an invisible Gaussian)
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSub; u++) {
+      const int64_t li = li0 + u * 256 + threadIdx.x;
+      if (li < n) {
+        const int h = vbase[u] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vm[u] >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)vm[u], 0u));
+        const bool v = own_vis[u];
+        for (int k = 0; k < 3; k++) {
+          gm_out[k * n + li] = v ? xg[k * 256 + h] : 0.f;
+          gs_out[k * n + li] = v ? xg[(3 + k) * 256 + h] : 0.f;
+          gc_out[k * n + li] = v ? xg[(6 + k) * 256 + h] : 0.f;
+        }
+        for (int k = 0; k < 4; k++) gq_out[k * n + li] = v ? xg[(9 + k) * 256 + h] : 0.f;
+        go_out[li] = v ? xg[13 * 256 + h] : 0.f;
+      }
+    }
+    __syncthreads();   // the pose reduction below reuses the LDS
+  }
   // The owners of invisible slots write zero gradients only now: the memory
   // counter a wave waits on for a load also counts its earlier stores, so
   // stores issued before the loads above would have delayed them.
-  if (map_grads && !accumulate) {
+  if (map_grads && !accumulate && !exchange) {
 #pragma unroll
     for (int u = 0; u < kSub; u++) {
       const int64_t li = li0 + u * 256 + threadIdx.x;
@@ -507,7 +546,6 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   if (!pose_grads) return;   // uniform over the block (one job per block)
   // block reduction of the 12 pose partials of the threads: through LDS, in a
   // fixed order (16 partial sums of 16 threads each, then their sum)
-  __shared__ double pr[12][256];
   __shared__ double ps[12][16];
   for (int a = 0; a < 3; a++) {
     for (int b = 0; b < 3; b++) pr[3 * a + b][threadIdx.x] = GR[a][b];
