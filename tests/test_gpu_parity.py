@@ -317,3 +317,35 @@ def test_stale_gradient_arrays_are_overwritten(bwd, schedule):
         assert not a[:, culled].any(), k
         assert np.isfinite(a).all() and (a != 7.0).any(), k
     check_reordered_grads(got, fresh, ("means", "scales", "quats", "opacity", "colors", "viewmat", "twist"))
+
+
+@pytest.mark.parametrize("bwd", ["mfma", "mfma_bf16x3"])
+def test_stale_gradient_arrays_sparse_visibility(bwd):
+    """Four of every five Gaussians culled (behind the camera), so that no
+    projection-adjoint block of 1024 slots holds more visible Gaussians than
+    it has threads: the adjoint then hands the visible gradients to the
+    slots' owners through LDS, and each owner writes its slot (zero when
+    culled) into stale arrays. Every gradient against the oracle, the culled
+    ones exactly zero."""
+    _log(f"stale gradient arrays, sparse visibility, bwd={bwd}")
+    sc = scenes.small_frustum()
+    idx = np.arange(sc.n)
+    sc.means[2, idx % 5 != 0] = -1.0
+    m, vm = to_dev(sc)
+    job = raster.Job(m, vm, sc.intr, raster.RenderOptions(check=True, bwd_records=bwd))
+    job.forward()
+    up = _up(sc)
+    stale = {k: torch.full_like(m[k], 7.0) for k in ("means", "scales", "quats", "opacity", "colors")}
+    stale["viewmat"] = torch.full((12,), 7.0, device="cuda")
+    stale["twist"] = torch.full((6,), 7.0, device="cuda")
+    got = job.backward(*_dev_grads(up), out=stale)
+    torch.cuda.synchronize()
+    culled = job.state()["depth_key"].cpu().numpy().view(np.uint32)[:sc.n] == 0xFFFFFFFF
+    assert culled.sum() >= 4 * sc.n // 5
+    per_block = np.add.reduceat((~culled).astype(np.int64), np.arange(0, sc.n, 1024))
+    assert per_block.max() <= 256, per_block
+    for k in ("means", "scales", "quats", "opacity", "colors"):
+        a = got[k].cpu().numpy().reshape(-1, sc.n)
+        assert not a[:, culled].any(), k
+        assert np.isfinite(a).all(), k
+    check_grads(got, oracle.backward(sc, *up))
