@@ -957,8 +957,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kGrp = 8;                        // Gaussians per product
 constexpr int kRow = 68;                       // padded row of 64 pixel values (bank spread)
 constexpr int kWaveLds = 16 * kRow;            // floats per wave: the A matrix
+// One staging round covers a full wave of list entries (every lane tests
+// one record). With the LDS accumulator at 176 rows a 16-px tile's
+// workgroup needs 40832 bytes of LDS, so four still fit on a CU.
 #ifndef MS_BWD_CHUNK
-#define MS_BWD_CHUNK 48
+#define MS_BWD_CHUNK 64
 #endif
 constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per staging round
 #define MS_BWD_PARAMS                                                                                     \
@@ -976,9 +979,10 @@ constexpr int kBwdChunk = MS_BWD_CHUNK;        // list entries packed per stagin
 
 constexpr int kBwdStep = 4;                    // entries whose alphas are evaluated together
 #ifndef MS_ACC_ROWS
-#define MS_ACC_ROWS 256
+#define MS_ACC_ROWS 176
 #endif
 constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
+static_assert(kBwdChunk % 4 == 0 && kBwdChunk <= 64, "a staging round pads to whole evaluation groups in one wave");
 
 template <int TILE>
 __device__ __forceinline__ void bwd_m_tile(int b, MS_BWD_PARAMS) {
