@@ -982,7 +982,7 @@ constexpr int kBwdStep = 4;                    // entries whose alphas are evalu
 #define MS_ACC_ROWS 176
 #endif
 constexpr int kAccRows = MS_ACC_ROWS;          // list positions aggregated in LDS per workgroup
-static_assert(kBwdChunk % 4 == 0 && kBwdChunk <= 64, "a staging round pads to whole evaluation groups in one wave");
+static_assert(kBwdChunk % kBwdStep == 0 && kBwdChunk <= 64, "a staging round pads to whole evaluation groups in one wave");
 
 template <int TILE>
 __device__ __forceinline__ void bwd_m_tile(int b, MS_BWD_PARAMS) {
