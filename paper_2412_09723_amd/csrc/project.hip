@@ -323,16 +323,17 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
   const bool pose_grads = !(J.flags & MS_FLAG_NO_POSE_GRAD);
   const bool accumulate = (J.flags & MS_FLAG_ACCUMULATE_MAP_GRADS) != 0;   // several views of one map
   const bool overflow = counters[C_OVERFLOW] != 0;
-  // The pose reduction's LDS, before that reduction, carries the gradients
-  // of the visible Gaussians from the threads that computed them to the
-  // slots' owners, so that every store of a gradient plane covers whole
-  // lines (64 consecutive slots) instead of scattered parts of them. Blocks
-  // with more visible Gaussians than threads (several compute rounds) store
-  // from the computing threads instead.
-  __shared__ double pr[12][256];
-  float* xg = reinterpret_cast<float*>(&pr[0][0]);   // [14][256]: gm 3, gs 3, gc 3, gq 4, go
-  static_assert(14 * 256 <= 2 * 12 * 256, "gradient exchange fits the pose reduction's LDS");
-  const bool exchange = map_grads && !accumulate && nvis <= 256;   // uniform
+  // LDS shared by two phases: first it carries the gradients of the visible
+  // Gaussians from the threads that computed them to the slots' owners, so
+  // that every store of a gradient plane covers whole lines (64 consecutive
+  // slots) instead of scattered parts of them; then it holds the pose
+  // reduction. 56 KB per block: the adjoint's registers allow two blocks
+  // per CU, whose LDS this leaves room for.
+  __shared__ __attribute__((aligned(16))) float adj_lds[14 * kAdjSlots];
+  float* xg = adj_lds;                                           // [14][kAdjSlots]: gm 3, gs 3, gc 3, gq 4, go
+  double (*pr)[256] = reinterpret_cast<double (*)[256]>(adj_lds);   // [12][256]
+  static_assert(12 * 256 * sizeof(double) <= 14 * kAdjSlots * sizeof(float), "pose reduction fits the exchange LDS");
+  const bool exchange = map_grads && !accumulate;   // uniform; otherwise atomics, or no map gradients
   double GR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gt[3] = {0, 0, 0};
   for (int h = threadIdx.x; h < nvis; h += 256) {
     const int64_t li = li0 + s_list[h];   // index within the job
@@ -489,23 +490,19 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
       __builtin_amdgcn_global_atomic_fadd_f32(go_out + li, go);
     } else if (exchange) {
       for (int k = 0; k < 3; k++) {
-        xg[k * 256 + h] = gm[k];
-        xg[(3 + k) * 256 + h] = gs[k];
-        xg[(6 + k) * 256 + h] = gc[k];
+        xg[k * kAdjSlots + h] = gm[k];
+        xg[(3 + k) * kAdjSlots + h] = gs[k];
+        xg[(6 + k) * kAdjSlots + h] = gc[k];
       }
-      for (int k = 0; k < 4; k++) xg[(9 + k) * 256 + h] = gq[k];
-      xg[13 * 256 + h] = go;
-    } else if (map_grads) {
-      for (int k = 0; k < 3; k++) {
-        gm_out[k * n + li] = gm[k];
-        gs_out[k * n + li] = gs[k];
-        gc_out[k * n + li] = gc[k];
-      }
-      for (int k = 0; k < 4; k++) gq_out[k * n + li] = gq[k];
-      go_out[li] = go;
+      for (int k = 0; k < 4; k++) xg[(9 + k) * kAdjSlots + h] = gq[k];
+      xg[13 * kAdjSlots + h] = go;
     }
   }
-  if (exchange) {   // every slot's owner stores its gradients (zero for an invisible Gaussian)
+  // Every slot's owner stores its gradients (zero for an invisible
+  // Gaussian). The stores come after all of the block's loads: one counter
+  // covers a wave's loads and stores, so a load issued after stores would
+  // wait for them.
+  if (exchange) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kSub; u++) {
@@ -515,33 +512,15 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDesc* __restrict__
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)vm[u], 0u));
         const bool v = own_vis[u];
         for (int k = 0; k < 3; k++) {
-          gm_out[k * n + li] = v ? xg[k * 256 + h] : 0.f;
-          gs_out[k * n + li] = v ? xg[(3 + k) * 256 + h] : 0.f;
-          gc_out[k * n + li] = v ? xg[(6 + k) * 256 + h] : 0.f;
+          gm_out[k * n + li] = v ? xg[k * kAdjSlots + h] : 0.f;
+          gs_out[k * n + li] = v ? xg[(3 + k) * kAdjSlots + h] : 0.f;
+          gc_out[k * n + li] = v ? xg[(6 + k) * kAdjSlots + h] : 0.f;
         }
-        for (int k = 0; k < 4; k++) gq_out[k * n + li] = v ? xg[(9 + k) * 256 + h] : 0.f;
-        go_out[li] = v ? xg[13 * 256 + h] : 0.f;
+        for (int k = 0; k < 4; k++) gq_out[k * n + li] = v ? xg[(9 + k) * kAdjSlots + h] : 0.f;
+        go_out[li] = v ? xg[13 * kAdjSlots + h] : 0.f;
       }
     }
     __syncthreads();   // the pose reduction below reuses the LDS
-  }
-  // The owners of invisible slots write zero gradients only now: the memory
-  // counter a wave waits on for a load also counts its earlier stores, so
-  // stores issued before the loads above would have delayed them.
-  if (map_grads && !accumulate && !exchange) {
-#pragma unroll
-    for (int u = 0; u < kSub; u++) {
-      const int64_t li = li0 + u * 256 + threadIdx.x;
-      if (li < n && !own_vis[u]) {
-        for (int k = 0; k < 3; k++) {
-          gm_out[k * n + li] = 0.f;
-          gs_out[k * n + li] = 0.f;
-          gc_out[k * n + li] = 0.f;
-        }
-        for (int k = 0; k < 4; k++) gq_out[k * n + li] = 0.f;
-        go_out[li] = 0.f;
-      }
-    }
   }
   if (!pose_grads) return;   // uniform over the block (one job per block)
   // block reduction of the 12 pose partials of the threads: through LDS, in a

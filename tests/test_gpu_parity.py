@@ -321,12 +321,11 @@ def test_stale_gradient_arrays_are_overwritten(bwd, schedule):
 
 @pytest.mark.parametrize("bwd", ["mfma", "mfma_bf16x3"])
 def test_stale_gradient_arrays_sparse_visibility(bwd):
-    """Four of every five Gaussians culled (behind the camera), so that no
-    projection-adjoint block of 1024 slots holds more visible Gaussians than
-    it has threads: the adjoint then hands the visible gradients to the
-    slots' owners through LDS, and each owner writes its slot (zero when
-    culled) into stale arrays. Every gradient against the oracle, the culled
-    ones exactly zero."""
+    """Four of every five Gaussians culled (behind the camera): the
+    projection adjoint packs a block's few visible Gaussians onto its first
+    threads and hands their gradients to the slots' owners through LDS, and
+    each owner writes its slot (zero when culled) into stale arrays. Every
+    gradient against the oracle, the culled ones exactly zero."""
     _log(f"stale gradient arrays, sparse visibility, bwd={bwd}")
     sc = scenes.small_frustum()
     idx = np.arange(sc.n)
