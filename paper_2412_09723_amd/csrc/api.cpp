@@ -932,7 +932,8 @@ int32_t ms_gicp_correspond(const ms_gicp_config* cfg, const ms_map* src, const f
   s = check_gicp_ws(p, workspace, ws_bytes);
   if (s != MS_OK) return s;
   StageTimer tm(MS_STAGE_GICP, (hipStream_t)stream);
-  hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, corr, (char*)workspace, (hipStream_t)stream);
+  hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, corr, nullptr, (char*)workspace,
+                                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "correspondences");
   return MS_OK;
 }
@@ -970,9 +971,14 @@ int32_t ms_gicp_align(const ms_gicp_config* cfg, const ms_map* src, const ms_map
   char* ws = (char*)workspace;
   int32_t* c = corr ? corr : at<int32_t>(ws, p.corr);
   StageTimer tm(MS_STAGE_GICP, st);
+  // the targets' covariances and means, gathered once for all iterations
+  if (iters > 0) {
+    const hipError_t e = gicp_records(p, *tgt, ws, st);
+    if (e != hipSuccess) return hip_fail(e, "target records");
+  }
   for (int it = 0; it < iters; it++) {
-    hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, c, ws, st);
-    if (e == hipSuccess) e = gicp_normal(p, *src, *tgt, T, c, cfg->eps, ws, st);
+    hipError_t e = gicp_correspond(p, src->means, src->n, T, cfg->d_max, c, at<int32_t>(ws, p.cslot), ws, st);
+    if (e == hipSuccess) e = gicp_normal_records(p, *src, T, cfg->eps, ws, st);
     if (e == hipSuccess)
       e = gicp_solve(p, src->n, T, at<double>(ws, p.out), hist ? hist + 29 * (int64_t)it : nullptr, ws, st, true);
     if (e != hipSuccess) return hip_fail(e, "alignment iteration");

@@ -43,6 +43,10 @@ __device__ inline bool finite3(float a, float b, float c) {
   return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
 }
 
+__global__ void k_gicp_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_gicp_zero(uint32_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -95,7 +99,8 @@ __global__ void __launch_bounds__(kBucketBlock) k_gicp_bscan(const uint32_t* __r
 
 __global__ void __launch_bounds__(kGThreads) k_gicp_fill(const float* __restrict__ mu, int64_t n, const int32_t* __restrict__ idx,
                                                          int64_t m, double inv_cell, uint32_t mask, const uint32_t* __restrict__ bstart,
-                                                         uint32_t* __restrict__ fillpos, float4* __restrict__ entries) {
+                                                         uint32_t* __restrict__ fillpos, float4* __restrict__ entries,
+                                                         int2* __restrict__ eslot) {
   const int64_t k = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
   if (k >= m) return;
   const int64_t j = target_index(idx, k);
@@ -105,6 +110,7 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_fill(const float* __restrict
   const uint32_t b = cell_hash(cell_of(x, inv_cell), cell_of(y, inv_cell), cell_of(z, inv_cell), mask);
   const uint32_t slot = bstart[b] + atomicAdd(&fillpos[b], 1u);
   entries[slot] = make_float4(x, y, z, __int_as_float((int32_t)j));
+  eslot[k] = make_int2((int32_t)slot, (int32_t)j);   // the entry of listed target k (-1 where none)
 }
 
 struct Pose32 {
@@ -131,12 +137,12 @@ __device__ inline bool closer(float dd, int32_t j, float bd, int32_t best) {
 __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __restrict__ src, int64_t n, const float* __restrict__ T,
                                                                double inv_cell, uint32_t mask, const uint32_t* __restrict__ bstart,
                                                                const float4* __restrict__ entries, float dmax2,
-                                                               int32_t* __restrict__ corr) {
+                                                               int32_t* __restrict__ corr, int32_t* __restrict__ cslot) {
   const int64_t g = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
   const int64_t k = g / kProbeLanes;
   const int sub = (int)(g % kProbeLanes);
   const bool live = k < n;   // the lanes of one source are all live or all not (kGThreads % kProbeLanes == 0)
-  int32_t best = -1;
+  int32_t best = -1, bslot = -1;   // target index and grid entry of the nearest mean
   float bd = 0.f;
   if (live) {
     const Pose32 P = load_pose32(T);
@@ -159,12 +165,13 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __re
           be[u] = bstart[b + 1];
         }
       }
-      auto test = [&](const float4& q) {
+      auto test = [&](const float4& q, uint32_t s) {
         const float d0 = y0 - q.x, d1 = y1 - q.y, d2 = y2 - q.z;
         const float dd = (d0 * d0 + d1 * d1) + d2 * d2;
         const int32_t j = __float_as_int(q.w);
         if (dd <= dmax2 && closer(dd, j, bd, best)) {
           best = j;
+          bslot = (int32_t)s;
           bd = dd;
         }
       };
@@ -173,10 +180,10 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __re
         uint32_t s = bs[u];
         for (; s + 1 < be[u]; s += 2) {   // two entries in flight
           const float4 qa = entries[s], qb = entries[s + 1];
-          test(qa);
-          test(qb);
+          test(qa, s);
+          test(qb, s + 1);
         }
-        if (s < be[u]) test(entries[s]);
+        if (s < be[u]) test(entries[s], s);
       }
     }
   }
@@ -184,12 +191,17 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_correspond(const float* __re
   for (int off = 1; off < kProbeLanes; off <<= 1) {
     const float od = __shfl_xor(bd, off, 64);
     const int32_t oj = __shfl_xor(best, off, 64);
+    const int32_t os = __shfl_xor(bslot, off, 64);
     if (closer(od, oj, bd, best)) {
       best = oj;
+      bslot = os;
       bd = od;
     }
   }
-  if (live && sub == 0) corr[k] = best;
+  if (live && sub == 0) {
+    corr[k] = best;
+    if (cslot) cslot[k] = bslot;
+  }
 }
 
 // covariance R_q diag(s^2) R_q^T of Gaussian j in binary64 (upper triangle
@@ -214,15 +226,61 @@ __device__ inline void gauss_cov(const float* __restrict__ sc, const float* __re
 
 constexpr int kSums = 29;   // H upper triangle (21), g (6), cost, count
 
+// A target as the normal equations read it, one record per grid entry (64
+// bytes, half a line): its binary64 covariance, its mean and its map index
+// (-1 when the index lies outside the map given to the alignment, which
+// then takes no part, as a correspondence outside the target map does).
+struct TargetRec {
+  double cov[6];
+  float mu[3];
+  int32_t idx;
+};
+static_assert(sizeof(TargetRec) == 64, "one target record per half line");
+
+// The records of the grid's entries from the target map tgt: the same
+// covariance (gauss_cov) and mean the normal equations would read at the map
+// index, computed once per alignment instead of once per correspondence and
+// iteration. Thread k takes the k-th listed target (map order, or the order
+// of the index list), so that its reads of the map's planes are coalesced;
+// eslot[k] holds its entry and map index, or -1.
+__global__ void __launch_bounds__(kGThreads) k_gicp_records(const int2* __restrict__ eslot, int64_t count,
+                                                            const float* __restrict__ tgt, const float* __restrict__ tsc,
+                                                            const float* __restrict__ tqt, int64_t nt,
+                                                            TargetRec* __restrict__ rec) {
+  const int64_t k = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
+  if (k >= count) return;
+  const int2 e = eslot[k];
+  if (e.x < 0) return;
+  const int64_t s = e.x;
+  const int32_t l = e.y;
+  TargetRec r;
+  if (l >= 0 && l < nt) {
+    gauss_cov(tsc, tqt, nt, l, r.cov);
+    r.mu[0] = tgt[l];
+    r.mu[1] = tgt[nt + l];
+    r.mu[2] = tgt[2 * nt + l];
+    r.idx = l;
+  } else {
+    for (int i = 0; i < 6; i++) r.cov[i] = 0.0;
+    r.mu[0] = r.mu[1] = r.mu[2] = 0.f;
+    r.idx = -1;
+  }
+  rec[s] = r;
+}
+
 __device__ inline double wave_sum_d(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
+// kRec: the target of source k is the grid entry cslot[k] (its record);
+// otherwise the map index corr[k], read from the target map.
+template <bool kRec>
 __global__ void __launch_bounds__(kGThreads) k_gicp_normal(const float* __restrict__ src, const float* __restrict__ ssc,
                                                            const float* __restrict__ sqt, int64_t n, const float* __restrict__ tgt,
                                                            const float* __restrict__ tsc, const float* __restrict__ tqt, int64_t nt,
-                                                           const float* __restrict__ T, const int32_t* __restrict__ corr, double eps,
+                                                           const float* __restrict__ T, const int32_t* __restrict__ corr,
+                                                           const TargetRec* __restrict__ rec, double eps,
                                                            double* __restrict__ partial) {
   __shared__ double red[kGThreads / 64][kSums];
   const int64_t k = (int64_t)blockIdx.x * kGThreads + threadIdx.x;
@@ -230,16 +288,32 @@ __global__ void __launch_bounds__(kGThreads) k_gicp_normal(const float* __restri
 #pragma unroll
   for (int i = 0; i < kSums; i++) acc[i] = 0.0;
   const int32_t l = k < n ? corr[k] : -1;
-  if (l >= 0 && l < nt) {   // a correspondence outside the target map takes no part
+  double ct[6], tm[3];
+  bool valid;
+  if (kRec) {
+    valid = l >= 0;
+    if (valid) {
+      const TargetRec& q = rec[l];
+      valid = q.idx >= 0;
+      for (int i = 0; i < 6; i++) ct[i] = q.cov[i];
+      for (int i = 0; i < 3; i++) tm[i] = q.mu[i];
+    }
+  } else {
+    valid = l >= 0 && l < nt;   // a correspondence outside the target map takes no part
+    if (valid) {
+      gauss_cov(tsc, tqt, nt, l, ct);
+      for (int i = 0; i < 3; i++) tm[i] = tgt[i * nt + l];
+    }
+  }
+  if (valid) {
     double V[12];
 #pragma unroll
     for (int i = 0; i < 12; i++) V[i] = (double)T[i];
     const double x0 = src[k], x1 = src[n + k], x2 = src[2 * n + k];
     const double p[3] = {((V[0] * x0 + V[1] * x1) + V[2] * x2) + V[3], ((V[4] * x0 + V[5] * x1) + V[6] * x2) + V[7],
                          ((V[8] * x0 + V[9] * x1) + V[10] * x2) + V[11]};
-    const double r[3] = {p[0] - (double)tgt[l], p[1] - (double)tgt[nt + l], p[2] - (double)tgt[2 * nt + l]};
-    double ct[6], cs[6];
-    gauss_cov(tsc, tqt, nt, l, ct);
+    const double r[3] = {p[0] - tm[0], p[1] - tm[1], p[2] - tm[2]};
+    double cs[6];
     gauss_cov(ssc, sqt, n, k, cs);
     // C = R S_k R^T + S_l + eps I
     const double S[3][3] = {{cs[0], cs[1], cs[2]}, {cs[1], cs[3], cs[4]}, {cs[2], cs[4], cs[5]}};
@@ -419,6 +493,9 @@ GicpPlan gicp_plan(int64_t max_src, int64_t max_tgt, float d_max) {
   p.total = take(8);
   p.entries = take((size_t)(max_tgt > 0 ? max_tgt : 1) * 16);
   p.corr = take((size_t)(max_src > 0 ? max_src : 1) * 4);
+  p.cslot = take((size_t)(max_src > 0 ? max_src : 1) * 4);
+  p.rec = take((size_t)(max_tgt > 0 ? max_tgt : 1) * sizeof(TargetRec));
+  p.eslot = take((size_t)(max_tgt > 0 ? max_tgt : 1) * 8);
   p.nblocks = (max_src + kGThreads - 1) / kGThreads;
   p.partial = take((size_t)(p.nblocks > 0 ? p.nblocks : 1) * 32 * 8);
   p.out = take(32 * 8);
@@ -434,6 +511,8 @@ hipError_t gicp_build(const GicpPlan& p, const float* mu, int64_t n, const int32
   const double inv = 1.0 / p.cell;
   hipLaunchKernelGGL(k_gicp_zero, dim3(1024), dim3(256), 0, st, bcount, p.nbuckets);
   hipLaunchKernelGGL(k_gicp_zero, dim3(1024), dim3(256), 0, st, fillpos, p.nbuckets);
+  // every listed target's entry starts as none (-1 in both words)
+  hipLaunchKernelGGL(k_gicp_fill_u32, dim3(1024), dim3(256), 0, st, at<uint32_t>(ws, p.eslot), 2 * p.max_tgt, 0xFFFFFFFFu);
   const unsigned tb = (unsigned)((m + kGThreads - 1) / kGThreads);
   if (m > 0) hipLaunchKernelGGL(k_gicp_count, dim3(tb), dim3(kGThreads), 0, st, mu, n, idx, m, inv, mask, bcount);
   const int64_t nb = p.nbuckets / kBucketBlock;
@@ -444,18 +523,18 @@ hipError_t gicp_build(const GicpPlan& p, const float* mu, int64_t n, const int32
                      at<uint32_t>(ws, p.bstart), p.nbuckets, at<int64_t>(ws, p.total));
   if (m > 0)
     hipLaunchKernelGGL(k_gicp_fill, dim3(tb), dim3(kGThreads), 0, st, mu, n, idx, m, inv, mask, at<uint32_t>(ws, p.bstart),
-                       fillpos, at<float4>(ws, p.entries));
+                       fillpos, at<float4>(ws, p.entries), at<int2>(ws, p.eslot));
   return hipGetLastError();
 }
 
 hipError_t gicp_correspond(const GicpPlan& p, const float* src, int64_t n, const float* T, float d_max,
-                           int32_t* corr, char* ws, hipStream_t st) {
+                           int32_t* corr, int32_t* cslot, char* ws, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const float dmax2 = d_max * d_max;
   static_assert(kGThreads % kProbeLanes == 0, "a source's lanes share one workgroup");
   hipLaunchKernelGGL(k_gicp_correspond, dim3((unsigned)((n * kProbeLanes + kGThreads - 1) / kGThreads)), dim3(kGThreads), 0, st, src, n, T,
                      1.0 / p.cell, (uint32_t)(p.nbuckets - 1), at<uint32_t>(ws, p.bstart), at<float4>(ws, p.entries), dmax2,
-                     corr);
+                     corr, cslot);
   return hipGetLastError();
 }
 
@@ -463,8 +542,26 @@ hipError_t gicp_normal(const GicpPlan& p, const ms_map& src, const ms_map& tgt, 
                        float eps, char* ws, hipStream_t st) {
   const int64_t nb = (src.n + kGThreads - 1) / kGThreads;
   if (nb > 0)
-    hipLaunchKernelGGL(k_gicp_normal, dim3((unsigned)nb), dim3(kGThreads), 0, st, src.means, src.scales, src.quats, src.n,
-                       tgt.means, tgt.scales, tgt.quats, tgt.n, T, corr, (double)eps, at<double>(ws, p.partial));
+    hipLaunchKernelGGL(k_gicp_normal<false>, dim3((unsigned)nb), dim3(kGThreads), 0, st, src.means, src.scales, src.quats,
+                       src.n, tgt.means, tgt.scales, tgt.quats, tgt.n, T, corr, (const TargetRec*)nullptr, (double)eps,
+                       at<double>(ws, p.partial));
+  return hipGetLastError();
+}
+
+hipError_t gicp_records(const GicpPlan& p, const ms_map& tgt, char* ws, hipStream_t st) {
+  if (p.max_tgt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gicp_records, dim3((unsigned)((p.max_tgt + kGThreads - 1) / kGThreads)), dim3(kGThreads), 0, st,
+                     at<int2>(ws, p.eslot), p.max_tgt, tgt.means, tgt.scales, tgt.quats, tgt.n, at<TargetRec>(ws, p.rec));
+  return hipGetLastError();
+}
+
+hipError_t gicp_normal_records(const GicpPlan& p, const ms_map& src, const float* T, float eps, char* ws,
+                               hipStream_t st) {
+  const int64_t nb = (src.n + kGThreads - 1) / kGThreads;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_gicp_normal<true>, dim3((unsigned)nb), dim3(kGThreads), 0, st, src.means, src.scales, src.quats,
+                       src.n, (const float*)nullptr, (const float*)nullptr, (const float*)nullptr, (int64_t)0, T,
+                       at<int32_t>(ws, p.cslot), at<TargetRec>(ws, p.rec), (double)eps, at<double>(ws, p.partial));
   return hipGetLastError();
 }
 

@@ -284,15 +284,22 @@ hipError_t launch_block_offsets(uint32_t* bcount, int64_t nblocks, int64_t* tota
 struct GicpPlan {
   int64_t nbuckets, max_src, max_tgt, nblocks;
   double cell;
-  size_t bcount, fillpos, bstart, bsum, total, entries, corr, partial, out, bytes;
+  size_t bcount, fillpos, bstart, bsum, total, entries, corr, cslot, rec, eslot, partial, out, bytes;
 };
 GicpPlan gicp_plan(int64_t max_src, int64_t max_tgt, float d_max);
 hipError_t gicp_build(const GicpPlan& p, const float* mu, int64_t n, const int32_t* idx, int64_t m, char* ws,
                       hipStream_t st);
+// cslot: device int32 [n] receiving each source's grid entry (or -1), or null
 hipError_t gicp_correspond(const GicpPlan& p, const float* src, int64_t n, const float* T, float d_max,
-                           int32_t* corr, char* ws, hipStream_t st);
+                           int32_t* corr, int32_t* cslot, char* ws, hipStream_t st);
 hipError_t gicp_normal(const GicpPlan& p, const ms_map& src, const ms_map& tgt, const float* T, const int32_t* corr,
                        float eps, char* ws, hipStream_t st);
+// The grid entries' target records from `tgt` (once per alignment), and the
+// normal equations over the entries the last correspondence search left in
+// the workspace (bit for bit those of gicp_normal with its map indices).
+hipError_t gicp_records(const GicpPlan& p, const ms_map& tgt, char* ws, hipStream_t st);
+hipError_t gicp_normal_records(const GicpPlan& p, const ms_map& src, const float* T, float eps, char* ws,
+                               hipStream_t st);
 hipError_t gicp_solve(const GicpPlan& p, int64_t n_src, float* T, double* out, double* hist, char* ws, hipStream_t st,
                       bool update);
 
