@@ -83,6 +83,36 @@ def test_room_alignment_matches_the_oracle():
     assert np.abs(Tg - Tt).max() < np.abs(T0 - Tt).max() and h[-1, 27] < h[0, 27]
 
 
+@pytest.mark.parametrize("targets", ["map", "candidates"])
+def test_alignment_sums_equal_the_direct_normal_equations(targets):
+    """ms_gicp_align reads each target from a per-entry record computed once
+    per call; its sums equal, bit for bit, ms_gicp_normal_equations over the
+    same correspondences, which reads the target map itself. Gaussian
+    sources, the whole map or a candidate list as targets, the first and a
+    later iteration."""
+    print(f"gicp record path against the direct path, {targets}", flush=True)
+    sc, src, Tt, T0, tgt = _room(20000, seed=3)
+    rng = np.random.default_rng(4)
+    ssc = np.exp(rng.uniform(np.log(0.002), np.log(0.02), (3, 20000))).astype(np.float32)
+    sq = rng.standard_normal((4, 20000)).astype(np.float32)
+    s = {"means": dev(src), "scales": dev(ssc), "quats": dev(sq)}
+    g = GeneralizedICP(20000, sc.n)
+    if targets == "map":
+        g.build(tgt)
+    else:
+        cand = SEL.select(sc.means, sc.viewmat.reshape(-1)[:12].astype(np.float32), sc.intr, max_dist=3.0)
+        assert 10000 < cand.size < sc.n
+        g.build(tgt, dev(cand))
+    T = dev(T0)
+    for step in range(2):
+        Tk = T.clone()
+        corr, hist = g.align(s, tgt, T, iters=1, history=True)
+        direct = g.normal_equations(s, tgt, Tk, corr)
+        torch.cuda.synchronize()
+        assert (corr >= 0).sum().item() > 5000, step
+        assert torch.equal(hist[0], direct), (step, (hist[0] - direct).abs().max().item())
+
+
 def test_known_transform_and_selected_targets():
     print("gicp lattice recovery", flush=True)
     rng = np.random.default_rng(2)
