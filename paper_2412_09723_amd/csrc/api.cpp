@@ -101,18 +101,21 @@ using StageTimer = StageScope;
 }  // namespace
 
 // Records the start event of a stage on `st` when the attached profiler
-// selects it; returns the event slot, or -1.
+// selects it; returns the event slot, or -1 (also when the record fails:
+// the stage then goes untimed).
 int prof_begin(int stage, hipStream_t st) {
   ms_profiler* p = g_prof;
   if (!p || !(p->mask & (1u << stage)) || p->used >= p->cap) return -1;
-  const int slot = p->used++;
+  const int slot = p->used;
+  if (hipEventRecord(p->ev[2 * slot], st) != hipSuccess) return -1;
   p->stage[slot] = stage;
-  hipEventRecord(p->ev[2 * slot], st);
+  p->used++;
   return slot;
 }
 
+// A slot whose end event could not be recorded is dropped from the totals.
 void prof_end(int slot, hipStream_t st) {
-  if (slot >= 0 && g_prof) hipEventRecord(g_prof->ev[2 * slot + 1], st);
+  if (slot >= 0 && g_prof && hipEventRecord(g_prof->ev[2 * slot + 1], st) != hipSuccess) g_prof->stage[slot] = -1;
 }
 
 bool layout_jobs(int njobs, JobTable& t, int tile, int bin, int64_t& n_virtual, int& tiles, int& bins,
@@ -1022,7 +1025,7 @@ int32_t ms_profiler_destroy(ms_profiler* p) {
   if (!p) return MS_OK;
   if (g_prof == p) g_prof = nullptr;
   for (auto& e : p->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);   // nothing to do about a failure while tearing down
   delete p;
   return MS_OK;
 }
@@ -1039,6 +1042,7 @@ int32_t ms_profiler_read(ms_profiler* p, double total_ms[MS_STAGE_COUNT], int64_
     launches[s] = 0;
   }
   for (int i = 0; i < p->used; i++) {
+    if (p->stage[i] < 0) continue;   // its end event was never recorded
     hipError_t e = hipEventSynchronize(p->ev[2 * i + 1]);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
