@@ -75,21 +75,26 @@ __global__ void __launch_bounds__(256) k_setup(JobTable t, JobTable* __restrict_
 
 // Adam on the twist xi = (rho, phi), then V <- exp(-step^) V in binary64.
 // state: m[6], v[6], t.
+// One wave: lane k < 6 takes twist component k, then lane 0 applies the step.
 __global__ void k_pose_adam(float* __restrict__ viewmat, const float* __restrict__ g, float* __restrict__ state,
                             float lr, float b1, float b2, float eps) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const float t = state[12] + 1.f;
-  state[12] = t;
-  double xi[6];
-  for (int k = 0; k < 6; k++) {
+  if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+  const int k = (int)threadIdx.x;
+  const float t = state[12] + 1.f;   // read by every lane before lane 0 stores it below
+  double xk = 0.0;
+  if (k < 6) {
     const float m = b1 * state[k] + (1.f - b1) * g[k];
     const float v = b2 * state[6 + k] + (1.f - b2) * g[k] * g[k];
     state[k] = m;
     state[6 + k] = v;
     const double mh = m / (1.0 - pow((double)b1, (double)t));
     const double vh = v / (1.0 - pow((double)b2, (double)t));
-    xi[k] = -(double)lr * mh / (sqrt(vh) + (double)eps);
+    xk = -(double)lr * mh / (sqrt(vh) + (double)eps);
   }
+  double xi[6];
+  for (int j = 0; j < 6; j++) xi[j] = __shfl(xk, j, 64);
+  if (k != 0) return;
+  state[12] = t;
   // exp of the se(3) element (rho = xi[0..2], phi = xi[3..5]), Rodrigues form
   const double px = xi[3], py = xi[4], pz = xi[5];
   const double th2 = px * px + py * py + pz * pz, th = sqrt(th2);
